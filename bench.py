@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Benchmark of the event-chained (SET) job scheduler on one MI355X.
+
+Workload (one "step" = one pass of the whole job path over one batch):
+10,000 jobs, each H2D of a 1024x1024 float32 N(0,1) image (pinned pool of 61
+images, job j uses entry j mod 61) -> separable 5x5 Gaussian (sigma 1,
+replicated borders) -> Sobel magnitude -> threshold 1.0 -> uint32 count +
+float32 magnitude sum -> D2H, on 8 worker streams x 16 buffer slots.
+
+The same jobs are also run through the batch-synchronised fixed-stream graph
+baseline (one graph of 8 job chains, host sync per batch) and the
+single-stream synchronous baseline, on the same GPU, and every result is
+checked against the CPU oracle after the timed regions.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "jobs/s and mean kernel gap (µs) vs batch-sync hipGraph; p50/p99 job latency"
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_jobs(ctx, tid, n_jobs, tin, pool, ib, tout, ob, stride):
+    arr = ctx.job_array(n_jobs)
+    j = np.arange(n_jobs, dtype=np.uint64)
+    arr["host_in"] = tin.data_ptr() + (j % np.uint64(pool)) * np.uint64(ib)
+    arr["in_bytes"] = ib
+    arr["host_out"] = tout.data_ptr() + j * np.uint64(stride)
+    arr["out_bytes"] = ob
+    arr["user_tag"] = j
+    return arr
+
+
+def run_mode(mode, args, jobs_per_step, steps, warmup, tin, tout, pool, torch, callback="event_chain"):
+    from paper_2606_05495_amd.runtime import Context
+    workers = args.workers
+    ctx = Context(mode=mode, workers=workers, slots=args.slots if mode == "set" else 1,
+                  batch_size=args.batch if mode == "batch" else 0, callback=callback, inflight=args.inflight,
+                  spin_us=args.spin_us)
+    tid = ctx.define("gauss_sobel", width=1024, height=1024)
+    ib, ob = ctx.in_bytes(tid), ctx.out_bytes(tid)
+    stride = 128
+    arr = make_jobs(ctx, tid, jobs_per_step, tin, pool, ib, tout, ob, stride)
+    for _ in range(warmup):
+        ctx.submit_many(tid, arr)
+        ctx.drain()
+    ctx.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.submit_many(tid, arr)
+        ctx.drain()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = ctx.stats()
+    times = ctx.job_times()
+    return ctx, tid, dt, st, times
+
+
+def verify(tout, n_jobs, pool_imgs, refs):
+    """Every job's result vs the oracle of its pool image (outside any timed region)."""
+    import oracle
+    from paper_2606_05495_amd import _abi as A
+    out = tout.numpy().reshape(-1, 128)[:n_jobs]
+    hdr = out[:, :64].copy().view(A.OUT_HEADER_DTYPE).ravel()
+    ok = bool(np.all(hdr["magic"] == A.SET_OUT_MAGIC) and np.all(hdr["canary_ok"] == 1))
+    cnt = out[:, 64:68].copy().view(np.uint32).ravel()
+    s = out[:, 68:72].copy().view(np.float32).ravel()
+    bad = 0
+    for j in range(n_jobs):
+        r = refs[j % len(refs)]
+        if abs(int(cnt[j]) - r["count"]) > r["band"] or abs(float(s[j]) - r["sum"]) > 1e-5 * abs(r["sum"]):
+            bad += 1
+    return ok and bad == 0, bad
+
+
+def cpu_baseline(pool_imgs, passes):
+    """The oracle as it stands, timed on this host's cores: a thread pool of
+    C calls (ctypes releases the interpreter lock) over `passes` x the pool."""
+    import oracle
+    oracle.lib()
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    work = [pool_imgs[k % len(pool_imgs)] for k in range(passes * len(pool_imgs))]
+    t0 = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=ncores) as ex:
+        list(ex.map(lambda im: oracle.gauss_sobel(im, want_images=False), work))
+    dt = time.perf_counter() - t0
+    return {"value": round(len(work) / dt, 2), "unit": "jobs/s", "cores": ncores, "kind": "oracle",
+            "sample": "%d jobs = %d passes over the 61 pool images (1024x1024 Gaussian->Sobel->threshold->count/sum, "
+                      "float64 C oracle), thread pool of %d" % (len(work), passes, ncores)}
+
+
+def traffic_for(kernel_name):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_2606_05495_amd", "csrc", "kernels.hip"), "rb").read()
+        if rec.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
+            return None
+        return rec["kernels"].get(kernel_name)
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--jobs", type=int, default=10000, help="jobs per step")
+    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--inflight", type=int, default=0)
+    ap.add_argument("--spin-us", type=int, default=0)
+    ap.add_argument("--callback", default="event_chain", choices=["event_chain", "same_stream", "event_poll"])
+    ap.add_argument("--baseline-steps", type=int, default=1)
+    ap.add_argument("--no-baselines", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-passes", type=int, default=5)
+    ap.add_argument("--stage-reps", type=int, default=200)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the job path shards by running one independent scheduler per GPU, "
+              "and runs on more than one GPU are not part of this build (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU (HIP device)", file=sys.stderr)
+        sys.exit(2)
+    from paper_2606_05495_amd import synth
+    from paper_2606_05495_amd.runtime import pinned
+    import oracle
+
+    pool = synth.IMAGE_POOL
+    log("generating %d pool images" % pool)
+    imgs = synth.image_pool(0, pool)
+    ib = 4 * 1024 * 1024
+    tin, nin = pinned(ib * pool)
+    nin.view(np.float32)[:] = imgs.ravel()
+    tout, _ = pinned(128 * args.jobs)
+    refs = [oracle.gauss_sobel(imgs[k], want_images=False) for k in range(pool)]
+
+    log("SET mode: %d jobs x %d steps" % (args.jobs, args.steps))
+    ctx, tid, dt, st, times = run_mode("set", args, args.jobs, args.steps, args.warmup, tin, tout, pool, torch,
+                                       callback=args.callback)
+    n_total = args.jobs * args.steps
+    set_jps = n_total / dt
+    set_ok, set_bad = verify(tout, args.jobs, imgs, refs)
+    lat_dev = (times["t_done"] - times["t_launch"]) / 1e3
+    lat_sub = (times["t_done"] - times["t_submit"]) / 1e3
+
+    # dominant kernel of the chain, timed with HIP events on worker 0's stream
+    stages = ctx.stage_info(tid)
+    stage_us = [ctx.time_stage(tid, i, 0, args.stage_reps) for i in range(len(stages))]
+    dom = int(np.argmax(stage_us))
+    dom_name, dom_bytes = stages[dom]
+    achieved = dom_bytes / (stage_us[dom] * 1e-6) / 1e9
+    ctx.close()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_for(dom_name),
+                "kernel": dom_name, "bytes_per_launch": int(dom_bytes), "avg_us": round(stage_us[dom], 3),
+                "stages_us": {n: round(u, 3) for (n, _), u in zip(stages, stage_us)}}
+
+    extra = {}
+    if not args.no_baselines:
+        for mode in ("batch", "sync"):
+            log("%s baseline: %d jobs x %d steps" % (mode, args.jobs, args.baseline_steps))
+            tout.zero_()
+            c2, _, dt2, st2, _ = run_mode(mode, args, args.jobs, args.baseline_steps, 1, tin, tout, pool, torch)
+            c2.close()
+            ok2, bad2 = verify(tout, args.jobs, imgs, refs)
+            jps = args.jobs * args.baseline_steps / dt2
+            extra[mode] = {"jobs_per_s": round(jps, 1), "verified": ok2,
+                           "host_sync_ms": round(st2.host_ns_sync / 1e6, 2)}
+
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        cpu = cpu_baseline(imgs, args.cpu_passes)
+
+    h2d = ib * set_jps / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(set_jps, 1),
+        "unit": "jobs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "gauss5-sobel-threshold-count/sum 1024x1024 f32 jobs, H2D 4 MiB + D2H 72 B each",
+                   "jobs_per_step": args.jobs, "workers": args.workers, "slots_per_worker": args.slots,
+                   "callback": args.callback, "image_pool": pool},
+        "verified": bool(set_ok),
+        "h2d_GBps": round(h2d, 2),
+        "batch_sync_jobs_per_s": extra.get("batch", {}).get("jobs_per_s"),
+        "speedup_vs_batch_sync": round(set_jps / extra["batch"]["jobs_per_s"], 3) if "batch" in extra else None,
+        "sync_jobs_per_s": extra.get("sync", {}).get("jobs_per_s"),
+        "speedup_vs_sync": round(set_jps / extra["sync"]["jobs_per_s"], 3) if "sync" in extra else None,
+        "baselines": extra,
+        "job_latency_us": {"launch_to_done_p50": round(float(np.percentile(lat_dev, 50)), 1),
+                           "launch_to_done_p99": round(float(np.percentile(lat_dev, 99)), 1),
+                           "submit_to_done_p50": round(float(np.percentile(lat_sub, 50)), 1),
+                           "submit_to_done_p99": round(float(np.percentile(lat_sub, 99)), 1)},
+        "sched": {"stolen": int(st.stolen), "inflight_high_water": int(st.inflight_high_water),
+                  "host_us_per_job_bind": round(st.host_ns_bind / 1e3 / max(1, st.completed), 2),
+                  "host_us_per_job_launch": round(st.host_ns_launch / 1e3 / max(1, st.completed), 2),
+                  "host_us_per_job_callback": round(st.host_ns_callback / 1e3 / max(1, st.completed), 2)},
+        "mean_kernel_gap_us": None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

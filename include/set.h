@@ -1,0 +1,312 @@
+/*
+ * set.h -- C ABI of the stream-event-triggered (SET) job-pipeline runtime for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method (Li, Huang, Ogras, "SET: Stream-Event-Triggered Scheduling for
+ * Efficient CUDA Graph Pipelines"): every job is a host-to-device copy, a
+ * chain of short kernels and a device-to-host copy (Section 3.2).  Each job
+ * is replayed as a pre-instantiated graph executable bound to one worker's
+ * stream and buffers (Section 4.1, "Job-as-Graph and Memory Management";
+ * Section 4.2 (1) "Workers").  A submitter thread binds per-job parameters
+ * and pushes ready executables into per-worker queues (Algorithm 1); a
+ * dispatcher thread pairs free workers with jobs, stealing from other
+ * workers' queues when its own is empty and retargeting a stolen job to the
+ * thief's buffers (Algorithm 2); a completion callback returns the worker to
+ * the free pool (Algorithm 3).
+ *
+ * Conventions for every call:
+ *  - Return value: SET_OK (0) or a negative SET_E* code.  No exception ever
+ *    crosses the ABI.  After the first device (HIP) failure a context is
+ *    latched into SET_EDEVICE and every later call on it returns SET_EDEVICE;
+ *    set_last_error() gives the message.
+ *  - Pointers named host_* are host addresses; pointers named dev_* / arena
+ *    are device addresses; streams are hipStream_t passed as void*.
+ *  - "Borrowed" memory and streams stay owned by the caller (in the Python
+ *    binding: allocated by PyTorch) and must outlive the context.
+ *  - Job inputs and outputs are caller-owned pinned host buffers.  host_in
+ *    must stay valid and unmodified until the job completes; host_out must
+ *    not be read before completion (completion callback or set_drain).
+ *  - Thread safety: set_submit / set_submit_many may be called from several
+ *    threads; set_get_stats may run concurrently with everything else.
+ *    set_template_define, set_drain, set_reset_stats and set_ctx_destroy must
+ *    not race with each other.
+ */
+#ifndef SET_H
+#define SET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SET_ABI_VERSION 1u
+
+/* ---------------------------------------------------------------- status codes */
+enum set_status {
+    SET_OK = 0,
+    SET_EINVAL = -1,       /* bad argument or configuration */
+    SET_ENOMEM = -2,       /* host or device allocation failed, or arena too small */
+    SET_EDEVICE = -3,      /* a HIP call failed; sticky for the context */
+    SET_EAGAIN = -4,       /* SET_NONBLOCK submit found the staging ring full */
+    SET_ETIMEOUT = -5,     /* set_drain timed out */
+    SET_ECLOSED = -6,      /* context is shutting down */
+    SET_EUNSUPPORTED = -7  /* operation not available in this mode/backend */
+};
+
+/* ---------------------------------------------------------------- run modes */
+/* The method and the comparison systems of Section 5.1 ("Baseline Models"),
+ * all behind the same submit/drain calls. */
+enum set_mode {
+    /* Event-chained per-job graphs: per-worker queues, free-worker pool,
+     * work stealing, completion callbacks (Section 4.2, Algorithms 1-3). */
+    SET_MODE_SET = 0,
+    /* Synchronous model: each job's copies and kernels launched directly on
+     * one stream, then a host synchronisation (Section 5.1, model 1).  Jobs
+     * run inside set_submit, round-robin over the configured streams. */
+    SET_MODE_SYNC = 1,
+    /* Graph model: one pre-instantiated job graph per stream, parameters
+     * updated and relaunched per job, host synchronisation per job
+     * (Section 5.1, model 2). */
+    SET_MODE_GRAPH = 2,
+    /* Static batching model: one graph of batch_size parallel job chains on a
+     * fixed stream, parameters updated per batch, host synchronisation per
+     * batch (Section 2; Section 3.2 "Inter-Batch Overheads"; Section 5.1,
+     * model 3). */
+    SET_MODE_BATCH_SYNC = 3
+};
+
+enum set_backend {
+    SET_BACKEND_HIP = 0,  /* the MI355X path */
+    SET_BACKEND_FAKE = 1  /* CPU stand-in (threads as streams) for scheduler tests; computes no pipeline */
+};
+
+/* Completion mechanism of SET mode ("AddCallback", Algorithm 2; Algorithm 3). */
+enum set_callback_mode {
+    /* hipEventRecord on the worker stream, hipStreamWaitEvent on a per-worker
+     * callback stream, hipLaunchHostFunc there: the worker stream never waits
+     * for the host callback (event chaining). */
+    SET_CB_EVENT_CHAIN = 0,
+    /* hipLaunchHostFunc directly on the worker stream after the graph. */
+    SET_CB_SAME_STREAM = 1,
+    /* hipEventRecord only; a library completion thread observes the events
+     * in launch order (ablation; polls instead of using driver callbacks). */
+    SET_CB_EVENT_POLL = 2
+};
+
+enum set_submit_policy {
+    SET_SUBMIT_ROUND_ROBIN = 0,  /* next queue with room, cyclically (Algorithm 1) */
+    SET_SUBMIT_SHORTEST = 1,     /* queue with fewest bound jobs */
+    SET_SUBMIT_SKEW0 = 2         /* everything to worker 0 (forces steals; tests) */
+};
+
+/* ---------------------------------------------------------------- pipelines */
+/* The job families (synthetic stand-ins for the image and small-kernel
+ * workloads of Section 5.1).  Layouts are row-major, dense. */
+enum set_pipeline {
+    /* in: h*w uint8 image.  3x3 box sum with zero padding (uint16) ->
+     * floor(sum/9) (uint8) -> 256-bin histogram (uint32).
+     * out: set_out_header + uint32[256]; with SET_TF_DEBUG also uint16 sums
+     * (h*w) then uint8 quotients (h*w), each at a 64-byte aligned offset. */
+    SET_PIPE_BOX_HIST_U8 = 0,
+    /* in: h*w float32 image.  Separable 5x5 Gaussian (sigma 1, radius 2, taps
+     * normalised then rounded to float32, replicated borders, horizontal then
+     * vertical) -> Sobel magnitude sqrt(gx^2+gy^2) (unnormalised 3x3 kernels,
+     * replicated borders) -> mask = mag > threshold (uint8) -> count of mask
+     * (uint32) and sum of mag over all pixels (float32).
+     * out: set_out_header + {uint32 count, float32 sum}; with SET_TF_DEBUG
+     * also the uint8 mask (h*w) then the float32 blurred image (h*w). */
+    SET_PIPE_GAUSS_SOBEL_F32 = 1,
+    /* no H2D: x and y are windows [x_off, x_off+n), [y_off, y_off+n) of the
+     * template's device-resident pools.  z = a*x + y -> t = tanh(z) ->
+     * S = sum t (float32).  out: set_out_header + float32 S. */
+    SET_PIPE_SAXPY_TANH_SUM_F32 = 2,
+    /* in: n int32.  Inclusive prefix sum accumulated in int64.
+     * out: set_out_header + int64[n] (or the low int32 words with
+     * SET_TF_SCAN_LOW32). */
+    SET_PIPE_SCAN_I32_I64 = 3
+};
+
+/* template flags */
+#define SET_TF_DEBUG 0x1u       /* also copy intermediate images back (parity tests) */
+#define SET_TF_SCAN_LOW32 0x2u  /* scan: copy back only the low 32 bits of each sum */
+
+/* submit flags */
+#define SET_NONBLOCK 0x1  /* return SET_EAGAIN instead of waiting for staging room */
+
+/* ---------------------------------------------------------------- structs */
+typedef struct set_config {
+    uint32_t abi_version;        /* must equal SET_ABI_VERSION */
+    int32_t mode;                /* enum set_mode */
+    int32_t backend;             /* enum set_backend */
+    int32_t device;              /* HIP device ordinal */
+    int32_t num_workers;         /* b: workers, one stream each (Section 4.2 (1)); 1..64 */
+    int32_t slots_per_worker;    /* d: buffer slots (one graph exec each) per worker; 1..64 */
+    int32_t queue_capacity;      /* capacity of each per-worker queue Q_i; 0 = d - inflight */
+    int32_t inflight_per_worker; /* launch permits per worker in the free pool; 0 = max(1, d/2) */
+    int32_t work_stealing;       /* 1: FindJob steals from (w+k) mod b (Algorithm 2); 0: local only */
+    int32_t batch_size;          /* SET_MODE_BATCH_SYNC: job chains per batch graph; 0 = num_workers */
+    int32_t callback_mode;       /* enum set_callback_mode (SET mode) */
+    int32_t submit_policy;       /* enum set_submit_policy */
+    int32_t spin_us;             /* dispatcher spin before blocking on its condition variable */
+    int32_t staging_capacity;    /* bound of the submit staging ring; 0 = 4096 */
+    uint64_t mem_budget_bytes;   /* admission cap on the summed slot footprint of bound jobs; 0 = none */
+    void **streams;              /* num_workers borrowed hipStream_t, or NULL: the library creates them */
+    uint64_t seed;               /* recorded in stats only */
+    /* CPU fake backend knobs (ignored by the HIP backend) */
+    int32_t fake_fail_after;     /* >0: the N-th launch fails with SET_EDEVICE (error latching tests) */
+    int32_t fake_reorder_callbacks; /* 1: completion callbacks may run out of launch order */
+} set_config;
+
+typedef struct set_job_template {
+    int32_t pipeline;            /* enum set_pipeline */
+    uint32_t flags;              /* SET_TF_* */
+    uint32_t width, height;      /* image pipelines: image size (each >= 1) */
+    uint64_t max_n;              /* vector / scan pipelines: largest n any job may use (>= 1) */
+    float threshold;             /* Gaussian/Sobel mask threshold; 0 means 1.0 */
+    uint32_t reserved0;
+    void *arena;                 /* borrowed device buffer for all slots of this template, or NULL: library allocates */
+    uint64_t arena_bytes;        /* size of `arena`; must be >= set_template_footprint's total */
+    const float *dev_x_pool;     /* SAXPY: borrowed device pool of x values */
+    const float *dev_y_pool;     /* SAXPY: borrowed device pool of y values */
+    uint64_t pool_len;           /* SAXPY: elements in each pool */
+    int32_t block;               /* tuning: threads per block (0 = default) */
+    int32_t grid;                /* tuning: grid cap for streaming kernels (0 = default) */
+} set_job_template;
+
+typedef struct set_job_args {
+    const void *host_in;         /* pinned host input (NULL for pipelines without H2D) */
+    uint64_t in_bytes;           /* must equal the pipeline's input size for this job */
+    void *host_out;              /* pinned host output: set_out_header + payload */
+    uint64_t out_bytes;          /* >= the pipeline's output size for this job */
+    uint64_t n;                  /* vector / scan length (0 = template max_n for scan) */
+    float a;                     /* SAXPY scale */
+    int32_t worker_hint;         /* -1: submitter policy; else preferred worker */
+    uint64_t x_off, y_off;       /* SAXPY: element offsets into the x / y pools */
+    uint64_t user_tag;           /* copied into the output header */
+} set_job_args;
+
+/* Written by the device at the start of every job output (64 bytes). */
+#define SET_OUT_MAGIC 0x5E7D0A11u
+typedef struct set_out_header {
+    uint64_t job_id;     /* id assigned by set_submit (consecutive from 0 per context) */
+    uint64_t seq;        /* per-slot binding sequence number */
+    uint32_t worker;     /* worker (stream) that ran the job */
+    uint32_t slot;       /* buffer slot the job ran in */
+    uint32_t magic;      /* SET_OUT_MAGIC once the job's last stage ran */
+    uint32_t canary_ok;  /* 1 if the slot's head and tail canaries were intact */
+    uint64_t user_tag;   /* set_job_args.user_tag */
+    uint64_t reserved[3];
+} set_out_header;
+
+typedef struct set_stats {
+    uint64_t submitted, completed, stolen, failed;
+    uint64_t launches_per_worker[64];
+    uint64_t host_ns_bind;       /* submitter (or caller) time spent binding parameters */
+    uint64_t host_ns_launch;     /* dispatcher time in graph launch + callback registration */
+    uint64_t host_ns_callback;   /* time spent inside completion callbacks */
+    uint64_t host_ns_sync;       /* baseline modes: time blocked in host synchronisation */
+    uint32_t queue_high_water;   /* most jobs ever queued in one Q_i */
+    uint32_t inflight_high_water;/* most jobs ever launched and not yet completed */
+    uint64_t bytes_h2d, bytes_d2h;
+    uint64_t mem_in_use, mem_high_water;  /* admission accounting (bytes of bound slots) */
+    uint64_t batches;            /* batch-sync mode: batch graphs launched */
+    uint64_t t_first_submit_ns, t_last_done_ns;  /* steady-clock stamps */
+} set_stats;
+
+/* Per-job timestamps (steady clock, ns) for latency percentiles. */
+typedef struct set_job_times {
+    uint64_t job_id;
+    uint64_t t_submit, t_launch, t_done;
+    int32_t worker, slot, stolen, status;
+} set_job_times;
+
+typedef void (*set_completion_fn)(uint64_t job_id, int status, void *user);
+
+typedef struct set_ctx set_ctx;
+
+/* ---------------------------------------------------------------- calls */
+
+/* Create a context: b workers with their streams (borrowed or created),
+ * per-worker queues and callback streams, the free pool, and (SET mode) the
+ * submitter and dispatcher threads ("Initialization", Section 4.2).
+ * cfg is copied.  *out receives the handle.  Errors: SET_EINVAL (bad sizes,
+ * abi_version mismatch), SET_ENOMEM, SET_EDEVICE (no device / HIP failure). */
+int set_ctx_create(const set_config *cfg, set_ctx **out);
+
+/* Drain outstanding jobs, stop threads, destroy graphs, events and
+ * library-created streams and allocations.  Never frees borrowed memory or
+ * streams.  NULL is accepted (no-op). */
+int set_ctx_destroy(set_ctx *c);
+
+/* Bytes of device memory one buffer slot of template t needs, and the total
+ * for num_workers * slots_per_worker slots of cfg (what a borrowed arena must
+ * hold).  Pure host computation; either output may be NULL. */
+int set_template_footprint(const set_config *cfg, const set_job_template *t,
+                           uint64_t *slot_bytes, uint64_t *total_bytes);
+
+/* Define a job template: lay out one buffer slot per (worker, slot) in the
+ * arena and build + instantiate + upload one graph per slot whose nodes hold
+ * placeholders for per-job arguments (Section 4.1).  In batch-sync mode the
+ * batch graph is built instead.  *template_id receives the id (0, 1, ...).
+ * Must be called before any submit of that template. */
+int set_template_define(set_ctx *c, const set_job_template *t, int *template_id);
+
+/* Submit one job.  Returns once the job is accepted: in SET mode it is in
+ * the staging ring (the submitter thread binds and queues it, Algorithm 1);
+ * in SYNC / GRAPH mode it has already run; in BATCH_SYNC mode it has joined
+ * the current batch (the batch runs when full or at set_drain).  *job_id
+ * (may be NULL) receives the consecutive id.  SET_EAGAIN with SET_NONBLOCK
+ * when the staging ring is full. */
+int set_submit(set_ctx *c, int template_id, const set_job_args *a, int flags, uint64_t *job_id);
+
+/* Submit count jobs of one template in order (same semantics as count calls
+ * of set_submit; stops at the first error, which is returned). */
+int set_submit_many(set_ctx *c, int template_id, const set_job_args *a, uint64_t count,
+                    int flags, uint64_t *first_job_id);
+
+/* Register a function called once per completed job, on a library or driver
+ * thread, after the job's output is in host memory.  It must not call back
+ * into this library or into HIP.  fn == NULL unregisters. */
+int set_set_completion_cb(set_ctx *c, set_completion_fn fn, void *user);
+
+/* Block until every submitted job has completed (c_done == submitted,
+ * Algorithm 3's counter).  timeout_ns < 0 waits forever.  SET_ETIMEOUT on
+ * timeout (jobs keep running). */
+int set_drain(set_ctx *c, int64_t timeout_ns);
+
+/* Snapshot of the counters (may run concurrently with jobs). */
+int set_get_stats(set_ctx *c, set_stats *out);
+
+/* Zero counters and per-job time records (call when drained). */
+int set_reset_stats(set_ctx *c);
+
+/* Copy up to max records of per-job times for jobs completed since the last
+ * reset, in completion order; *count receives how many were written. */
+int set_get_job_times(set_ctx *c, set_job_times *out, uint64_t max, uint64_t *count);
+
+/* Measurement helper: launch stage `stage` (0-based kernel of the template's
+ * chain) of template `template_id` `reps` times back to back on worker
+ * `worker`'s stream against slot 0 of that worker, bracketed by two HIP events
+ * on that stream; *avg_us receives the mean duration per launch.  The slot's
+ * current contents are used as input, so run one job on that slot first.
+ * Requires a drained context. */
+int set_time_stage(set_ctx *c, int template_id, int stage, int worker, int reps, double *avg_us);
+
+/* Number of kernels in the template's chain and the algorithmic HBM bytes one
+ * launch of each moves (reads + writes of its operands, counted once). */
+int set_stage_info(set_ctx *c, int template_id, int *num_stages, uint64_t *bytes_per_stage,
+                   int max_stages, char *names, int names_len);
+
+/* Message of the last error on this context ("" if none); c == NULL gives the
+ * last error of a failed set_ctx_create on this thread. */
+const char *set_last_error(const set_ctx *c);
+
+/* Static name of a status code. */
+const char *set_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SET_H */

@@ -1,0 +1,600 @@
+// HIP backend: job templates become per-(worker, slot) graph executables
+// (H2D memcpy node -> stage kernel nodes -> D2H memcpy node, Section 4.1),
+// bound per job by updating the executable's memcpy endpoints and the first
+// kernel's argument block (UpdateGraphParams), launched on the worker's
+// stream with a completion callback (GraphLaunch + AddCallback, Algorithm 2).
+// The same slots and kernels serve the comparison systems of Section 5.1
+// (direct launches, per-job graph relaunch, one batch graph of b chains).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace setrt {
+
+namespace {
+
+#define HIPCK(expr)                                                                  \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      if (err) *err = std::string(#expr) + " failed: " + hipGetErrorString(e_);     \
+      return SET_EDEVICE;                                                            \
+    }                                                                                \
+  } while (0)
+
+struct CbCtx {
+  JobRec* job;
+  DoneFn done;
+  void* ctx;
+};
+
+struct ChainNodes {
+  hipGraphNode_t h2d = nullptr, d2h = nullptr;
+  hipGraphNode_t k[kMaxStages] = {};
+};
+
+struct Slot {
+  char* base = nullptr;
+  int tmpl = 0, w = 0, s = 0;
+  BoxArgs box;
+  Div9Args div;
+  HistArgs hist;
+  GaussArgs gauss;
+  SobelArgs sobel;
+  VecArgs vec;
+  ScanArgs scan;
+  int nstages = 0;
+  const void* func[kMaxStages] = {};
+  dim3 grid[kMaxStages];
+  void* argv[kMaxStages][1] = {};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ChainNodes nodes;
+  hipEvent_t ev = nullptr;
+  CbCtx cb{};
+  const void* host_in = nullptr;
+  uint64_t in_bytes = 0;
+  void* host_out = nullptr;
+  uint64_t out_bytes = 0;
+};
+
+struct BatchGraph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  std::vector<ChainNodes> chains;
+};
+
+struct Pipe {
+  set_job_template t{};
+  SlotLayout L{};
+  char* arena = nullptr;
+  bool own_arena = false;
+  void* placeholder = nullptr;  // pinned host buffer the memcpy nodes point at before the first bind
+  std::vector<Slot> slots;      // [w * d + s]
+  std::vector<BatchGraph> batch;  // [count - 1]
+};
+
+// Taps of the sampled Gaussian of radius 2 and sigma 1, normalised and
+// rounded to float32: out[0] for |k| = 2, out[1] for |k| = 1, out[2] centre.
+void gaussian_taps(float out[3]) {
+  const double e2 = std::exp(-2.0), e1 = std::exp(-0.5), e0 = 1.0;
+  const double s = e0 + 2.0 * e1 + 2.0 * e2;
+  out[0] = (float)(e2 / s);
+  out[1] = (float)(e1 / s);
+  out[2] = (float)(e0 / s);
+}
+
+inline dim3 to_dim3(Grid3 g) { return dim3(g.x, g.y, g.z); }
+
+thread_local int t_dev = -1;
+
+class HipBackend : public Backend {
+ public:
+  ~HipBackend() override { shutdown(); }
+
+  int init(const set_config& cfg, std::string* err) override {
+    cfg_ = cfg;
+    b_ = cfg.num_workers;
+    d_ = cfg.slots_per_worker;
+    int ndev = 0;
+    HIPCK(hipGetDeviceCount(&ndev));
+    if (cfg.device < 0 || cfg.device >= ndev) {
+      if (err) *err = "no such HIP device";
+      return SET_EDEVICE;
+    }
+    dev_ = cfg.device;
+    HIPCK(hipSetDevice(dev_));
+    t_dev = dev_;
+    streams_.resize(b_);
+    if (cfg.streams) {
+      for (int i = 0; i < b_; ++i) {
+        if (!cfg.streams[i]) {
+          if (err) *err = "null borrowed stream";
+          return SET_EINVAL;
+        }
+        streams_[i] = (hipStream_t)cfg.streams[i];
+      }
+    } else {
+      own_streams_ = true;
+      for (int i = 0; i < b_; ++i) HIPCK(hipStreamCreateWithFlags(&streams_[i], hipStreamNonBlocking));
+    }
+    if (cfg.mode == SET_MODE_SET && cfg.callback_mode == SET_CB_EVENT_CHAIN) {
+      cb_streams_.resize(b_);
+      for (int i = 0; i < b_; ++i) HIPCK(hipStreamCreateWithFlags(&cb_streams_[i], hipStreamNonBlocking));
+    }
+    if (cfg.mode == SET_MODE_SET && cfg.callback_mode == SET_CB_EVENT_POLL) {
+      poll_q_.resize(b_);
+      poller_ = std::thread([this] { poll_loop(); });
+    }
+    return SET_OK;
+  }
+
+  int define_template(int id, const set_job_template& t, std::string* err) override {
+    ensure_dev();
+    if ((int)pipes_.size() != id) {
+      if (err) *err = "template ids out of order";
+      return SET_EINVAL;
+    }
+    pipes_.emplace_back(new Pipe());
+    Pipe& p = *pipes_.back();
+    p.t = t;
+    p.L = slot_layout(t);
+    const uint64_t total = p.L.total * (uint64_t)b_ * (uint64_t)d_;
+    if (t.arena) {
+      if (t.arena_bytes < total) {
+        if (err) *err = "borrowed arena smaller than the template footprint";
+        return SET_ENOMEM;
+      }
+      p.arena = (char*)t.arena;
+    } else {
+      void* a = nullptr;
+      hipError_t e = hipMalloc(&a, total);
+      if (e != hipSuccess) {
+        if (err) *err = std::string("hipMalloc arena: ") + hipGetErrorString(e);
+        return SET_ENOMEM;
+      }
+      p.arena = (char*)a;
+      p.own_arena = true;
+    }
+    HIPCK(hipMemset(p.arena, 0, total));
+    const uint64_t ph = std::max<uint64_t>(std::max(p.L.in_cap, p.L.out_cap), 64);
+    HIPCK(hipHostMalloc(&p.placeholder, ph, hipHostMallocDefault));
+    std::memset(p.placeholder, 0, ph);
+    float taps[3];
+    gaussian_taps(taps);
+    p.slots.resize((size_t)b_ * d_);
+    for (int w = 0; w < b_; ++w) {
+      for (int s = 0; s < d_; ++s) {
+        Slot& sl = p.slots[(size_t)w * d_ + s];
+        sl.tmpl = id;
+        sl.w = w;
+        sl.s = s;
+        sl.base = p.arena + p.L.total * ((uint64_t)w * d_ + s);
+        setup_slot(p, sl, taps);
+        const uint64_t ch = canary_value(id, w, s, 0), ct = canary_value(id, w, s, 1);
+        HIPCK(hipMemcpy(sl.base + p.L.hdr, &ch, 8, hipMemcpyHostToDevice));
+        HIPCK(hipMemcpy(sl.base + p.L.tail, &ct, 8, hipMemcpyHostToDevice));
+      }
+    }
+    if (cfg_.mode == SET_MODE_SET || cfg_.mode == SET_MODE_GRAPH) {
+      const int ds = (cfg_.mode == SET_MODE_GRAPH) ? 1 : d_;
+      for (int w = 0; w < b_; ++w) {
+        for (int s = 0; s < ds; ++s) {
+          Slot& sl = p.slots[(size_t)w * d_ + s];
+          HIPCK(hipGraphCreate(&sl.graph, 0));
+          int rc = add_chain(p, sl, sl.graph, &sl.nodes, err);
+          if (rc != SET_OK) return rc;
+          HIPCK(hipGraphInstantiateWithFlags(&sl.exec, sl.graph, 0));
+          HIPCK(hipGraphUpload(sl.exec, streams_[w]));
+          if (cfg_.mode == SET_MODE_SET) HIPCK(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+        }
+      }
+    }
+    if (cfg_.mode == SET_MODE_BATCH_SYNC) p.batch.resize(b_);
+    HIPCK(hipDeviceSynchronize());
+    return SET_OK;
+  }
+
+  int bind(JobRec* j, std::string* err) override {
+    ensure_dev();
+    Pipe& p = *pipes_[j->tmpl];
+    Slot& sl = p.slots[(size_t)j->worker * d_ + j->slot];
+    set_scalars(p, sl, j);
+    return update_exec(p, sl, sl.exec, sl.nodes, err);
+  }
+
+  int launch(JobRec* j, DoneFn done, void* ctx, std::string* err) override {
+    ensure_dev();
+    Pipe& p = *pipes_[j->tmpl];
+    Slot& sl = p.slots[(size_t)j->worker * d_ + j->slot];
+    const int w = j->worker;
+    hipStream_t st = streams_[w];
+    sl.cb = CbCtx{j, done, ctx};
+    HIPCK(hipGraphLaunch(sl.exec, st));
+    switch (cfg_.callback_mode) {
+      case SET_CB_EVENT_CHAIN:
+        HIPCK(hipEventRecord(sl.ev, st));
+        HIPCK(hipStreamWaitEvent(cb_streams_[w], sl.ev, 0));
+        HIPCK(hipLaunchHostFunc(cb_streams_[w], &HipBackend::host_cb, &sl.cb));
+        break;
+      case SET_CB_SAME_STREAM:
+        HIPCK(hipLaunchHostFunc(st, &HipBackend::host_cb, &sl.cb));
+        break;
+      case SET_CB_EVENT_POLL: {
+        HIPCK(hipEventRecord(sl.ev, st));
+        {
+          std::lock_guard<std::mutex> g(poll_mu_);
+          poll_q_[w].push_back(&sl);
+          ++poll_pending_;
+        }
+        poll_cv_.notify_one();
+        break;
+      }
+    }
+    return SET_OK;
+  }
+
+  int run_sync(JobRec* j, int si, std::string* err) override {
+    ensure_dev();
+    Pipe& p = *pipes_[j->tmpl];
+    Slot& sl = p.slots[(size_t)si * d_];
+    set_scalars(p, sl, j);
+    hipStream_t st = streams_[si];
+    if (sl.in_bytes) HIPCK(hipMemcpyAsync(sl.base + p.L.in, sl.host_in, sl.in_bytes, hipMemcpyHostToDevice, st));
+    for (int i = 0; i < sl.nstages; ++i)
+      HIPCK(hipLaunchKernel(sl.func[i], sl.grid[i], dim3(kBlock), sl.argv[i], 0, st));
+    HIPCK(hipMemcpyAsync(sl.host_out, sl.base + p.L.out, sl.out_bytes, hipMemcpyDeviceToHost, st));
+    const uint64_t t0 = now_ns();
+    HIPCK(hipStreamSynchronize(st));
+    sync_ns_ += now_ns() - t0;
+    return SET_OK;
+  }
+
+  int run_graph(JobRec* j, int si, std::string* err) override {
+    ensure_dev();
+    Pipe& p = *pipes_[j->tmpl];
+    Slot& sl = p.slots[(size_t)si * d_];
+    set_scalars(p, sl, j);
+    int rc = update_exec(p, sl, sl.exec, sl.nodes, err);
+    if (rc != SET_OK) return rc;
+    hipStream_t st = streams_[si];
+    HIPCK(hipGraphLaunch(sl.exec, st));
+    const uint64_t t0 = now_ns();
+    HIPCK(hipStreamSynchronize(st));
+    sync_ns_ += now_ns() - t0;
+    return SET_OK;
+  }
+
+  int run_batch(JobRec** jobs, int count, std::string* err) override {
+    ensure_dev();
+    if (count < 1) return SET_OK;
+    const int tmpl = jobs[0]->tmpl;
+    for (int i = 1; i < count; ++i)
+      if (jobs[i]->tmpl != tmpl) {
+        if (err) *err = "a batch graph holds chains of one template";
+        return SET_EINVAL;
+      }
+    Pipe& p = *pipes_[tmpl];
+    BatchGraph& bg = p.batch[count - 1];
+    if (!bg.ex) {
+      HIPCK(hipGraphCreate(&bg.g, 0));
+      bg.chains.resize(count);
+      for (int i = 0; i < count; ++i) {
+        int rc = add_chain(p, p.slots[(size_t)i * d_], bg.g, &bg.chains[i], err);
+        if (rc != SET_OK) return rc;
+      }
+      HIPCK(hipGraphInstantiateWithFlags(&bg.ex, bg.g, 0));
+      HIPCK(hipGraphUpload(bg.ex, streams_[0]));
+    }
+    for (int i = 0; i < count; ++i) {
+      Slot& sl = p.slots[(size_t)i * d_];
+      set_scalars(p, sl, jobs[i]);
+      int rc = update_exec(p, sl, bg.ex, bg.chains[i], err);
+      if (rc != SET_OK) return rc;
+    }
+    HIPCK(hipGraphLaunch(bg.ex, streams_[0]));
+    const uint64_t t0 = now_ns();
+    HIPCK(hipStreamSynchronize(streams_[0]));
+    sync_ns_ += now_ns() - t0;
+    return SET_OK;
+  }
+
+  int time_stage(int tmpl, int stage, int worker, int reps, double* avg_us, std::string* err) override {
+    ensure_dev();
+    Pipe& p = *pipes_[tmpl];
+    Slot& sl = p.slots[(size_t)worker * d_];
+    if (stage < 0 || stage >= sl.nstages) {
+      if (err) *err = "no such stage";
+      return SET_EINVAL;
+    }
+    hipStream_t st = streams_[worker];
+    hipEvent_t e0, e1;
+    HIPCK(hipEventCreate(&e0));
+    HIPCK(hipEventCreate(&e1));
+    const uint64_t seq0 = sl.scan.js.seq;
+    HIPCK(hipLaunchKernel(sl.func[stage], sl.grid[stage], dim3(kBlock), sl.argv[stage], 0, st));
+    HIPCK(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r) {
+      if (p.t.pipeline == SET_PIPE_SCAN_I32_I64) sl.scan.js.seq = seq0 + 1 + (uint64_t)r;  // fresh epoch per launch
+      HIPCK(hipLaunchKernel(sl.func[stage], sl.grid[stage], dim3(kBlock), sl.argv[stage], 0, st));
+    }
+    HIPCK(hipEventRecord(e1, st));
+    HIPCK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCK(hipEventElapsedTime(&ms, e0, e1));
+    sl.scan.js.seq = seq0;
+    HIPCK(hipEventDestroy(e0));
+    HIPCK(hipEventDestroy(e1));
+    *avg_us = (double)ms * 1e3 / reps;
+    return SET_OK;
+  }
+
+  uint64_t host_ns_sync() const override { return sync_ns_.load(); }
+
+  void shutdown() override {
+    if (down_) return;
+    down_ = true;
+    if (poller_.joinable()) {
+      {
+        std::lock_guard<std::mutex> g(poll_mu_);
+        poll_stop_ = true;
+      }
+      poll_cv_.notify_all();
+      poller_.join();
+    }
+    if (dev_ >= 0) (void)hipSetDevice(dev_);
+    (void)hipDeviceSynchronize();
+    for (auto& pp : pipes_) {
+      Pipe& p = *pp;
+      for (Slot& sl : p.slots) {
+        if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+        if (sl.graph) (void)hipGraphDestroy(sl.graph);
+        if (sl.ev) (void)hipEventDestroy(sl.ev);
+      }
+      for (BatchGraph& bg : p.batch) {
+        if (bg.ex) (void)hipGraphExecDestroy(bg.ex);
+        if (bg.g) (void)hipGraphDestroy(bg.g);
+      }
+      if (p.own_arena && p.arena) (void)hipFree(p.arena);
+      if (p.placeholder) (void)hipHostFree(p.placeholder);
+    }
+    pipes_.clear();
+    for (hipStream_t s : cb_streams_) (void)hipStreamDestroy(s);
+    cb_streams_.clear();
+    if (own_streams_)
+      for (hipStream_t s : streams_) (void)hipStreamDestroy(s);
+    streams_.clear();
+  }
+
+ private:
+  void ensure_dev() {
+    if (t_dev != dev_) {
+      (void)hipSetDevice(dev_);
+      t_dev = dev_;
+    }
+  }
+
+  static void host_cb(void* p) {
+    const CbCtx c = *static_cast<CbCtx*>(p);  // copy: the slot may be rebound once done() returns
+    c.done(c.ctx, c.job, SET_OK);
+  }
+
+  // Completion thread of SET_CB_EVENT_POLL: observes each worker's events in
+  // launch order.
+  void poll_loop() {
+    ensure_dev();
+    std::vector<Slot*> ready;
+    while (true) {
+      {
+        std::unique_lock<std::mutex> lk(poll_mu_);
+        poll_cv_.wait(lk, [&] { return poll_stop_ || poll_pending_ > 0; });
+        if (poll_stop_ && poll_pending_ == 0) return;
+      }
+      ready.clear();
+      {
+        std::lock_guard<std::mutex> g(poll_mu_);
+        for (auto& q : poll_q_) {
+          while (!q.empty() && hipEventQuery(q.front()->ev) == hipSuccess) {
+            ready.push_back(q.front());
+            q.pop_front();
+            --poll_pending_;
+          }
+        }
+      }
+      for (Slot* sl : ready) host_cb(&sl->cb);
+      if (ready.empty()) std::this_thread::yield();
+    }
+  }
+
+  void setup_slot(Pipe& p, Slot& sl, const float taps[3]) {
+    const SlotLayout& L = p.L;
+    char* b = sl.base;
+    SlotConst sc;
+    sc.hdr = reinterpret_cast<DevSlotHdr*>(b + L.hdr);
+    sc.tail = reinterpret_cast<const uint64_t*>(b + L.tail);
+    sc.outh = reinterpret_cast<set_out_header*>(b + L.out);
+    sc.canary_head = canary_value(sl.tmpl, sl.w, sl.s, 0);
+    sc.canary_tail = canary_value(sl.tmpl, sl.w, sl.s, 1);
+    const set_job_template& t = p.t;
+    const int h = (int)t.height, w = (int)t.width;
+    const int64_t npix = (int64_t)h * w;
+    std::memset(&sl.box, 0, sizeof(sl.box));
+    switch (t.pipeline) {
+      case SET_PIPE_BOX_HIST_U8: {
+        sl.box = BoxArgs{(const uint8_t*)(b + L.in), (uint16_t*)(b + L.b1), h, w, sc.hdr, JobScalars{}};
+        sl.div = Div9Args{(const uint16_t*)(b + L.b1), (uint8_t*)(b + L.b2), npix};
+        const unsigned hb = hist_blocks(npix);
+        const uint64_t pbytes = (((uint64_t)hb * 1024) + 255) / 256 * 256;
+        sl.hist = HistArgs{(const uint8_t*)(b + L.b2), npix, (uint32_t*)(b + L.scratch),
+                           (uint32_t*)(b + L.scratch + pbytes), (uint32_t*)(b + L.out + 64), sc};
+        sl.nstages = 3;
+        sl.func[0] = (const void*)&k_box3_u8_u16;
+        sl.grid[0] = to_dim3(box_grid(h, w));
+        sl.argv[0][0] = &sl.box;
+        sl.func[1] = (const void*)&k_div9_u16_u8;
+        sl.grid[1] = dim3(div9_blocks(npix));
+        sl.argv[1][0] = &sl.div;
+        sl.func[2] = (const void*)&k_hist256_u8;
+        sl.grid[2] = dim3(hb);
+        sl.argv[2][0] = &sl.hist;
+        break;
+      }
+      case SET_PIPE_GAUSS_SOBEL_F32: {
+        sl.gauss = GaussArgs{(const float*)(b + L.in), (float*)(b + L.b1), h, w, taps[0], taps[1], taps[2], sc.hdr,
+                             JobScalars{}};
+        const Grid3 sg = sobel_grid(h, w);
+        const uint64_t nb = (uint64_t)sg.x * sg.y;
+        const uint64_t q = (nb * 4 + 255) / 256 * 256;
+        sl.sobel = SobelArgs{(const float*)(b + L.b1),
+                             (uint8_t*)(b + L.b2),
+                             h,
+                             w,
+                             t.threshold != 0.f ? t.threshold : 1.0f,
+                             (uint32_t*)(b + L.scratch),
+                             (float*)(b + L.scratch + q),
+                             (uint32_t*)(b + L.scratch + 2 * q),
+                             (uint32_t*)(b + L.out + 64),
+                             (float*)(b + L.out + 68),
+                             sc};
+        sl.nstages = 2;
+        sl.func[0] = (const void*)&k_gauss5_f32;
+        sl.grid[0] = to_dim3(gauss_grid(h, w));
+        sl.argv[0][0] = &sl.gauss;
+        sl.func[1] = (const void*)&k_sobel_thresh_f32;
+        sl.grid[1] = to_dim3(sg);
+        sl.argv[1][0] = &sl.sobel;
+        break;
+      }
+      case SET_PIPE_SAXPY_TANH_SUM_F32: {
+        const uint64_t q = ((uint64_t)kVecGridCap * 4 + 255) / 256 * 256;
+        sl.vec = VecArgs{t.dev_x_pool, t.dev_y_pool, (float*)(b + L.scratch), (uint32_t*)(b + L.scratch + q),
+                         (float*)(b + L.out + 64), sc, JobScalars{}};
+        sl.vec.js.n = t.max_n;
+        sl.nstages = 1;
+        sl.func[0] = (const void*)&k_saxpy_tanh_sum_f32;
+        sl.grid[0] = dim3(vec_blocks(t.max_n));
+        sl.argv[0][0] = &sl.vec;
+        break;
+      }
+      case SET_PIPE_SCAN_I32_I64: {
+        const uint64_t T = scan_tiles(t.max_n);
+        const uint64_t q4 = (T * 4 + 255) / 256 * 256, q8 = (T * 8 + 255) / 256 * 256;
+        char* sb = b + L.scratch;
+        uint32_t* ctr = (uint32_t*)(sb + q4 + 2 * q8);
+        sl.scan = ScanArgs{(const int32_t*)(b + L.in), (void*)(b + L.out + 64), (uint32_t*)sb, (int64_t*)(sb + q4),
+                           (int64_t*)(sb + q4 + q8), ctr, ctr + 1, ctr + 2,
+                           (t.flags & SET_TF_SCAN_LOW32) ? 1 : 0, sc, JobScalars{}};
+        sl.scan.js.n = t.max_n;
+        sl.nstages = 1;
+        sl.func[0] = (const void*)&k_scan_i32_i64;
+        sl.grid[0] = dim3((unsigned)T);
+        sl.argv[0][0] = &sl.scan;
+        break;
+      }
+    }
+  }
+
+  // Write the job's scalars into the slot's first-stage argument block and
+  // record its host endpoints.
+  void set_scalars(Pipe& p, Slot& sl, const JobRec* j) {
+    JobScalars js{};
+    js.job_id = j->id;
+    js.seq = j->seq;
+    js.user_tag = j->args.user_tag;
+    js.n = j->args.n;
+    js.x_off = j->args.x_off;
+    js.y_off = j->args.y_off;
+    js.worker = (uint32_t)j->worker;
+    js.slot = (uint32_t)j->slot;
+    js.a = j->args.a;
+    switch (p.t.pipeline) {
+      case SET_PIPE_BOX_HIST_U8:
+        sl.box.js = js;
+        break;
+      case SET_PIPE_GAUSS_SOBEL_F32:
+        sl.gauss.js = js;
+        break;
+      case SET_PIPE_SAXPY_TANH_SUM_F32:
+        sl.vec.js = js;
+        sl.grid[0] = dim3(vec_blocks(js.n));
+        break;
+      case SET_PIPE_SCAN_I32_I64:
+        if (js.n == 0) js.n = p.t.max_n;
+        sl.scan.js = js;
+        sl.grid[0] = dim3(scan_tiles(js.n));
+        break;
+    }
+    sl.host_in = j->args.host_in;
+    sl.in_bytes = pipeline_in_bytes(p.t, js.n);
+    sl.host_out = j->args.host_out;
+    sl.out_bytes = pipeline_out_bytes(p.t, js.n);
+  }
+
+  hipKernelNodeParams kparams(Slot& sl, int i) {
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(sl.func[i]);
+    kp.gridDim = sl.grid[i];
+    kp.blockDim = dim3(kBlock);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = sl.argv[i];
+    kp.extra = nullptr;
+    return kp;
+  }
+
+  int add_chain(Pipe& p, Slot& sl, hipGraph_t g, ChainNodes* cn, std::string* err) {
+    hipGraphNode_t prev = nullptr;
+    if (p.L.in_cap > 0) {
+      HIPCK(hipGraphAddMemcpyNode1D(&cn->h2d, g, nullptr, 0, sl.base + p.L.in, p.placeholder, p.L.in_cap,
+                                    hipMemcpyHostToDevice));
+      prev = cn->h2d;
+    }
+    for (int i = 0; i < sl.nstages; ++i) {
+      hipKernelNodeParams kp = kparams(sl, i);
+      HIPCK(hipGraphAddKernelNode(&cn->k[i], g, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+      prev = cn->k[i];
+    }
+    HIPCK(hipGraphAddMemcpyNode1D(&cn->d2h, g, &prev, 1, p.placeholder, sl.base + p.L.out, p.L.out_cap,
+                                  hipMemcpyDeviceToHost));
+    return SET_OK;
+  }
+
+  // UpdateGraphParams: retarget an executable's chain to the slot's current
+  // binding (H2D source, first kernel's argument block and grid, D2H target).
+  int update_exec(Pipe& p, Slot& sl, hipGraphExec_t ex, const ChainNodes& cn, std::string* err) {
+    if (sl.in_bytes)
+      HIPCK(hipGraphExecMemcpyNodeSetParams1D(ex, cn.h2d, sl.base + p.L.in, sl.host_in, sl.in_bytes,
+                                              hipMemcpyHostToDevice));
+    hipKernelNodeParams kp = kparams(sl, 0);
+    HIPCK(hipGraphExecKernelNodeSetParams(ex, cn.k[0], &kp));
+    HIPCK(hipGraphExecMemcpyNodeSetParams1D(ex, cn.d2h, sl.host_out, sl.base + p.L.out, sl.out_bytes,
+                                            hipMemcpyDeviceToHost));
+    return SET_OK;
+  }
+
+  set_config cfg_{};
+  int b_ = 0, d_ = 0, dev_ = -1;
+  bool own_streams_ = false, down_ = false;
+  std::vector<hipStream_t> streams_, cb_streams_;
+  std::vector<std::unique_ptr<Pipe>> pipes_;
+  std::atomic<uint64_t> sync_ns_{0};
+  // event polling
+  std::thread poller_;
+  std::mutex poll_mu_;
+  std::condition_variable poll_cv_;
+  std::vector<std::deque<Slot*>> poll_q_;
+  int64_t poll_pending_ = 0;
+  bool poll_stop_ = false;
+};
+
+}  // namespace
+
+Backend* make_hip_backend() { return new HipBackend(); }
+
+}  // namespace setrt

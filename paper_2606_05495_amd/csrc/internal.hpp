@@ -1,0 +1,126 @@
+// Internal declarations shared by the scheduler core, the HIP backend and the
+// CPU fake backend.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <atomic>
+#include <chrono>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "set.h"
+#include "tiles.hpp"
+
+namespace setrt {
+
+inline uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+constexpr int kMaxWorkers = 64;
+constexpr int kMaxSlots = 64;
+constexpr int kMaxTemplates = 16;
+constexpr int kMaxStages = 8;
+
+// Per-job scalar arguments.  Passed by value to the first kernel of a chain
+// (a kernel-node placeholder, Section 4.1) and written by it into the slot's
+// device header, where later stages read it.
+struct JobScalars {
+  uint64_t job_id;
+  uint64_t seq;
+  uint64_t user_tag;
+  uint64_t n;
+  uint64_t x_off;
+  uint64_t y_off;
+  uint32_t worker;
+  uint32_t slot;
+  float a;
+  uint32_t flags;
+};
+static_assert(sizeof(JobScalars) == 64, "JobScalars layout");
+
+// Device-side slot header (first bytes of every slot).  The first stage of a
+// job writes job_id/seq/worker/slot/user_tag; the last stage copies them into
+// the output header after checking the head and tail canaries.
+struct DevSlotHdr {
+  uint64_t canary_head;
+  uint64_t job_id;
+  uint64_t seq;
+  uint64_t user_tag;
+  uint32_t worker;
+  uint32_t slot;
+  uint32_t pad[6];
+};
+static_assert(sizeof(DevSlotHdr) == 64, "DevSlotHdr layout");
+static_assert(sizeof(set_out_header) == 64, "set_out_header layout");
+
+inline uint64_t canary_value(int tmpl, int w, int s, int which) {
+  return 0x5E7CA9A200000000ull ^ ((uint64_t)which << 60) ^ ((uint64_t)tmpl << 24) ^ ((uint64_t)w << 12) ^
+         (uint64_t)s;
+}
+
+// A submitted job (M5 of the method: id, prepared parameters, is_stolen).
+struct JobRec {
+  uint64_t id;
+  int tmpl;
+  set_job_args args;
+  int worker;     // worker whose slot the job is bound to
+  int slot;       // bound slot
+  int stolen;     // retargeted by a thief (Algorithm 2)
+  uint64_t seq;   // binding sequence number of that slot
+  uint64_t footprint;
+  uint64_t t_submit, t_launch, t_done;
+  int status;
+  JobRec* next;   // free list / intrusive links
+};
+
+// Sizes one template needs, computed on the host.
+struct TemplateSizes {
+  uint64_t slot_bytes;
+  int num_stages;
+  uint64_t stage_bytes[kMaxStages];
+  char stage_names[kMaxStages][32];
+};
+
+// Static per-job sizes of a template (in/out bytes for a job with length n).
+uint64_t pipeline_in_bytes(const set_job_template& t, uint64_t n);
+uint64_t pipeline_out_bytes(const set_job_template& t, uint64_t n);
+int pipeline_validate(const set_job_template& t, std::string* why);
+int pipeline_validate_job(const set_job_template& t, const set_job_args& a, std::string* why);
+// Implemented by the HIP pipeline code (needs kernel tile constants); the fake
+// backend uses the same sizes so footprints agree.
+int pipeline_sizes(const set_job_template& t, TemplateSizes* out);
+SlotLayout slot_layout(const set_job_template& t);
+
+// Completion hook the scheduler core hands to a backend launch.
+using DoneFn = void (*)(void* ctx, JobRec* job, int status);
+
+// Execution backend: owns device resources of every template.
+class Backend {
+ public:
+  virtual ~Backend() {}
+  // Create per-worker resources (streams are borrowed or created here).
+  virtual int init(const set_config& cfg, std::string* err) = 0;
+  // Allocate/lay out slots and build per-slot graphs (SET/GRAPH) or the batch graph (BATCH_SYNC).
+  virtual int define_template(int id, const set_job_template& t, std::string* err) = 0;
+  // UpdateGraphParams(J, i): bind job to slot (worker, slot) of its template.
+  virtual int bind(JobRec* job, std::string* err) = 0;
+  // GraphLaunch + AddCallback: launch the bound slot's executable on the
+  // worker's stream and arrange for done(ctx, job, status) after it finishes.
+  virtual int launch(JobRec* job, DoneFn done, void* ctx, std::string* err) = 0;
+  // Baselines, run on the caller's thread.
+  virtual int run_sync(JobRec* job, int stream_index, std::string* err) = 0;
+  virtual int run_graph(JobRec* job, int stream_index, std::string* err) = 0;
+  virtual int run_batch(JobRec** jobs, int count, std::string* err) = 0;
+  virtual int time_stage(int tmpl, int stage, int worker, int reps, double* avg_us, std::string* err) = 0;
+  virtual uint64_t host_ns_sync() const { return 0; }
+  virtual void shutdown() = 0;
+};
+
+Backend* make_hip_backend();
+Backend* make_fake_backend();
+
+}  // namespace setrt

@@ -1,0 +1,462 @@
+// Stage kernels for CDNA4 (gfx950), wave64.  No MFMA: nothing here is a dense
+// contraction.  Image stages stage their tile plus halo in LDS; reductions use
+// wave shuffles and LDS in a fixed order, so every result depends only on the
+// job's input and size (bit-identical whatever stream, slot or neighbour ran
+// beside it); the histogram uses LDS atomics on per-wave private bins.
+//
+// Every chain ends in a kernel whose last-arriving block (an agent-scope
+// counter) combines the per-block partials in block order, resets its
+// counters for the slot's next job, checks the slot's canaries and publishes
+// the output header.
+#include "kernels.hpp"
+
+namespace setrt {
+
+// ------------------------------------------------------------------ helpers
+__device__ inline void write_slot_hdr(DevSlotHdr* hdr, const JobScalars& js) {
+  hdr->job_id = js.job_id;
+  hdr->seq = js.seq;
+  hdr->user_tag = js.user_tag;
+  hdr->worker = js.worker;
+  hdr->slot = js.slot;
+}
+
+// One thread; the caller has acquired everything the job wrote.
+__device__ inline void publish_out(const SlotConst& sc, bool extra_ok) {
+  const DevSlotHdr* h = sc.hdr;
+  set_out_header* o = sc.outh;
+  const bool canaries = (h->canary_head == sc.canary_head) && (*sc.tail == sc.canary_tail);
+  o->job_id = h->job_id;
+  o->seq = h->seq;
+  o->worker = h->worker;
+  o->slot = h->slot;
+  o->user_tag = h->user_tag;
+  o->canary_ok = canaries ? 1u : 0u;
+  o->reserved[0] = 0;
+  o->reserved[1] = 0;
+  o->reserved[2] = 0;
+  o->magic = extra_ok ? SET_OUT_MAGIC : 0xBAD0BAD0u;
+}
+
+// Returns true in every thread of the block that arrives last.  All global
+// writes the block made before the call are released (agent scope) and, in
+// the last block, every other block's writes are acquired.
+__device__ inline bool last_block_arrive(uint32_t* counter, unsigned nblocks) {
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (prev == nblocks - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = s_last != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+__device__ inline float wave_sum_f32(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block sums in a fixed order: lane 0 of each wave, then waves 0..3 pairwise.
+// Every thread returns the same value.
+__device__ inline float block_sum_f32(float v, float* s4) {
+  v = wave_sum_f32(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) s4[wave] = v;
+  __syncthreads();
+  return (s4[0] + s4[1]) + (s4[2] + s4[3]);
+}
+__device__ inline uint32_t block_sum_u32(uint32_t v, uint32_t* s4) {
+  v = wave_sum_u32(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) s4[wave] = v;
+  __syncthreads();
+  return (s4[0] + s4[1]) + (s4[2] + s4[3]);
+}
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// ------------------------------------------------------------------ 3x3 box sum (zero padded), uint8 -> uint16
+// Output tile kBoxTW x kBoxTH, input tile + 1-pixel halo staged in LDS.
+__global__ __launch_bounds__(kBlock) void k_box3_u8_u16(BoxArgs a) {
+  constexpr int LW = kBoxTW + 2, LH = kBoxTH + 2;
+  __shared__ uint8_t tile[LH][LW + 2];
+  const int x0 = blockIdx.x * kBoxTW, y0 = blockIdx.y * kBoxTH;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
+  for (int i = threadIdx.x; i < LH * LW; i += kBlock) {
+    const int r = i / LW, c = i - r * LW;
+    const int gy = y0 + r - 1, gx = x0 + c - 1;
+    tile[r][c] = (gy >= 0 && gy < a.h && gx >= 0 && gx < a.w) ? a.in[(size_t)gy * a.w + gx] : (uint8_t)0;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int y = y0 + ty;
+  if (y >= a.h) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int lx = tx * 4 + k, x = x0 + lx;
+    if (x < a.w) {
+      unsigned s = 0;
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) s += tile[ty + dy][lx + dx];
+      a.S[(size_t)y * a.w + x] = (uint16_t)s;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ floor(s / 9), uint16 -> uint8
+__global__ __launch_bounds__(kBlock) void k_div9_u16_u8(Div9Args a) {
+  const int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kDivPerThread;
+  if (i0 + kDivPerThread <= a.npix) {
+    const uint4 v = *reinterpret_cast<const uint4*>(a.S + i0);  // 8 x uint16, 16-byte aligned
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    uint32_t o[2] = {0u, 0u};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t lo = (w[k] & 0xFFFFu) / 9u, hi = (w[k] >> 16) / 9u;
+      o[k >> 1] |= (lo | (hi << 8)) << (16 * (k & 1));
+    }
+    *reinterpret_cast<uint2*>(a.Q + i0) = make_uint2(o[0], o[1]);
+  } else {
+    for (int64_t i = i0; i < a.npix; ++i) a.Q[i] = (uint8_t)(a.S[i] / 9u);
+  }
+}
+
+// ------------------------------------------------------------------ 256-bin histogram of uint8
+// Per-wave private LDS bins (4 x 256) take the LDS atomics; the block's sum of
+// them goes to partials[block]; the last block adds the partials in block
+// order (integer, so exact) into the output payload.
+__global__ __launch_bounds__(kBlock) void k_hist256_u8(HistArgs a) {
+  __shared__ uint32_t wh[4][256];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  for (int i = tid; i < 4 * 256; i += kBlock) (&wh[0][0])[i] = 0u;
+  __syncthreads();
+  const int64_t base = ((int64_t)blockIdx.x * kBlock + tid) * kHistPerThread;
+  if (base + kHistPerThread <= a.npix) {
+    const uint4 v = *reinterpret_cast<const uint4*>(a.Q + base);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) atomicAdd(&wh[wave][(w[k] >> (8 * b)) & 255u], 1u);
+  } else {
+    for (int64_t i = base; i < a.npix; ++i) atomicAdd(&wh[wave][a.Q[i]], 1u);
+  }
+  __syncthreads();
+  a.partials[(size_t)blockIdx.x * 256 + tid] = wh[0][tid] + wh[1][tid] + wh[2][tid] + wh[3][tid];
+  if (last_block_arrive(a.counter, gridDim.x)) {
+    uint32_t s = 0;
+    for (unsigned b = 0; b < gridDim.x; ++b) s += a.partials[(size_t)b * 256 + tid];
+    a.H[tid] = s;
+    if (tid == 0) {
+      *a.counter = 0u;
+      publish_out(a.sc, true);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ separable 5-tap Gaussian, replicated borders
+// Input tile (kGaussTH+4) x (kGaussTW+4) in LDS, horizontal pass into a
+// second LDS tile (kGaussTH+4) x kGaussTW, vertical pass to global.
+__global__ __launch_bounds__(kBlock) void k_gauss5_f32(GaussArgs a) {
+  constexpr int IW = kGaussTW + 4, IH = kGaussTH + 4;
+  __shared__ float tin[IH][IW + 1];
+  __shared__ float tmid[IH][kGaussTW + 1];
+  const int x0 = blockIdx.x * kGaussTW, y0 = blockIdx.y * kGaussTH;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
+  const int wm = a.w - 1, hm = a.h - 1;
+  for (int i = threadIdx.x; i < IH * IW; i += kBlock) {
+    const int r = i / IW, c = i - r * IW;
+    const int gy = clampi(y0 + r - 2, 0, hm), gx = clampi(x0 + c - 2, 0, wm);
+    tin[r][c] = a.in[(size_t)gy * a.w + gx];
+  }
+  __syncthreads();
+  const float g0 = a.g0, g1 = a.g1, g2 = a.g2;
+  for (int i = threadIdx.x; i < IH * kGaussTW; i += kBlock) {
+    const int r = i / kGaussTW, c = i - r * kGaussTW;
+    float acc = g0 * tin[r][c];
+    acc = fmaf(g1, tin[r][c + 1], acc);
+    acc = fmaf(g2, tin[r][c + 2], acc);
+    acc = fmaf(g1, tin[r][c + 3], acc);
+    acc = fmaf(g0, tin[r][c + 4], acc);
+    tmid[r][c] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kGaussTH * kGaussTW; i += kBlock) {
+    const int r = i / kGaussTW, c = i - r * kGaussTW;
+    const int y = y0 + r, x = x0 + c;
+    if (y < a.h && x < a.w) {
+      float acc = g0 * tmid[r][c];
+      acc = fmaf(g1, tmid[r + 1][c], acc);
+      acc = fmaf(g2, tmid[r + 2][c], acc);
+      acc = fmaf(g1, tmid[r + 3][c], acc);
+      acc = fmaf(g0, tmid[r + 4][c], acc);
+      a.out[(size_t)y * a.w + x] = acc;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ Sobel magnitude + threshold + count/sum
+// gx = (right column) - (left column) with weights 1,2,1; gy = (row below) -
+// (row above); mag = sqrt(gx^2 + gy^2); mask = mag > thr.  Per-block count and
+// sum go to partials; the last block combines them in block order.
+__global__ __launch_bounds__(kBlock) void k_sobel_thresh_f32(SobelArgs a) {
+  constexpr int IW = kSobelTW + 2, IH = kSobelTH + 2;
+  __shared__ float t[IH][IW + 1];
+  __shared__ float s4f[4];
+  __shared__ uint32_t s4u[4];
+  const int x0 = blockIdx.x * kSobelTW, y0 = blockIdx.y * kSobelTH;
+  const int wm = a.w - 1, hm = a.h - 1;
+  for (int i = threadIdx.x; i < IH * IW; i += kBlock) {
+    const int r = i / IW, c = i - r * IW;
+    const int gy = clampi(y0 + r - 1, 0, hm), gx = clampi(x0 + c - 1, 0, wm);
+    t[r][c] = a.blur[(size_t)gy * a.w + gx];
+  }
+  __syncthreads();
+  float sum = 0.f;
+  uint32_t cnt = 0;
+  for (int i = threadIdx.x; i < kSobelTH * kSobelTW; i += kBlock) {
+    const int r = i / kSobelTW, c = i - r * kSobelTW;
+    const int y = y0 + r, x = x0 + c;
+    if (y < a.h && x < a.w) {
+      const float p00 = t[r][c], p01 = t[r][c + 1], p02 = t[r][c + 2];
+      const float p10 = t[r + 1][c], p12 = t[r + 1][c + 2];
+      const float p20 = t[r + 2][c], p21 = t[r + 2][c + 1], p22 = t[r + 2][c + 2];
+      const float gx = (p02 + 2.f * p12 + p22) - (p00 + 2.f * p10 + p20);
+      const float gy = (p20 + 2.f * p21 + p22) - (p00 + 2.f * p01 + p02);
+      const float mag = sqrtf(gx * gx + gy * gy);
+      const uint32_t on = mag > a.thr ? 1u : 0u;
+      a.mask[(size_t)y * a.w + x] = (uint8_t)on;
+      cnt += on;
+      sum += mag;
+    }
+  }
+  const unsigned nb = gridDim.x * gridDim.y;
+  const unsigned b = blockIdx.y * gridDim.x + blockIdx.x;
+  const float bs = block_sum_f32(sum, s4f);
+  const uint32_t bc = block_sum_u32(cnt, s4u);
+  if (threadIdx.x == 0) {
+    a.psum[b] = bs;
+    a.pcount[b] = bc;
+  }
+  if (last_block_arrive(a.counter, nb)) {
+    float s = 0.f;
+    uint32_t c = 0;
+    for (unsigned k = threadIdx.x; k < nb; k += kBlock) {
+      s += a.psum[k];
+      c += a.pcount[k];
+    }
+    s = block_sum_f32(s, s4f);
+    c = block_sum_u32(c, s4u);
+    if (threadIdx.x == 0) {
+      *a.out_count = c;
+      *a.out_sum = s;
+      *a.counter = 0u;
+      publish_out(a.sc, true);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ vector job: S = sum tanh(a*x + y)
+// Block b reduces elements [b*C, min((b+1)*C, n)), C = vec_chunk(n, grid),
+// with 16-byte loads when both windows are 4-element aligned.
+__global__ __launch_bounds__(kBlock) void k_saxpy_tanh_sum_f32(VecArgs a) {
+  __shared__ float s4f[4];
+  const JobScalars js = a.js;
+  if (blockIdx.x == 0 && threadIdx.x == 0) write_slot_hdr(a.sc.hdr, js);
+  const uint64_t n = js.n;
+  const unsigned G = gridDim.x;
+  const uint64_t C = vec_chunk(n, G);
+  const uint64_t beg = (uint64_t)blockIdx.x * C;
+  const uint64_t end = beg + C < n ? beg + C : n;
+  const float* __restrict__ x = a.x + js.x_off;
+  const float* __restrict__ y = a.y + js.y_off;
+  const float av = js.a;
+  float acc = 0.f;
+  if (beg < end) {
+    if (((js.x_off | js.y_off) & 3u) == 0) {
+      const uint64_t vend = beg + ((end - beg) & ~3ull);
+      for (uint64_t i = beg + 4ull * threadIdx.x; i < vend; i += 4ull * kBlock) {
+        const float4 xv = *reinterpret_cast<const float4*>(x + i);
+        const float4 yv = *reinterpret_cast<const float4*>(y + i);
+        acc += tanhf(fmaf(av, xv.x, yv.x));
+        acc += tanhf(fmaf(av, xv.y, yv.y));
+        acc += tanhf(fmaf(av, xv.z, yv.z));
+        acc += tanhf(fmaf(av, xv.w, yv.w));
+      }
+      if (threadIdx.x == 0)
+        for (uint64_t i = vend; i < end; ++i) acc += tanhf(fmaf(av, x[i], y[i]));
+    } else {
+      for (uint64_t i = beg + threadIdx.x; i < end; i += kBlock) acc += tanhf(fmaf(av, x[i], y[i]));
+    }
+  }
+  const float bs = block_sum_f32(acc, s4f);
+  if (threadIdx.x == 0) a.partials[blockIdx.x] = bs;
+  if (last_block_arrive(a.counter, G)) {
+    float s = 0.f;
+    for (unsigned k = threadIdx.x; k < G; k += kBlock) s += a.partials[k];
+    s = block_sum_f32(s, s4f);
+    if (threadIdx.x == 0) {
+      *a.out_sum = s;
+      *a.counter = 0u;
+      publish_out(a.sc, true);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ inclusive scan int32 -> int64
+// Single pass with decoupled look-back: tiles are numbered in arrival order
+// (an atomic counter), so every tile a block waits on belongs to a block that
+// is already running and publishes its tile sum before looking back itself.
+// Tile state words carry the job's epoch (its slot sequence number), so
+// states left by the slot's previous job are never mistaken for this job's.
+namespace {
+constexpr uint32_t kTileAgg = 1u, kTileInc = 2u;
+constexpr uint32_t kScanSpinLimit = 1u << 20;
+}  // namespace
+
+__global__ __launch_bounds__(kBlock) void k_scan_i32_i64(ScanArgs a) {
+  __shared__ uint32_t s_tile;
+  __shared__ int64_t s_wave[4];
+  __shared__ int64_t s_excl;
+  const JobScalars js = a.js;
+  const uint64_t n = js.n;
+  const unsigned ntiles = gridDim.x;
+  const uint32_t epoch = (uint32_t)(js.seq & 0x3FFFFFFFull);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_tile = __hip_atomic_fetch_add(a.tile_counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const unsigned t = s_tile;
+  if (t == 0 && tid == 0) write_slot_hdr(a.sc.hdr, js);
+
+  const uint64_t base = (uint64_t)t * kScanTile + (uint64_t)tid * kScanItems;
+  int64_t v[kScanItems];
+  if (base + kScanItems <= n) {
+    const int4 p0 = *reinterpret_cast<const int4*>(a.in + base);
+    const int4 p1 = *reinterpret_cast<const int4*>(a.in + base + 4);
+    v[0] = p0.x; v[1] = p0.y; v[2] = p0.z; v[3] = p0.w;
+    v[4] = p1.x; v[5] = p1.y; v[6] = p1.z; v[7] = p1.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? (int64_t)a.in[base + k] : 0;
+  }
+#pragma unroll
+  for (int k = 1; k < kScanItems; ++k) v[k] += v[k - 1];
+  const int64_t tsum = v[kScanItems - 1];
+  int64_t xs = tsum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t yv = __shfl_up(xs, off, 64);
+    if (lane >= off) xs += yv;
+  }
+  if (lane == 63) s_wave[wave] = xs;
+  __syncthreads();
+  int64_t wave_excl = 0;
+  for (int i = 0; i < wave; ++i) wave_excl += s_wave[i];
+  const int64_t block_total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+  const int64_t thread_excl = wave_excl + xs - tsum;
+
+  if (wave == 0) {
+    int64_t excl = 0;
+    if (t == 0) {
+      if (lane == 0) {
+        __hip_atomic_store(&a.tile_inc[0], block_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.tile_status[0], (epoch << 2) | kTileInc, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    } else {
+      if (lane == 0) {
+        __hip_atomic_store(&a.tile_agg[t], block_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.tile_status[t], (epoch << 2) | kTileAgg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      int64_t j = (int64_t)t - 1;
+      uint32_t spins = 0;
+      bool failed = false;
+      while (true) {
+        const int64_t idx = j - lane;
+        uint32_t st = kTileInc;
+        int64_t val = 0;
+        if (idx >= 0) {
+          const uint32_t w = __hip_atomic_load(&a.tile_status[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          st = ((w >> 2) == epoch) ? (w & 3u) : 0u;
+          if (st == kTileInc)
+            val = __hip_atomic_load(&a.tile_inc[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          else if (st == kTileAgg)
+            val = __hip_atomic_load(&a.tile_agg[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const uint64_t inc = __ballot(st == kTileInc);
+        const uint64_t inv = __ballot(st == 0u);
+        const int first = inc ? (__ffsll((unsigned long long)inc) - 1) : 64;
+        const uint64_t upto = (first >= 63) ? ~0ull : ((2ull << first) - 1ull);
+        if (inv & upto) {
+          if (++spins > kScanSpinLimit) {
+            failed = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        int64_t contrib = (lane <= first) ? val : 0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off, 64);
+        excl += contrib;
+        if (first < 64) break;
+        j -= 64;
+      }
+      if (failed && lane == 0) __hip_atomic_store(a.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0) {
+        __hip_atomic_store(&a.tile_inc[t], excl + block_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.tile_status[t], (epoch << 2) | kTileInc, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    if (lane == 0) s_excl = excl;
+  }
+  __syncthreads();
+  const int64_t off0 = s_excl + thread_excl;
+  if (!a.low32) {
+    int64_t* o = reinterpret_cast<int64_t*>(a.out);
+    if (base + kScanItems <= n) {
+      longlong2* o2 = reinterpret_cast<longlong2*>(o + base);
+#pragma unroll
+      for (int k = 0; k < kScanItems / 2; ++k) o2[k] = make_longlong2(off0 + v[2 * k], off0 + v[2 * k + 1]);
+    } else {
+      for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) o[base + k] = off0 + v[k];
+    }
+  } else {
+    uint32_t* o = reinterpret_cast<uint32_t*>(a.out);
+    if (base + kScanItems <= n) {
+      uint4* o4 = reinterpret_cast<uint4*>(o + base);
+      o4[0] = make_uint4((uint32_t)(off0 + v[0]), (uint32_t)(off0 + v[1]), (uint32_t)(off0 + v[2]),
+                         (uint32_t)(off0 + v[3]));
+      o4[1] = make_uint4((uint32_t)(off0 + v[4]), (uint32_t)(off0 + v[5]), (uint32_t)(off0 + v[6]),
+                         (uint32_t)(off0 + v[7]));
+    } else {
+      for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) o[base + k] = (uint32_t)(off0 + v[k]);
+    }
+  }
+  if (last_block_arrive(a.done_counter, ntiles)) {
+    if (tid == 0) {
+      const bool ok = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+      *a.tile_counter = 0u;
+      *a.done_counter = 0u;
+      *a.err = 0u;
+      publish_out(a.sc, ok);
+    }
+  }
+}
+
+}  // namespace setrt

@@ -1,0 +1,223 @@
+// Slot layouts, per-job copy sizes and argument validation of every pipeline.
+// Host-only, no HIP headers.
+#include <cstdio>
+#include <string>
+
+#include "internal.hpp"
+#include "tiles.hpp"
+
+namespace setrt {
+
+namespace {
+constexpr uint64_t kAlign = 256;
+inline uint64_t up(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) / a * a; }
+}  // namespace
+
+int pipeline_validate(const set_job_template& t, std::string* why) {
+  auto bad = [&](const char* m) {
+    if (why) *why = m;
+    return SET_EINVAL;
+  };
+  switch (t.pipeline) {
+    case SET_PIPE_BOX_HIST_U8:
+    case SET_PIPE_GAUSS_SOBEL_F32:
+      if (t.width < 1 || t.height < 1) return bad("image templates need width >= 1 and height >= 1");
+      if ((uint64_t)t.width * t.height > (1ull << 28)) return bad("image larger than 2^28 pixels");
+      if (t.width > (1u << 20) || t.height > (1u << 20)) return bad("image side larger than 2^20");
+      break;
+    case SET_PIPE_SAXPY_TANH_SUM_F32:
+      if (t.max_n < 1 || t.max_n > (1ull << 32)) return bad("vector template needs 1 <= max_n <= 2^32");
+      if (t.dev_x_pool == nullptr || t.dev_y_pool == nullptr || t.pool_len < 1)
+        return bad("vector template needs device x/y pools");
+      break;
+    case SET_PIPE_SCAN_I32_I64:
+      if (t.max_n < 1 || t.max_n > (1ull << 31)) return bad("scan template needs 1 <= max_n <= 2^31");
+      break;
+    default:
+      return bad("unknown pipeline");
+  }
+  if (t.flags & ~(uint32_t)(SET_TF_DEBUG | SET_TF_SCAN_LOW32)) return bad("unknown template flags");
+  return SET_OK;
+}
+
+static SlotLayout layout_of(const set_job_template& t) {
+  SlotLayout L{};
+  const bool dbg = (t.flags & SET_TF_DEBUG) != 0;
+  uint64_t off = 0;
+  L.hdr = 0;
+  off = up(sizeof(DevSlotHdr));
+  switch (t.pipeline) {
+    case SET_PIPE_BOX_HIST_U8: {
+      const uint64_t npix = (uint64_t)t.width * t.height;
+      L.in = off;
+      L.in_cap = npix;
+      off = up(off + npix);
+      L.out = off;
+      uint64_t o = 64 + 1024;  // header + uint32 histogram
+      if (dbg) {
+        const uint64_t s_off = up(o, 64);
+        const uint64_t q_off = up(s_off + 2 * npix, 64);
+        L.b1 = L.out + s_off;
+        L.b2 = L.out + q_off;
+        o = q_off + npix;
+      }
+      L.out_cap = o;
+      off = up(off + o);
+      if (!dbg) {
+        L.b1 = off;
+        off = up(off + 2 * npix);
+        L.b2 = off;
+        off = up(off + npix);
+      }
+      L.scratch = off;
+      L.scratch_bytes = up((uint64_t)hist_blocks((int64_t)npix) * 256 * 4) + kAlign;  // partials + counter
+      off = up(off + L.scratch_bytes);
+      break;
+    }
+    case SET_PIPE_GAUSS_SOBEL_F32: {
+      const uint64_t npix = (uint64_t)t.width * t.height;
+      L.in = off;
+      L.in_cap = 4 * npix;
+      off = up(off + 4 * npix);
+      L.out = off;
+      uint64_t o = 64 + 8;  // header + {count, sum}
+      if (dbg) {
+        const uint64_t m_off = 128;
+        const uint64_t b_off = up(m_off + npix, 64);
+        L.b2 = L.out + m_off;  // mask
+        L.b1 = L.out + b_off;  // blur
+        o = b_off + 4 * npix;
+      }
+      L.out_cap = o;
+      off = up(off + o);
+      if (!dbg) {
+        L.b1 = off;
+        off = up(off + 4 * npix);
+        L.b2 = off;
+        off = up(off + npix);
+      }
+      const Grid3 g = sobel_grid((int)t.height, (int)t.width);
+      const uint64_t nb = (uint64_t)g.x * g.y;
+      L.scratch = off;
+      L.scratch_bytes = up(nb * 4) + up(nb * 4) + kAlign;  // pcount, psum, counter
+      off = up(off + L.scratch_bytes);
+      break;
+    }
+    case SET_PIPE_SAXPY_TANH_SUM_F32: {
+      L.in = off;
+      L.in_cap = 0;
+      L.out = off;
+      L.out_cap = 64 + 4;
+      off = up(off + L.out_cap);
+      L.scratch = off;
+      L.scratch_bytes = up((uint64_t)kVecGridCap * 4) + kAlign;  // partials + counter
+      off = up(off + L.scratch_bytes);
+      break;
+    }
+    case SET_PIPE_SCAN_I32_I64: {
+      const uint64_t n = t.max_n;
+      const uint64_t tiles = scan_tiles(n);
+      L.in = off;
+      L.in_cap = 4 * n;
+      off = up(off + 4 * n);
+      L.out = off;
+      L.out_cap = 64 + ((t.flags & SET_TF_SCAN_LOW32) ? 4 * n : 8 * n);
+      off = up(off + L.out_cap);
+      L.scratch = off;
+      // status[tiles] u32, agg[tiles] i64, inc[tiles] i64, tile counter, done counter, err
+      L.scratch_bytes = up(tiles * 4) + up(tiles * 8) + up(tiles * 8) + kAlign;
+      off = up(off + L.scratch_bytes);
+      break;
+    }
+    default:
+      break;
+  }
+  L.tail = off;
+  off = up(off + 8);
+  L.total = off;
+  return L;
+}
+
+SlotLayout slot_layout(const set_job_template& t) { return layout_of(t); }
+
+uint64_t pipeline_in_bytes(const set_job_template& t, uint64_t n) {
+  switch (t.pipeline) {
+    case SET_PIPE_BOX_HIST_U8:
+      return (uint64_t)t.width * t.height;
+    case SET_PIPE_GAUSS_SOBEL_F32:
+      return 4ull * t.width * t.height;
+    case SET_PIPE_SAXPY_TANH_SUM_F32:
+      return 0;
+    case SET_PIPE_SCAN_I32_I64:
+      return 4ull * (n ? n : t.max_n);
+  }
+  return 0;
+}
+
+uint64_t pipeline_out_bytes(const set_job_template& t, uint64_t n) {
+  switch (t.pipeline) {
+    case SET_PIPE_BOX_HIST_U8:
+    case SET_PIPE_GAUSS_SOBEL_F32:
+      return layout_of(t).out_cap;
+    case SET_PIPE_SAXPY_TANH_SUM_F32:
+      return 64 + 4;
+    case SET_PIPE_SCAN_I32_I64:
+      return 64 + ((t.flags & SET_TF_SCAN_LOW32) ? 4ull : 8ull) * (n ? n : t.max_n);
+  }
+  return 0;
+}
+
+int pipeline_validate_job(const set_job_template& t, const set_job_args& a, std::string* why) {
+  auto bad = [&](const char* m) {
+    if (why) *why = m;
+    return SET_EINVAL;
+  };
+  uint64_t n = a.n;
+  if (t.pipeline == SET_PIPE_SAXPY_TANH_SUM_F32) {
+    if (n < 1 || n > t.max_n) return bad("vector job needs 1 <= n <= template max_n");
+    if (a.x_off > t.pool_len || n > t.pool_len - a.x_off) return bad("x window outside the pool");
+    if (a.y_off > t.pool_len || n > t.pool_len - a.y_off) return bad("y window outside the pool");
+  }
+  if (t.pipeline == SET_PIPE_SCAN_I32_I64) {
+    if (n == 0) n = t.max_n;
+    if (n > t.max_n) return bad("scan job n exceeds template max_n");
+  }
+  const uint64_t ib = pipeline_in_bytes(t, n), ob = pipeline_out_bytes(t, n);
+  if (ib > 0 && (a.host_in == nullptr || a.in_bytes != ib)) return bad("host_in missing or in_bytes mismatch");
+  if (a.host_out == nullptr || a.out_bytes < ob) return bad("host_out missing or out_bytes too small");
+  return SET_OK;
+}
+
+int pipeline_sizes(const set_job_template& t, TemplateSizes* out) {
+  std::string why;
+  if (pipeline_validate(t, &why) != SET_OK) return SET_EINVAL;
+  const SlotLayout L = layout_of(t);
+  TemplateSizes s{};
+  s.slot_bytes = L.total;
+  auto stage = [&](const char* name, uint64_t bytes) {
+    snprintf(s.stage_names[s.num_stages], sizeof(s.stage_names[0]), "%s", name);
+    s.stage_bytes[s.num_stages++] = bytes;
+  };
+  const uint64_t npix = (uint64_t)t.width * t.height;
+  switch (t.pipeline) {
+    case SET_PIPE_BOX_HIST_U8:
+      stage("box3_u8_u16", npix + 2 * npix);
+      stage("div9_u16_u8", 2 * npix + npix);
+      stage("hist256_u8", npix + 1024);
+      break;
+    case SET_PIPE_GAUSS_SOBEL_F32:
+      stage("gauss5_f32", 4 * npix + 4 * npix);
+      stage("sobel_thresh_f32", 4 * npix + npix + 8);
+      break;
+    case SET_PIPE_SAXPY_TANH_SUM_F32:
+      stage("saxpy_tanh_sum_f32", 8 * t.max_n + 4);
+      break;
+    case SET_PIPE_SCAN_I32_I64:
+      stage("scan_i32_i64", 4 * t.max_n + ((t.flags & SET_TF_SCAN_LOW32) ? 4 : 8) * t.max_n);
+      break;
+  }
+  *out = s;
+  return SET_OK;
+}
+
+}  // namespace setrt

@@ -1,0 +1,77 @@
+// Tile geometry and grid sizes of the stage kernels.  Plain C++ so host-only
+// code (slot layout, scheduler, fake backend) shares it without HIP headers.
+#pragma once
+
+#include <cstdint>
+
+#if defined(__HIPCC__)
+#define SETRT_HD __host__ __device__
+#else
+#define SETRT_HD
+#endif
+
+namespace setrt {
+
+constexpr int kBlock = 256;
+constexpr int kBoxTW = 64, kBoxTH = 16;       // 3x3 box: output tile
+constexpr int kDivPerThread = 8;              // floor(s/9): pixels per thread
+constexpr int kHistPerThread = 16;            // histogram: pixels per thread
+constexpr int kGaussTW = 64, kGaussTH = 16;   // separable Gaussian: output tile
+constexpr int kSobelTW = 64, kSobelTH = 16;   // Sobel: output tile
+constexpr int kVecChunk = 2048;               // vector job: elements per block (multiple of 4*kBlock)
+constexpr int kVecGridCap = 2048;             // vector job: most blocks per job
+constexpr int kScanItems = 8;                 // scan: items per thread
+constexpr int kScanTile = kBlock * kScanItems;
+
+struct Grid3 {
+  unsigned x, y, z;
+};
+
+inline Grid3 box_grid(int h, int w) {
+  return {(unsigned)((w + kBoxTW - 1) / kBoxTW), (unsigned)((h + kBoxTH - 1) / kBoxTH), 1u};
+}
+inline unsigned div9_blocks(int64_t npix) {
+  return (unsigned)((npix + (int64_t)kBlock * kDivPerThread - 1) / ((int64_t)kBlock * kDivPerThread));
+}
+inline unsigned hist_blocks(int64_t npix) {
+  return (unsigned)((npix + (int64_t)kBlock * kHistPerThread - 1) / ((int64_t)kBlock * kHistPerThread));
+}
+inline Grid3 gauss_grid(int h, int w) {
+  return {(unsigned)((w + kGaussTW - 1) / kGaussTW), (unsigned)((h + kGaussTH - 1) / kGaussTH), 1u};
+}
+inline Grid3 sobel_grid(int h, int w) {
+  return {(unsigned)((w + kSobelTW - 1) / kSobelTW), (unsigned)((h + kSobelTH - 1) / kSobelTH), 1u};
+}
+// Vector job: blocks for length n.  Deterministic in n, so the reduction
+// order of a job depends only on its length.
+SETRT_HD inline unsigned vec_blocks(uint64_t n) {
+  uint64_t b = (n + kVecChunk - 1) / kVecChunk;
+  if (b < 1) b = 1;
+  if (b > (uint64_t)kVecGridCap) b = kVecGridCap;
+  return (unsigned)b;
+}
+// Elements per block for length n over g blocks (a multiple of 4*kBlock).
+SETRT_HD inline uint64_t vec_chunk(uint64_t n, unsigned g) {
+  uint64_t c = (n + g - 1) / g;
+  const uint64_t q = 4ull * kBlock;
+  return (c + q - 1) / q * q;
+}
+inline unsigned scan_tiles(uint64_t n) { return (unsigned)((n + kScanTile - 1) / kScanTile); }
+
+// Byte layout of one buffer slot of a template (offsets from the slot base,
+// all 256-byte aligned).  In debug templates the intermediate images live
+// inside the output block so the D2H copy returns them.
+struct SlotLayout {
+  uint64_t hdr;        // DevSlotHdr
+  uint64_t in;         // H2D destination
+  uint64_t in_cap;
+  uint64_t out;        // output block: set_out_header + payload (+ debug images)
+  uint64_t out_cap;
+  uint64_t b1, b2;     // intermediates (box: S, Q; gauss: blur, mask)
+  uint64_t scratch;    // partials, counters, tile states
+  uint64_t scratch_bytes;
+  uint64_t tail;       // tail canary
+  uint64_t total;
+};
+
+}  // namespace setrt

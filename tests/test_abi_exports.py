@@ -1,0 +1,56 @@
+"""The C-ABI library loads and exports every symbol include/set.h declares (no compute)."""
+import ctypes
+import os
+import re
+
+from paper_2606_05495_amd import _abi as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "set.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(set_[a-z_]+)\s*\(", text, re.M)))
+
+
+def test_header_declarations_match_binding():
+    assert _declared() == sorted(A.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = A.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+        assert ctypes.cast(getattr(lib, name), ctypes.c_void_p).value
+
+
+def test_struct_sizes_match_header_layout():
+    assert ctypes.sizeof(A.set_config) == 88
+    assert ctypes.sizeof(A.set_job_args) == 72 == A.JOB_ARGS_DTYPE.itemsize
+    assert ctypes.sizeof(A.set_out_header) == 64 == A.OUT_HEADER_DTYPE.itemsize
+    assert ctypes.sizeof(A.set_job_template) == 80
+    for f, off in (("a", 40), ("worker_hint", 44), ("x_off", 48), ("user_tag", 64)):
+        assert getattr(A.set_job_args, f).offset == off
+
+
+def test_strerror_and_create_errors():
+    assert A.set_strerror(A.SET_EDEVICE) == "SET_EDEVICE"
+    cfg = A.set_config()
+    cfg.abi_version = 999
+    h = ctypes.c_void_p()
+    rc = A.load().set_ctx_create(ctypes.byref(cfg), ctypes.byref(h))
+    assert rc == A.SET_EINVAL and not h.value
+    assert "abi_version" in A.set_last_error(None)
+
+
+def test_footprint_is_host_only():
+    cfg = A.set_config()
+    cfg.abi_version = A.SET_ABI_VERSION
+    cfg.num_workers, cfg.slots_per_worker = 8, 16
+    t = A.set_job_template()
+    t.pipeline = A.SET_PIPE_GAUSS_SOBEL_F32
+    t.width = t.height = 1024
+    slot, total = A.set_template_footprint(cfg, t)
+    # input 4 MiB + blur 4 MiB + mask 1 MiB + small
+    assert 9 * 2 ** 20 <= slot < 9 * 2 ** 20 + 64 * 1024
+    assert total == 128 * slot

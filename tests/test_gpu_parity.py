@@ -1,0 +1,359 @@
+"""GPU parity: every pipeline run through the C ABI on an MI355X against the
+CPU oracle on the same seeded inputs.
+
+Bars: integer stages (box sums, quotients, histogram, scan) bit-exact; the
+float32 Gaussian within 1e-5 of the convolution of |input| (a relative bound
+on the terms summed); Sobel sums within 1e-5 relative; the mask bit-exact
+outside the band |mag - 1| <= 1e-5 and the count within that band; vector sums
+within max(1e-5 |S|, E) with E the float32 error allowance the oracle returns.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_05495_amd import _abi as A
+from paper_2606_05495_amd import synth
+from paper_2606_05495_amd.runtime import Context, out_header, pinned
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _up64(v):
+    return (v + 63) // 64 * 64
+
+
+def _check_header(buf, job_id, tag=None):
+    h = out_header(buf)
+    assert h["magic"] == A.SET_OUT_MAGIC, hex(int(h["magic"]))
+    assert h["canary_ok"] == 1
+    assert h["job_id"] == job_id
+    if tag is not None:
+        assert h["user_tag"] == tag
+    return h
+
+
+# ------------------------------------------------------------------ box / histogram
+def _run_images(mode, pipeline, imgs, in_dtype, workers=4, slots=4, flags=A.SET_TF_DEBUG, **kw):
+    h, w = imgs[0].shape
+    ctx = Context(mode=mode, workers=workers, slots=slots, **kw)
+    tid = ctx.define(pipeline, width=w, height=h, flags=flags)
+    ib, ob = ctx.in_bytes(tid), ctx.out_bytes(tid)
+    stride = _up64(ob)
+    tin, nin = pinned(ib * len(imgs))
+    tout, nout = pinned(stride * len(imgs))
+    nin.view(in_dtype)[:] = np.concatenate([im.ravel() for im in imgs]).view(in_dtype)
+    arr = ctx.job_array(len(imgs))
+    arr["host_in"] = tin.data_ptr() + np.arange(len(imgs), dtype=np.uint64) * ib
+    arr["in_bytes"] = ib
+    arr["host_out"] = tout.data_ptr() + np.arange(len(imgs), dtype=np.uint64) * stride
+    arr["out_bytes"] = ob
+    arr["user_tag"] = 1000 + np.arange(len(imgs))
+    first = ctx.submit_many(tid, arr)
+    ctx.drain()
+    st = ctx.stats()
+    outs = [nout[i * stride:(i + 1) * stride] for i in range(len(imgs))]
+    for i in range(len(imgs)):
+        _check_header(outs[i], first + i, 1000 + i)
+    ctx.close()
+    return outs, st
+
+
+BOX_SHAPES = [(1, 1), (1, 7), (7, 1), (2, 2), (3, 5), (16, 64), (17, 65), (17, 33), (256, 256), (300, 513)]
+
+
+@pytest.mark.parametrize("mode", ["sync", "set"])
+@pytest.mark.parametrize("shape", BOX_SHAPES)
+def test_box_hist_parity(torch_gpu, mode, shape):
+    _say("box_hist", mode, shape)
+    h, w = shape
+    rng = np.random.default_rng(h * 1000 + w)
+    imgs = [rng.integers(0, 256, shape, dtype=np.uint8), np.full(shape, 255, np.uint8),
+            np.zeros(shape, np.uint8), rng.choice(np.array([0, 255], np.uint8), shape)]
+    outs, _ = _run_images(mode, "box_hist", imgs, np.uint8)
+    s_off = _up64(64 + 1024)
+    q_off = _up64(s_off + 2 * h * w)
+    for img, o in zip(imgs, outs):
+        S, Q, H = oracle.box_hist(img)
+        assert np.array_equal(o[64:64 + 1024].view(np.uint32), H)
+        assert np.array_equal(o[s_off:s_off + 2 * h * w].view(np.uint16).reshape(h, w), S)
+        assert np.array_equal(o[q_off:q_off + h * w].reshape(h, w), Q)
+
+
+@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "set"])
+def test_box_hist_workload_64_jobs(torch_gpu, mode):
+    """64 jobs of 256x256 uint8 (uniform, stream key = seed + job id), 4 streams."""
+    _say("box_hist 64 jobs", mode)
+    imgs = [synth.box_image(0, j) for j in range(64)]
+    outs, st = _run_images(mode, "box_hist", imgs, np.uint8, workers=4, slots=4, flags=0)
+    for img, o in zip(imgs, outs):
+        assert np.array_equal(o[64:64 + 1024].view(np.uint32), oracle.box_hist(img)[2])
+    assert st.completed == 64
+
+
+# ------------------------------------------------------------------ Gaussian / Sobel
+def _check_gauss(img, o, exact_mask=True):
+    h, w = img.shape
+    ref = oracle.gauss_sobel(img)
+    absconv = oracle.gauss_sobel(np.abs(img))["blur"]
+    m_off = 128
+    b_off = _up64(128 + h * w)
+    count = int(o[64:68].view(np.uint32)[0])
+    s = float(o[68:72].view(np.float32)[0])
+    mask = o[m_off:m_off + h * w].reshape(h, w)
+    blur = o[b_off:b_off + 4 * h * w].view(np.float32).reshape(h, w)
+    err = np.abs(blur.astype(np.float64) - ref["blur"])
+    assert np.all(err <= 1e-5 * absconv + 1e-30), float((err / (absconv + 1e-30)).max())
+    outside = np.abs(ref["mag"] - 1.0) > oracle.BAND_EPS
+    assert np.array_equal(mask[outside], ref["mask"][outside])
+    assert abs(count - ref["count"]) <= ref["band"]
+    assert abs(s - ref["sum"]) <= 1e-5 * abs(ref["sum"]) + 1e-6, (s, ref["sum"])
+    return ref
+
+
+GAUSS_SHAPES = [(1, 1), (1, 9), (9, 1), (2, 3), (5, 5), (16, 64), (17, 65), (33, 17), (100, 130), (256, 256)]
+
+
+@pytest.mark.parametrize("mode", ["sync", "set"])
+@pytest.mark.parametrize("shape", GAUSS_SHAPES)
+def test_gauss_sobel_parity(torch_gpu, mode, shape):
+    _say("gauss_sobel", mode, shape)
+    h, w = shape
+    imgs = [synth.normal_image(0, k, h, w) for k in range(3)]
+    imgs.append((synth.normal_image(0, 9, h, w) * 4).astype(np.float32))
+    outs, _ = _run_images(mode, "gauss_sobel", imgs, np.float32)
+    for img, o in zip(imgs, outs):
+        _check_gauss(img, o)
+
+
+def test_gauss_sobel_pins_on_gpu(torch_gpu):
+    """Constant image: zero gradient everywhere; impulse: blur = g_i*g_j in float32."""
+    _say("gauss_sobel pins")
+    h, w = 24, 70
+    const = np.full((h, w), 3.25, np.float32)
+    imp = np.zeros((h, w), np.float32)
+    imp[10, 30] = 1.0
+    ramp = (0.25 * np.tile(np.arange(w, dtype=np.float32), (h, 1))).astype(np.float32)
+    outs, _ = _run_images("set", "gauss_sobel", [const, imp, ramp], np.float32)
+    b_off = _up64(128 + h * w)
+    assert int(outs[0][64:68].view(np.uint32)[0]) == 0
+    assert float(outs[0][68:72].view(np.float32)[0]) == 0.0
+    blur = outs[1][b_off:b_off + 4 * h * w].view(np.float32).reshape(h, w)
+    g = oracle.gauss_taps().astype(np.float32)
+    for i in range(5):
+        for j in range(5):
+            assert blur[10 + i - 2, 30 + j - 2] == np.float32(g[i]) * np.float32(g[j])
+    mask = outs[2][128:128 + h * w].reshape(h, w)
+    assert np.all(mask[:, 3:w - 3] == 1)
+
+
+@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "set"])
+def test_gauss_sobel_full_size(torch_gpu, mode):
+    """1024x1024 N(0,1) images from the 61-image pool, 8 workers x 16 slots."""
+    _say("gauss_sobel 1024^2", mode)
+    imgs = [synth.normal_image(0, k) for k in range(6)]
+    outs, st = _run_images(mode, "gauss_sobel", imgs + imgs, np.float32, workers=8, slots=16, flags=0)
+    for k, img in enumerate(imgs + imgs):
+        ref = oracle.gauss_sobel(img, want_images=False)
+        o = outs[k]
+        count = int(o[64:68].view(np.uint32)[0])
+        s = float(o[68:72].view(np.float32)[0])
+        assert abs(count - ref["count"]) <= ref["band"]
+        assert abs(s - ref["sum"]) <= 1e-5 * abs(ref["sum"])
+    # determinism: the same image gives bit-identical results in any slot/stream
+    for k in range(6):
+        assert np.array_equal(outs[k][64:72], outs[k + 6][64:72])
+
+
+# ------------------------------------------------------------------ vector jobs
+@pytest.fixture(scope="module")
+def vec_pools(torch_gpu):
+    L = 1 << 23
+    x = synth.vec_pool(0, "x", L)
+    y = synth.vec_pool(0, "y", L)
+    xd = torch_gpu.from_numpy(x).cuda()
+    yd = torch_gpu.from_numpy(y).cuda()
+    return x, y, xd, yd
+
+
+def _run_vec(mode, pools, ns, offs_x, offs_y, avals, workers=4, slots=8, policy=A.SET_SUBMIT_ROUND_ROBIN):
+    x, y, xd, yd = pools
+    ctx = Context(mode=mode, workers=workers, slots=slots, submit_policy=policy)
+    tid = ctx.define("saxpy_tanh_sum", max_n=int(max(ns)), x_pool=xd, y_pool=yd)
+    k = len(ns)
+    tout, nout = pinned(128 * k)
+    arr = ctx.job_array(k)
+    arr["host_out"] = tout.data_ptr() + np.arange(k, dtype=np.uint64) * 128
+    arr["out_bytes"] = 68
+    arr["n"] = ns
+    arr["a"] = avals
+    arr["x_off"] = offs_x
+    arr["y_off"] = offs_y
+    arr["user_tag"] = np.arange(k)
+    first = ctx.submit_many(tid, arr)
+    ctx.drain()
+    st = ctx.stats()
+    res = []
+    for i in range(k):
+        o = nout[i * 128:(i + 1) * 128]
+        _check_header(o, first + i, i)
+        res.append(float(o[64:68].view(np.float32)[0]))
+    ctx.close()
+    return np.array(res), st
+
+
+@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "set"])
+def test_vector_parity(torch_gpu, vec_pools, mode):
+    _say("vector", mode)
+    x, y = vec_pools[0], vec_pools[1]
+    ns = np.array([1, 2, 3, 4, 5, 1023, 1024, 2047, 2048, 4096, 4097, 65549, 1 << 20, 4194303], np.int64)
+    L = len(x)
+    rng = np.random.default_rng(5)
+    xo = 64 * (rng.integers(0, (L - ns) // 64))
+    yo = 64 * (rng.integers(0, (L - ns) // 64))
+    xo[3] += 1  # misaligned windows take the scalar path
+    yo[5] += 3
+    av = rng.uniform(0.5, 2, len(ns)).astype(np.float32)
+    got, _ = _run_vec(mode, vec_pools, ns, xo, yo, av)
+    for i, n in enumerate(ns):
+        S, E = oracle.saxpy_tanh_sum(x[xo[i]:xo[i] + n], y[yo[i]:yo[i] + n], av[i])
+        assert abs(got[i] - S) <= oracle.vec_tolerance(S, E), (n, got[i], S, E)
+
+
+def test_vector_pins_on_gpu(torch_gpu):
+    """a=16, x=1, y=0 saturates tanh to exactly 1.0f, so S = n exactly; x=y=0 gives 0."""
+    _say("vector pins")
+    import torch
+    L = 1 << 22
+    ones = torch.ones(L, dtype=torch.float32, device="cuda")
+    zeros = torch.zeros(L, dtype=torch.float32, device="cuda")
+    ns = np.array([1, 4096, 4097, 1 << 20, 4194303], np.int64)
+    got, _ = _run_vec("set", (None, None, ones, zeros), ns, np.zeros(5, np.int64), np.zeros(5, np.int64),
+                      np.full(5, 16.0, np.float32))
+    assert np.array_equal(got, ns.astype(np.float32))
+    got0, _ = _run_vec("set", (None, None, zeros, zeros), ns, np.zeros(5, np.int64), np.zeros(5, np.int64),
+                       np.full(5, 1.5, np.float32))
+    assert np.all(got0 == 0.0)
+
+
+def test_vector_workload_sample(torch_gpu, vec_pools):
+    """A sample of the uneven vector workload (n log-uniform in [4096, 4194304)), with stealing."""
+    _say("vector workload sample")
+    x, y = vec_pools[0], vec_pools[1]
+    jobs = synth.vec_jobs(0, 120, pool_len=len(x))
+    got, st = _run_vec("set", vec_pools, jobs["n"], jobs["x_off"], jobs["y_off"], jobs["a"], workers=8, slots=16,
+                       policy=A.SET_SUBMIT_SKEW0)
+    assert st.stolen > 0
+    for i in range(len(got)):
+        n = int(jobs["n"][i])
+        S, E = oracle.saxpy_tanh_sum(x[jobs["x_off"][i]:jobs["x_off"][i] + n],
+                                     y[jobs["y_off"][i]:jobs["y_off"][i] + n], jobs["a"][i])
+        assert abs(got[i] - S) <= oracle.vec_tolerance(S, E)
+    # alone vs in the mix: bit-identical
+    alone, _ = _run_vec("sync", vec_pools, jobs["n"][:10], jobs["x_off"][:10], jobs["y_off"][:10], jobs["a"][:10],
+                        workers=1, slots=1)
+    assert np.array_equal(alone, got[:10])
+
+
+# ------------------------------------------------------------------ scan
+def _run_scan(mode, inputs, max_n, low32=False, workers=4, slots=4):
+    ctx = Context(mode=mode, workers=workers, slots=slots)
+    tid = ctx.define("scan", max_n=max_n, flags=A.SET_TF_SCAN_LOW32 if low32 else 0)
+    k = len(inputs)
+    ib = [4 * len(v) for v in inputs]
+    ob = [ctx.out_bytes(tid, len(v)) for v in inputs]
+    tin, nin = pinned(sum(_up64(v) for v in ib))
+    tout, nout = pinned(sum(_up64(v) for v in ob))
+    arr = ctx.job_array(k)
+    oi = oo = 0
+    offs = []
+    for i, v in enumerate(inputs):
+        nin[oi:oi + ib[i]].view(np.int32)[:] = v
+        arr[i]["host_in"] = tin.data_ptr() + oi
+        arr[i]["in_bytes"] = ib[i]
+        arr[i]["host_out"] = tout.data_ptr() + oo
+        arr[i]["out_bytes"] = ob[i]
+        arr[i]["n"] = len(v)
+        offs.append(oo)
+        oi += _up64(ib[i])
+        oo += _up64(ob[i])
+    first = ctx.submit_many(tid, arr)
+    ctx.drain()
+    res = []
+    for i, v in enumerate(inputs):
+        o = nout[offs[i]:offs[i] + ob[i]]
+        _check_header(o, first + i)
+        res.append(o[64:].view(np.uint32 if low32 else np.int64).copy())
+    ctx.close()
+    return res
+
+
+@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "set"])
+def test_scan_parity(torch_gpu, mode):
+    _say("scan", mode)
+    rng = np.random.default_rng(3)
+    ns = [1, 7, 8, 2047, 2048, 2049, 4096, 100003, 1 << 18]
+    inputs = [rng.integers(-(1 << 20), (1 << 20) + 1, n).astype(np.int32) for n in ns]
+    inputs.append(np.full(50000, np.iinfo(np.int32).max, np.int32))
+    inputs.append(np.full(50000, np.iinfo(np.int32).min, np.int32))
+    res = _run_scan(mode, inputs, max_n=1 << 18)
+    for v, r in zip(inputs, res):
+        assert np.array_equal(r, oracle.scan(v))
+
+
+def test_scan_full_size_and_low32(torch_gpu):
+    """2^21 int32 inputs in [-2^20, 2^20]; the int64 sums reach 2^41."""
+    _say("scan 2^21")
+    inputs = [synth.scan_input(0, k) for k in range(3)] + [np.full(1 << 21, 1 << 20, np.int32)]
+    res = _run_scan("set", inputs, max_n=1 << 21, workers=8, slots=4)
+    for v, r in zip(inputs, res):
+        assert np.array_equal(r, oracle.scan(v))
+    assert res[-1][-1] == 1 << 41
+    res32 = _run_scan("set", inputs[:2], max_n=1 << 21, low32=True)
+    for v, r in zip(inputs[:2], res32):
+        assert np.array_equal(r, (oracle.scan(v) & 0xFFFFFFFF).astype(np.uint32))
+
+
+# ------------------------------------------------------------------ scheduling on the device
+@pytest.mark.parametrize("callback", ["event_chain", "same_stream", "event_poll"])
+def test_set_mode_callbacks_and_steals(torch_gpu, callback):
+    """Skewed submission on the GPU: steals retarget jobs to thieves' slots; results stay exact."""
+    _say("set callbacks", callback)
+    imgs = [synth.box_image(0, j) for j in range(96)]
+    ctx = Context(mode="set", workers=4, slots=4, callback=callback, submit_policy=A.SET_SUBMIT_SKEW0)
+    tid = ctx.define("box_hist", width=256, height=256)
+    ib, ob = ctx.in_bytes(tid), ctx.out_bytes(tid)
+    tin, nin = pinned(ib * 96)
+    tout, nout = pinned(_up64(ob) * 96)
+    nin[:] = np.concatenate([im.ravel() for im in imgs])
+    arr = ctx.job_array(96)
+    arr["host_in"] = tin.data_ptr() + np.arange(96, dtype=np.uint64) * ib
+    arr["in_bytes"] = ib
+    arr["host_out"] = tout.data_ptr() + np.arange(96, dtype=np.uint64) * _up64(ob)
+    arr["out_bytes"] = ob
+    ctx.submit_many(tid, arr)
+    ctx.drain()
+    st = ctx.stats()
+    times = {int(r["job_id"]): r for r in ctx.job_times()}
+    ctx.close()
+    for j in range(96):
+        o = nout[j * _up64(ob):(j + 1) * _up64(ob)]
+        h = _check_header(o, j)
+        assert h["worker"] == times[j]["worker"] and h["slot"] == times[j]["slot"]
+        assert np.array_equal(o[64:64 + 1024].view(np.uint32), oracle.box_hist(imgs[j])[2])
+    assert st.completed == 96
+    assert st.stolen > 0

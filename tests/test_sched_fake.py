@@ -1,0 +1,264 @@
+"""Scheduler invariants (Algorithms 1-3) on the CPU fake backend: threads
+stand in for streams, completions arrive on a separate callback thread.
+
+Checked here without a GPU:
+ (i)   every submitted id completes exactly once; ids are consecutive;
+ (ii)  stealing happens only when enabled, and skewed submission forces it;
+ (iii) a stolen job runs on the thief's slot (its output header says so);
+ (iv)  no slot is used by two jobs at once (fake backend's in-use check +
+       header canary flag);
+ (v)   at most b*k jobs in flight;
+ (vii) set_drain returns only when completed == submitted; timeouts and
+       injected device errors surface as error codes.
+"""
+import os
+import subprocess
+import threading
+
+import numpy as np
+import pytest
+
+from paper_2606_05495_amd import _abi as A
+from paper_2606_05495_amd.runtime import Context, out_header
+
+DUMMY_POOL = (0x1000, 0x2000, 1 << 30)  # never dereferenced by the fake backend
+
+
+def _vec_jobs(ctx, tid, n_jobs, dur_us, tags=None, hints=None):
+    outs = np.zeros((n_jobs, 128), np.uint8)
+    arr = ctx.job_array(n_jobs)
+    arr["host_out"] = outs.ctypes.data + np.arange(n_jobs, dtype=np.uint64) * 128
+    arr["out_bytes"] = 68
+    arr["n"] = dur_us
+    arr["a"] = 1.0
+    arr["user_tag"] = np.arange(n_jobs) if tags is None else tags
+    if hints is not None:
+        arr["worker_hint"] = hints
+    return arr, outs
+
+
+def _headers(outs):
+    return np.stack([out_header(outs[i]) for i in range(len(outs))])
+
+
+def _fake(**kw):
+    kw.setdefault("backend", "fake")
+    return Context(**kw)
+
+
+@pytest.mark.parametrize("b,d", [(1, 2), (4, 8), (8, 16)])
+def test_every_job_completes_once(b, d):
+    with _fake(workers=b, slots=d) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        arr, outs = _vec_jobs(ctx, tid, 500, np.random.default_rng(0).integers(1, 60, 500))
+        first = ctx.submit_many(tid, arr)
+        assert first == 0
+        ctx.drain()
+        st = ctx.stats()
+        assert st.submitted == st.completed == 500 and st.failed == 0
+        h = _headers(outs)
+        assert np.all(h["magic"] == A.SET_OUT_MAGIC)
+        assert np.all(h["canary_ok"] == 1)
+        assert np.array_equal(np.sort(h["job_id"]), np.arange(500))
+        assert np.array_equal(h["user_tag"], np.arange(500))
+        times = ctx.job_times()
+        assert len(times) == 500 and len(set(times["job_id"].tolist())) == 500
+        assert np.all(times["t_done"] >= times["t_launch"]) and np.all(times["t_launch"] >= times["t_submit"])
+        assert st.inflight_high_water <= b * max(1, d // 2)
+        assert sum(st.launches_per_worker[:b]) == 500
+
+
+def test_skewed_submission_forces_steals_and_retargets():
+    with _fake(workers=4, slots=8, submit_policy=A.SET_SUBMIT_SKEW0) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        arr, outs = _vec_jobs(ctx, tid, 400, 200)
+        ctx.submit_many(tid, arr)
+        ctx.drain()
+        st = ctx.stats()
+        assert st.stolen > 0
+        h = _headers(outs)
+        t = ctx.job_times()
+        by_id = {int(r["job_id"]): r for r in t}
+        stolen_ids = [i for i, r in by_id.items() if r["stolen"]]
+        assert len(stolen_ids) == st.stolen
+        # a stolen job ran on its thief (worker != 0) and its header says so
+        for i in stolen_ids:
+            k = int(np.nonzero(h["job_id"] == i)[0][0])
+            assert h["worker"][k] == by_id[i]["worker"] != 0
+            assert h["slot"][k] == by_id[i]["slot"]
+        assert np.all(h["canary_ok"] == 1)
+        assert sum(st.launches_per_worker[1:4]) > 0
+
+
+def test_no_stealing_keeps_jobs_local():
+    with _fake(workers=4, slots=8, submit_policy=A.SET_SUBMIT_SKEW0, stealing=False) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        arr, outs = _vec_jobs(ctx, tid, 100, 50)
+        ctx.submit_many(tid, arr)
+        ctx.drain()
+        st = ctx.stats()
+        assert st.stolen == 0
+        assert np.all(_headers(outs)["worker"] == 0)
+        assert st.launches_per_worker[0] == 100
+
+
+def test_worker_hint_and_local_first():
+    with _fake(workers=3, slots=4) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        arr, outs = _vec_jobs(ctx, tid, 30, 10, hints=np.full(30, 2))
+        ctx.submit_many(tid, arr)
+        ctx.drain()
+        h = _headers(outs)
+        t = ctx.job_times()
+        # jobs that were not stolen ran on the hinted worker
+        for r in t:
+            if not r["stolen"]:
+                assert r["worker"] == 2
+
+
+def test_out_of_order_callbacks_keep_memory_safety():
+    with _fake(workers=4, slots=4, fake_reorder=True) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        arr, outs = _vec_jobs(ctx, tid, 600, np.random.default_rng(1).integers(1, 40, 600))
+        ctx.submit_many(tid, arr)
+        ctx.drain()
+        h = _headers(outs)
+        assert np.all(h["canary_ok"] == 1)
+        # a slot is released only after its job's completion is recorded, so per (worker, slot)
+        # the next launch never precedes the previous job's completion stamp
+        t = ctx.job_times()
+        for key in {(int(r["worker"]), int(r["slot"])) for r in t}:
+            rs = sorted((r for r in t if (r["worker"], r["slot"]) == key), key=lambda r: r["t_launch"])
+            for a, b in zip(rs, rs[1:]):
+                assert b["t_launch"] >= a["t_done"]
+        assert ctx.stats().completed == 600
+
+
+def test_concurrent_submitters_get_unique_consecutive_ids():
+    with _fake(workers=4, slots=8) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        outs = np.zeros((4, 100, 128), np.uint8)
+        ids = [[] for _ in range(4)]
+
+        def producer(p):
+            for i in range(100):
+                ids[p].append(ctx.submit(tid, host_out=outs[p, i].ctypes.data, out_bytes=68, n=5, a=1.0,
+                                         user_tag=p * 1000 + i))
+
+        th = [threading.Thread(target=producer, args=(p,)) for p in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        ctx.drain()
+        all_ids = sorted(sum(ids, []))
+        assert all_ids == list(range(400))
+        for p in range(4):
+            assert ids[p] == sorted(ids[p])
+            for i in range(100):
+                h = out_header(outs[p, i])
+                assert h["job_id"] == ids[p][i] and h["user_tag"] == p * 1000 + i
+
+
+def test_drain_timeout_then_completion():
+    with _fake(workers=1, slots=2) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        arr, outs = _vec_jobs(ctx, tid, 3, 300000)  # 0.3 s each
+        ctx.submit_many(tid, arr)
+        with pytest.raises(A.SetError) as e:
+            ctx.drain(timeout_ns=1_000_000)
+        assert e.value.code == A.SET_ETIMEOUT
+        ctx.drain()
+        assert ctx.stats().completed == 3
+
+
+def test_nonblocking_submit_reports_full_staging():
+    with _fake(workers=1, slots=2, staging=4) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        outs = np.zeros((64, 128), np.uint8)
+        got = [ctx.submit(tid, host_out=outs[i].ctypes.data, out_bytes=68, n=20000, a=1.0, flags=A.SET_NONBLOCK)
+               for i in range(64)]
+        assert -1 in got  # SET_EAGAIN surfaced as -1
+        accepted = [g for g in got if g >= 0]
+        assert accepted == list(range(len(accepted)))
+        ctx.drain()
+        assert ctx.stats().completed == len(accepted)
+
+
+def test_injected_device_error_latches_context():
+    with _fake(workers=2, slots=4, fake_fail_after=5) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        arr, outs = _vec_jobs(ctx, tid, 40, 100)
+        try:
+            ctx.submit_many(tid, arr)
+        except A.SetError as e:
+            assert e.code == A.SET_EDEVICE
+        with pytest.raises(A.SetError) as e:
+            ctx.drain()
+        assert e.value.code == A.SET_EDEVICE
+        st = ctx.stats()
+        assert st.completed == st.submitted and st.failed >= 1
+        assert "injected" in A.set_last_error(ctx.h)
+        with pytest.raises(A.SetError) as e2:
+            ctx.submit(tid, host_out=outs[0].ctypes.data, out_bytes=68, n=5, a=1.0)
+        assert e2.value.code == A.SET_EDEVICE
+
+
+def test_memory_budget_bounds_bound_slots():
+    with _fake(workers=4, slots=8) as ctx0:
+        tid0 = ctx0.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        fp = A.set_template_footprint(ctx0.cfg, ctx0.templates[tid0])[0]
+    with _fake(workers=4, slots=8, mem_budget=3 * fp) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        arr, outs = _vec_jobs(ctx, tid, 200, 100)
+        ctx.submit_many(tid, arr)
+        ctx.drain()
+        st = ctx.stats()
+        assert st.completed == 200
+        assert 0 < st.mem_high_water <= 3 * fp
+        assert st.inflight_high_water <= 3
+        assert st.mem_in_use == 0
+
+
+@pytest.mark.parametrize("mode", ["sync", "graph", "batch"])
+def test_baseline_modes_complete_in_order(mode):
+    with _fake(mode=mode, workers=4, slots=2) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        arr, outs = _vec_jobs(ctx, tid, 37, 30)
+        ctx.submit_many(tid, arr)
+        ctx.drain()
+        st = ctx.stats()
+        assert st.completed == 37 and st.stolen == 0
+        h = _headers(outs)
+        assert np.array_equal(h["job_id"], np.arange(37))
+        assert np.all(h["worker"] == np.arange(37) % 4)
+        if mode == "batch":
+            assert st.batches == 10  # 9 full batches of 4 and one of 1 at drain
+
+
+def test_invalid_arguments_rejected():
+    with _fake(workers=2, slots=2) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1000, pool_ptrs=DUMMY_POOL)
+        out = np.zeros(128, np.uint8)
+        with pytest.raises(A.SetError) as e:
+            ctx.submit(tid, host_out=out.ctypes.data, out_bytes=68, n=5000, a=1.0)  # n > max_n
+        assert e.value.code == A.SET_EINVAL
+        with pytest.raises(A.SetError):
+            ctx.submit(tid + 5, host_out=out.ctypes.data, out_bytes=68, n=5, a=1.0)
+        with pytest.raises(A.SetError):
+            ctx.submit(tid, host_out=out.ctypes.data, out_bytes=8, n=5, a=1.0)  # output too small
+        with pytest.raises(A.SetError):
+            ctx.define("gauss_sobel", width=0, height=4)
+    with pytest.raises(A.SetError):
+        _fake(workers=0, slots=2)
+    with pytest.raises(A.SetError):
+        _fake(workers=2, slots=4, queue_capacity=4, inflight=4)  # q + k > d
+
+
+def test_thread_sanitizer_stress():
+    from paper_2606_05495_amd import build
+    exe = build.build_tsan()
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=600,
+                       env=dict(os.environ, TSAN_OPTIONS="halt_on_error=1"))
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
