@@ -55,7 +55,7 @@ def run_mode(mode, args, jobs_per_step, steps, warmup, tin, tout, pool, torch, c
     ctx = Context(mode=mode, workers=workers, slots=args.slots if mode == "set" else 1,
                   batch_size=args.batch if mode == "batch" else 0, callback=callback, inflight=args.inflight,
                   spin_us=args.spin_us)
-    tid = ctx.define("gauss_sobel", width=1024, height=1024)
+    tid = ctx.define("gauss_sobel", width=1024, height=1024, copy=args.copy)
     ib, ob = ctx.in_bytes(tid), ctx.out_bytes(tid)
     stride = 128
     arr = make_jobs(ctx, tid, jobs_per_step, tin, pool, ib, tout, ob, stride)
@@ -124,6 +124,90 @@ def traffic_for(kernel_name):
         return None
 
 
+def bench_vectors(args, torch):
+    """100,000 uneven vector jobs (n log-uniform in [4096, 4194304)) over two
+    2^27-element device pools: bucketed persistent batches dispatched by SET vs
+    per-job graphs (SET), the batch-synchronised graph baseline and the
+    synchronous baseline.  Prints one JSON line."""
+    from paper_2606_05495_amd import _abi as A
+    from paper_2606_05495_amd import autotune, synth
+    from paper_2606_05495_amd.runtime import Context, pinned
+    import oracle
+    L = synth.VEC_POOL_LEN
+    log("generating vector pools (2 x %d floats)" % L)
+    x = synth.vec_pool(0, "x", L)
+    y = synth.vec_pool(0, "y", L)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.from_numpy(y).cuda()
+    J = args.vjobs
+    js = synth.vec_jobs(0, J, pool_len=L)
+    vj = np.zeros(J, dtype=A.VEC_JOB_DTYPE)
+    for f in ("n", "a", "x_off", "y_off"):
+        vj[f] = js[f]
+    total_bytes = 8.0 * float(js["n"].sum())
+    sample = np.arange(0, J, max(1, J // args.vsample))
+    refs = {int(i): oracle.saxpy_tanh_sum(x[js["x_off"][i]:js["x_off"][i] + js["n"][i]],
+                                          y[js["y_off"][i]:js["y_off"][i] + js["n"][i]], js["a"][i]) for i in sample}
+
+    def check(res):
+        return all(abs(float(res[i]) - S) <= oracle.vec_tolerance(S, E) for i, (S, E) in refs.items())
+
+    out = {}
+    # ---- bucketed persistent batches, dispatched by SET
+    ctx = Context(mode="set", workers=args.workers, slots=4, callback=args.callback)
+    tid = ctx.define("saxpy_batch", max_n=int(js["n"].max()), x_pool=xd, y_pool=yd, batch_max=args.batch_max,
+                     tiles_max=args.tiles_max, copy=args.copy)
+    tuning = None if args.no_tune else autotune.load()
+    if tuning is None and not args.no_tune:
+        log("autotuning buckets")
+        tuning = autotune.tune(ctx, tid, vj, calib=512, log=log)
+    res = np.zeros(J, np.float32)
+    ctx.run_vector_jobs(tid, vj, res, tuning)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, nb = ctx.run_vector_jobs(tid, vj, res, tuning)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["persistent"] = {"jobs_per_s": round(J / dt, 1), "batches": int(nb), "verified": check(res),
+                         "effective_GBps": round(total_bytes / dt / 1e9, 1)}
+    ctx.close()
+    # ---- per-job graphs / baselines on the per-job template
+    for mode in ("set", "batch", "sync"):
+        c = Context(mode=mode, workers=args.workers, slots=16 if mode == "set" else 1,
+                    batch_size=args.batch if mode == "batch" else 0, callback=args.callback)
+        t2 = c.define("saxpy_tanh_sum", max_n=int(js["n"].max()), x_pool=xd, y_pool=yd, copy=args.copy)
+        tout, nout = pinned(128 * J)
+        arr = c.job_array(J)
+        arr["host_out"] = tout.data_ptr() + np.arange(J, dtype=np.uint64) * 128
+        arr["out_bytes"] = 68
+        arr["n"] = js["n"]
+        arr["a"] = js["a"]
+        arr["x_off"] = js["x_off"]
+        arr["y_off"] = js["y_off"]
+        c.submit_many(t2, arr[:min(J, 2000)])
+        c.drain()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.submit_many(t2, arr)
+        c.drain()
+        torch.cuda.synchronize()
+        dt2 = time.perf_counter() - t0
+        r2 = nout.reshape(J, 128)[:, 64:68].copy().view(np.float32).ravel()
+        out["per_job_" + mode] = {"jobs_per_s": round(J / dt2, 1), "verified": check(r2)}
+        c.close()
+    p = out["persistent"]["jobs_per_s"]
+    line = {"metric": METRIC, "workload": "vector jobs: %d uneven (n log-uniform [4096, 4194304)) SAXPY->tanh->sum"
+            % J, "value": p, "unit": "jobs/s", "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+            "higher_is_better": True, "vs_baseline": None,
+            "speedup_vs_batch_sync": round(p / out["per_job_batch"]["jobs_per_s"], 2),
+            "speedup_vs_sync": round(p / out["per_job_sync"]["jobs_per_s"], 2),
+            "speedup_vs_per_job_set": round(p / out["per_job_set"]["jobs_per_s"], 2),
+            "modes": out, "config": {"workers": args.workers, "batch_max": args.batch_max,
+                                     "tiles_max": args.tiles_max, "copy": args.copy, "callback": args.callback,
+                                     "tuned": tuning is not None}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,11 +220,21 @@ def main():
     ap.add_argument("--inflight", type=int, default=0)
     ap.add_argument("--spin-us", type=int, default=0)
     ap.add_argument("--callback", default="event_chain", choices=["event_chain", "same_stream", "event_poll"])
+    ap.add_argument("--copy", default="kernels", choices=["nodes", "kernels"],
+                    help="job copies as graph memcpy nodes or as small-grid copy kernels")
     ap.add_argument("--baseline-steps", type=int, default=1)
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-passes", type=int, default=5)
     ap.add_argument("--stage-reps", type=int, default=200)
+    ap.add_argument("--workload", choices=["images", "vectors"], default="images")
+    ap.add_argument("--vjobs", type=int, default=100000)
+    ap.add_argument("--vsample", type=int, default=400)
+    ap.add_argument("--batch-max", type=int, default=1024)
+    ap.add_argument("--tiles-max", type=int, default=16384)
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--only", choices=["set", "batch", "sync"], default=None,
+                    help="run one mode only (for traced runs); prints its line")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -152,6 +246,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU (HIP device)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "vectors":
+        bench_vectors(args, torch)
+        return
     from paper_2606_05495_amd import synth
     from paper_2606_05495_amd.runtime import pinned
     import oracle
@@ -165,6 +262,14 @@ def main():
     tout, _ = pinned(128 * args.jobs)
     refs = [oracle.gauss_sobel(imgs[k], want_images=False) for k in range(pool)]
 
+    if args.only in ("batch", "sync"):
+        log("%s only: %d jobs x %d steps" % (args.only, args.jobs, args.steps))
+        c2, _, dt2, st2, _ = run_mode(args.only, args, args.jobs, args.steps, args.warmup, tin, tout, pool, torch)
+        c2.close()
+        ok2, _ = verify(tout, args.jobs, imgs, refs)
+        print(json.dumps({"mode": args.only, "jobs_per_s": round(args.jobs * args.steps / dt2, 1),
+                          "verified": ok2}), flush=True)
+        return
     log("SET mode: %d jobs x %d steps" % (args.jobs, args.steps))
     ctx, tid, dt, st, times = run_mode("set", args, args.jobs, args.steps, args.warmup, tin, tout, pool, torch,
                                        callback=args.callback)
@@ -187,7 +292,7 @@ def main():
                 "stages_us": {n: round(u, 3) for (n, _), u in zip(stages, stage_us)}}
 
     extra = {}
-    if not args.no_baselines:
+    if not args.no_baselines and args.only is None:
         for mode in ("batch", "sync"):
             log("%s baseline: %d jobs x %d steps" % (mode, args.jobs, args.baseline_steps))
             tout.zero_()
@@ -219,7 +324,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "gauss5-sobel-threshold-count/sum 1024x1024 f32 jobs, H2D 4 MiB + D2H 72 B each",
                    "jobs_per_step": args.jobs, "workers": args.workers, "slots_per_worker": args.slots,
-                   "callback": args.callback, "image_pool": pool},
+                   "callback": args.callback, "copy": args.copy, "image_pool": pool},
         "verified": bool(set_ok),
         "h2d_GBps": round(h2d, 2),
         "batch_sync_jobs_per_s": extra.get("batch", {}).get("jobs_per_s"),

@@ -125,7 +125,22 @@ enum set_pipeline {
     /* in: n int32.  Inclusive prefix sum accumulated in int64.
      * out: set_out_header + int64[n] (or the low int32 words with
      * SET_TF_SCAN_LOW32). */
-    SET_PIPE_SCAN_I32_I64 = 3
+    SET_PIPE_SCAN_I32_I64 = 3,
+    /* A batch of vector jobs in one launch graph: H2D of a descriptor table
+     * (64-byte header + one 32-byte descriptor per job) -> a persistent
+     * kernel whose blocks pull (job, tile) work items from an atomic counter
+     * -> a kernel summing each job's tile partials in tile order -> D2H of
+     * set_out_header + one float32 S per job, in descriptor order.  Jobs are
+     * normally submitted through set_run_vector_jobs, which builds the
+     * tables; per-job S depends only on (n, tile size). */
+    SET_PIPE_SAXPY_BATCH_F32 = 4
+};
+
+/* How a job's host<->device copies execute (both are part of the job's graph). */
+enum set_copy_mode {
+    SET_COPY_NODES = 0,   /* graph memcpy nodes (hipMemcpyAsync in the synchronous model) */
+    SET_COPY_KERNELS = 1  /* small-grid copy kernels that pull the input from / push the output to pinned
+                             host memory; host buffers must then be 16-byte aligned */
 };
 
 /* template flags */
@@ -165,7 +180,7 @@ typedef struct set_job_template {
     uint32_t width, height;      /* image pipelines: image size (each >= 1) */
     uint64_t max_n;              /* vector / scan pipelines: largest n any job may use (>= 1) */
     float threshold;             /* Gaussian/Sobel mask threshold; 0 means 1.0 */
-    uint32_t reserved0;
+    uint32_t copy_mode;          /* enum set_copy_mode */
     void *arena;                 /* borrowed device buffer for all slots of this template, or NULL: library allocates */
     uint64_t arena_bytes;        /* size of `arena`; must be >= set_template_footprint's total */
     const float *dev_x_pool;     /* SAXPY: borrowed device pool of x values */
@@ -173,6 +188,8 @@ typedef struct set_job_template {
     uint64_t pool_len;           /* SAXPY: elements in each pool */
     int32_t block;               /* tuning: threads per block (0 = default) */
     int32_t grid;                /* tuning: grid cap for streaming kernels (0 = default) */
+    uint32_t batch_max;          /* SAXPY batch: most jobs per batch (descriptor table capacity) */
+    uint32_t tiles_max;          /* SAXPY batch: most (job, tile) work items per batch */
 } set_job_template;
 
 typedef struct set_job_args {
@@ -185,7 +202,24 @@ typedef struct set_job_args {
     int32_t worker_hint;         /* -1: submitter policy; else preferred worker */
     uint64_t x_off, y_off;       /* SAXPY: element offsets into the x / y pools */
     uint64_t user_tag;           /* copied into the output header */
+    uint32_t grid;               /* SAXPY batch: persistent grid (blocks); 0 = template default */
+    uint32_t reserved;
 } set_job_args;
+
+/* One vector job for set_run_vector_jobs (z = a*x + y over pool windows). */
+typedef struct set_vec_job {
+    uint64_t x_off, y_off;       /* element offsets into the template's x / y pools */
+    uint64_t n;                  /* 1 <= n <= template max_n */
+    float a;
+    uint32_t reserved;
+} set_vec_job;
+
+/* Per size bucket b = floor(log2 n): elements per (job, tile) work item and
+ * the persistent grid.  Zero entries take the defaults. */
+typedef struct set_vec_tuning {
+    uint32_t tile_elems[64];     /* multiple of 1024 */
+    uint32_t grid[64];
+} set_vec_tuning;
 
 /* Written by the device at the start of every job output (64 bytes). */
 #define SET_OUT_MAGIC 0x5E7D0A11u
@@ -293,6 +327,18 @@ int set_get_job_times(set_ctx *c, set_job_times *out, uint64_t max, uint64_t *co
  * current contents are used as input, so run one job on that slot first.
  * Requires a drained context. */
 int set_time_stage(set_ctx *c, int template_id, int stage, int worker, int reps, double *avg_us);
+
+/* Bucketed persistent batching of vector jobs (template of pipeline
+ * SET_PIPE_SAXPY_BATCH_F32): jobs are grouped by size bucket floor(log2 n),
+ * each bucket in input order into batches of at most batch_max jobs and
+ * tiles_max work items; every batch is one job of the context (in SET mode
+ * it is queued, dispatched, stolen and released like any other job).
+ * results[i] receives S of jobs[i].  Blocks until every batch has completed.
+ * tuning may be NULL.  Descriptor tables and result staging are pinned host
+ * memory owned by the library.  *batches (may be NULL) receives the number of
+ * batches submitted. */
+int set_run_vector_jobs(set_ctx *c, int template_id, const set_vec_job *jobs, uint64_t count,
+                        float *results, const set_vec_tuning *tuning, uint64_t *batches);
 
 /* Number of kernels in the template's chain and the algorithmic HBM bytes one
  * launch of each moves (reads + writes of its operands, counted once). */

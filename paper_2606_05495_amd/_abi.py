@@ -32,7 +32,10 @@ SET_CB_EVENT_CHAIN, SET_CB_SAME_STREAM, SET_CB_EVENT_POLL = 0, 1, 2
 SET_SUBMIT_ROUND_ROBIN, SET_SUBMIT_SHORTEST, SET_SUBMIT_SKEW0 = 0, 1, 2
 # pipelines
 SET_PIPE_BOX_HIST_U8, SET_PIPE_GAUSS_SOBEL_F32, SET_PIPE_SAXPY_TANH_SUM_F32, SET_PIPE_SCAN_I32_I64 = 0, 1, 2, 3
+SET_PIPE_SAXPY_BATCH_F32 = 4
 SET_TF_DEBUG, SET_TF_SCAN_LOW32 = 0x1, 0x2
+SET_COPY_NODES, SET_COPY_KERNELS = 0, 1
+COPY_MODES = {"nodes": SET_COPY_NODES, "kernels": SET_COPY_KERNELS}
 SET_NONBLOCK = 0x1
 SET_OUT_MAGIC = 0x5E7D0A11
 
@@ -72,7 +75,7 @@ class set_job_template(ctypes.Structure):
         ("height", ctypes.c_uint32),
         ("max_n", ctypes.c_uint64),
         ("threshold", ctypes.c_float),
-        ("reserved0", ctypes.c_uint32),
+        ("copy_mode", ctypes.c_uint32),
         ("arena", ctypes.c_void_p),
         ("arena_bytes", ctypes.c_uint64),
         ("dev_x_pool", ctypes.c_void_p),
@@ -80,6 +83,8 @@ class set_job_template(ctypes.Structure):
         ("pool_len", ctypes.c_uint64),
         ("block", ctypes.c_int32),
         ("grid", ctypes.c_int32),
+        ("batch_max", ctypes.c_uint32),
+        ("tiles_max", ctypes.c_uint32),
     ]
 
 
@@ -95,17 +100,29 @@ class set_job_args(ctypes.Structure):
         ("x_off", ctypes.c_uint64),
         ("y_off", ctypes.c_uint64),
         ("user_tag", ctypes.c_uint64),
+        ("grid", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 
 # numpy mirror of set_job_args for bulk submission
 JOB_ARGS_DTYPE = np.dtype({
-    "names": ["host_in", "in_bytes", "host_out", "out_bytes", "n", "a", "worker_hint", "x_off", "y_off", "user_tag"],
+    "names": ["host_in", "in_bytes", "host_out", "out_bytes", "n", "a", "worker_hint", "x_off", "y_off", "user_tag",
+              "grid", "reserved"],
     "formats": [np.uint64, np.uint64, np.uint64, np.uint64, np.uint64, np.float32, np.int32, np.uint64, np.uint64,
-                np.uint64],
-    "offsets": [0, 8, 16, 24, 32, 40, 44, 48, 56, 64],
-    "itemsize": 72,
+                np.uint64, np.uint32, np.uint32],
+    "offsets": [0, 8, 16, 24, 32, 40, 44, 48, 56, 64, 72, 76],
+    "itemsize": 80,
 })
+
+# numpy mirror of set_vec_job
+VEC_JOB_DTYPE = np.dtype({"names": ["x_off", "y_off", "n", "a", "reserved"],
+                          "formats": [np.uint64, np.uint64, np.uint64, np.float32, np.uint32],
+                          "offsets": [0, 8, 16, 24, 28], "itemsize": 32})
+
+
+class set_vec_tuning(ctypes.Structure):
+    _fields_ = [("tile_elems", ctypes.c_uint32 * 64), ("grid", ctypes.c_uint32 * 64)]
 
 
 class set_out_header(ctypes.Structure):
@@ -161,6 +178,7 @@ EXPORTS = [
     "set_ctx_create", "set_ctx_destroy", "set_template_footprint", "set_template_define", "set_submit",
     "set_submit_many", "set_set_completion_cb", "set_drain", "set_get_stats", "set_reset_stats",
     "set_get_job_times", "set_time_stage", "set_stage_info", "set_last_error", "set_strerror",
+    "set_run_vector_jobs",
 ]
 
 _lib = None
@@ -193,6 +211,7 @@ def load():
         "set_get_job_times": (I, [P, P, U64, ctypes.POINTER(U64)]),
         "set_time_stage": (I, [P, I, I, I, I, ctypes.POINTER(ctypes.c_double)]),
         "set_stage_info": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(U64), I, ctypes.c_char_p, I]),
+        "set_run_vector_jobs": (I, [P, I, P, U64, P, ctypes.POINTER(set_vec_tuning), ctypes.POINTER(U64)]),
         "set_last_error": (ctypes.c_char_p, [P]),
         "set_strerror": (ctypes.c_char_p, [I]),
     }
@@ -294,6 +313,15 @@ def set_stage_info(ctx, template_id: int):
     names = ctypes.create_string_buffer(512)
     check(load().set_stage_info(ctx, template_id, ctypes.byref(n), b, 8, names, 512), ctx)
     return list(zip(names.value.decode().split(","), list(b)[:n.value]))
+
+
+def set_run_vector_jobs(ctx, template_id: int, jobs: np.ndarray, results: np.ndarray, tuning=None) -> int:
+    assert jobs.dtype == VEC_JOB_DTYPE and jobs.flags["C_CONTIGUOUS"]
+    assert results.dtype == np.float32 and results.size >= jobs.size and results.flags["C_CONTIGUOUS"]
+    nb = ctypes.c_uint64()
+    check(load().set_run_vector_jobs(ctx, template_id, jobs.ctypes.data, jobs.size, results.ctypes.data,
+                                     ctypes.byref(tuning) if tuning is not None else None, ctypes.byref(nb)), ctx)
+    return nb.value
 
 
 def set_last_error(ctx) -> str:

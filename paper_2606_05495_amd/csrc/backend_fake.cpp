@@ -7,6 +7,7 @@
 // Simulated job duration: vector jobs take n microseconds (n mod 10^6), all
 // other pipelines take 20 microseconds.
 #include <algorithm>
+#include <cstdlib>
 #include <condition_variable>
 #include <deque>
 #include <random>
@@ -88,6 +89,8 @@ class FakeBackend : public Backend {
     for (int i = 0; i < count; ++i) write_header(jobs[i], true);
     return SET_OK;
   }
+  void* alloc_host(uint64_t bytes) override { return std::calloc(1, bytes); }
+  void free_host(void* p) override { std::free(p); }
   int time_stage(int, int, int, int, double* avg_us, std::string*) override {
     *avg_us = 0.0;
     return SET_OK;

@@ -46,10 +46,20 @@ struct Slot {
   BoxArgs box;
   Div9Args div;
   HistArgs hist;
+  HistFinalArgs histf;
   GaussArgs gauss;
   SobelArgs sobel;
+  SobelFinalArgs sobelf;
   VecArgs vec;
-  ScanArgs scan;
+  VecFinalArgs vecf;
+  ScanReduceArgs scan_r;
+  ScanSpineArgs scan_s;
+  ScanDownArgs scan_d;
+  VecBatchArgs vb;
+  VecBatchFinalArgs vbf;
+  CopyArgs h2d_copy, d2h_copy;
+  void* h2d_argv[1] = {&h2d_copy};
+  void* d2h_argv[1] = {&d2h_copy};
   int nstages = 0;
   const void* func[kMaxStages] = {};
   dim3 grid[kMaxStages];
@@ -247,10 +257,23 @@ class HipBackend : public Backend {
     Slot& sl = p.slots[(size_t)si * d_];
     set_scalars(p, sl, j);
     hipStream_t st = streams_[si];
-    if (sl.in_bytes) HIPCK(hipMemcpyAsync(sl.base + p.L.in, sl.host_in, sl.in_bytes, hipMemcpyHostToDevice, st));
+    const bool kcopy = p.t.copy_mode == SET_COPY_KERNELS;
+    if (sl.in_bytes) {
+      if (kcopy) {
+        sl.h2d_copy = CopyArgs{sl.host_in, sl.base + p.L.in, sl.in_bytes};
+        HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(kCopyBlocks), dim3(kBlock), sl.h2d_argv, 0, st));
+      } else {
+        HIPCK(hipMemcpyAsync(sl.base + p.L.in, sl.host_in, sl.in_bytes, hipMemcpyHostToDevice, st));
+      }
+    }
     for (int i = 0; i < sl.nstages; ++i)
       HIPCK(hipLaunchKernel(sl.func[i], sl.grid[i], dim3(kBlock), sl.argv[i], 0, st));
-    HIPCK(hipMemcpyAsync(sl.host_out, sl.base + p.L.out, sl.out_bytes, hipMemcpyDeviceToHost, st));
+    if (kcopy) {
+      sl.d2h_copy = CopyArgs{sl.base + p.L.out, sl.host_out, sl.out_bytes};
+      HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(kCopyBlocks), dim3(kBlock), sl.d2h_argv, 0, st));
+    } else {
+      HIPCK(hipMemcpyAsync(sl.host_out, sl.base + p.L.out, sl.out_bytes, hipMemcpyDeviceToHost, st));
+    }
     const uint64_t t0 = now_ns();
     HIPCK(hipStreamSynchronize(st));
     sync_ns_ += now_ns() - t0;
@@ -318,18 +341,14 @@ class HipBackend : public Backend {
     hipEvent_t e0, e1;
     HIPCK(hipEventCreate(&e0));
     HIPCK(hipEventCreate(&e1));
-    const uint64_t seq0 = sl.scan.js.seq;
     HIPCK(hipLaunchKernel(sl.func[stage], sl.grid[stage], dim3(kBlock), sl.argv[stage], 0, st));
     HIPCK(hipEventRecord(e0, st));
-    for (int r = 0; r < reps; ++r) {
-      if (p.t.pipeline == SET_PIPE_SCAN_I32_I64) sl.scan.js.seq = seq0 + 1 + (uint64_t)r;  // fresh epoch per launch
+    for (int r = 0; r < reps; ++r)
       HIPCK(hipLaunchKernel(sl.func[stage], sl.grid[stage], dim3(kBlock), sl.argv[stage], 0, st));
-    }
     HIPCK(hipEventRecord(e1, st));
     HIPCK(hipEventSynchronize(e1));
     float ms = 0.f;
     HIPCK(hipEventElapsedTime(&ms, e0, e1));
-    sl.scan.js.seq = seq0;
     HIPCK(hipEventDestroy(e0));
     HIPCK(hipEventDestroy(e1));
     *avg_us = (double)ms * 1e3 / reps;
@@ -337,6 +356,16 @@ class HipBackend : public Backend {
   }
 
   uint64_t host_ns_sync() const override { return sync_ns_.load(); }
+
+  void* alloc_host(uint64_t bytes) override {
+    ensure_dev();
+    void* p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    return p;
+  }
+  void free_host(void* p) override {
+    if (p) (void)hipHostFree(p);
+  }
 
   void shutdown() override {
     if (down_) return;
@@ -425,77 +454,73 @@ class HipBackend : public Backend {
     const set_job_template& t = p.t;
     const int h = (int)t.height, w = (int)t.width;
     const int64_t npix = (int64_t)h * w;
-    std::memset(&sl.box, 0, sizeof(sl.box));
+    auto stage = [&](const void* f, dim3 g, void* args) {
+      sl.func[sl.nstages] = f;
+      sl.grid[sl.nstages] = g;
+      sl.argv[sl.nstages][0] = args;
+      ++sl.nstages;
+    };
+    sl.nstages = 0;
     switch (t.pipeline) {
       case SET_PIPE_BOX_HIST_U8: {
+        const unsigned hb = hist_blocks(npix);
         sl.box = BoxArgs{(const uint8_t*)(b + L.in), (uint16_t*)(b + L.b1), h, w, sc.hdr, JobScalars{}};
         sl.div = Div9Args{(const uint16_t*)(b + L.b1), (uint8_t*)(b + L.b2), npix};
-        const unsigned hb = hist_blocks(npix);
-        const uint64_t pbytes = (((uint64_t)hb * 1024) + 255) / 256 * 256;
-        sl.hist = HistArgs{(const uint8_t*)(b + L.b2), npix, (uint32_t*)(b + L.scratch),
-                           (uint32_t*)(b + L.scratch + pbytes), (uint32_t*)(b + L.out + 64), sc};
-        sl.nstages = 3;
-        sl.func[0] = (const void*)&k_box3_u8_u16;
-        sl.grid[0] = to_dim3(box_grid(h, w));
-        sl.argv[0][0] = &sl.box;
-        sl.func[1] = (const void*)&k_div9_u16_u8;
-        sl.grid[1] = dim3(div9_blocks(npix));
-        sl.argv[1][0] = &sl.div;
-        sl.func[2] = (const void*)&k_hist256_u8;
-        sl.grid[2] = dim3(hb);
-        sl.argv[2][0] = &sl.hist;
+        sl.hist = HistArgs{(const uint8_t*)(b + L.b2), npix, (uint32_t*)(b + L.scratch)};
+        sl.histf = HistFinalArgs{(const uint32_t*)(b + L.scratch), hb, (uint32_t*)(b + L.out + 64), sc};
+        stage((const void*)&k_box3_u8_u16, to_dim3(box_grid(h, w)), &sl.box);
+        stage((const void*)&k_div9_u16_u8, dim3(div9_blocks(npix)), &sl.div);
+        stage((const void*)&k_hist256_u8, dim3(hb), &sl.hist);
+        stage((const void*)&k_hist256_final, dim3(1), &sl.histf);
         break;
       }
       case SET_PIPE_GAUSS_SOBEL_F32: {
         sl.gauss = GaussArgs{(const float*)(b + L.in), (float*)(b + L.b1), h, w, taps[0], taps[1], taps[2], sc.hdr,
                              JobScalars{}};
         const Grid3 sg = sobel_grid(h, w);
-        const uint64_t nb = (uint64_t)sg.x * sg.y;
-        const uint64_t q = (nb * 4 + 255) / 256 * 256;
-        sl.sobel = SobelArgs{(const float*)(b + L.b1),
-                             (uint8_t*)(b + L.b2),
-                             h,
-                             w,
-                             t.threshold != 0.f ? t.threshold : 1.0f,
-                             (uint32_t*)(b + L.scratch),
-                             (float*)(b + L.scratch + q),
-                             (uint32_t*)(b + L.scratch + 2 * q),
-                             (uint32_t*)(b + L.out + 64),
-                             (float*)(b + L.out + 68),
-                             sc};
-        sl.nstages = 2;
-        sl.func[0] = (const void*)&k_gauss5_f32;
-        sl.grid[0] = to_dim3(gauss_grid(h, w));
-        sl.argv[0][0] = &sl.gauss;
-        sl.func[1] = (const void*)&k_sobel_thresh_f32;
-        sl.grid[1] = to_dim3(sg);
-        sl.argv[1][0] = &sl.sobel;
+        const unsigned nb = sg.x * sg.y;
+        const uint64_t q = ((uint64_t)nb * 4 + 255) / 256 * 256;
+        sl.sobel = SobelArgs{(const float*)(b + L.b1), (uint8_t*)(b + L.b2), h, w,
+                             t.threshold != 0.f ? t.threshold : 1.0f, (uint32_t*)(b + L.scratch),
+                             (float*)(b + L.scratch + q)};
+        sl.sobelf = SobelFinalArgs{(const uint32_t*)(b + L.scratch), (const float*)(b + L.scratch + q), nb,
+                                   (uint32_t*)(b + L.out + 64), (float*)(b + L.out + 68), sc};
+        stage((const void*)&k_gauss5_f32, to_dim3(gauss_grid(h, w)), &sl.gauss);
+        stage((const void*)&k_sobel_thresh_f32, to_dim3(sg), &sl.sobel);
+        stage((const void*)&k_sobel_final, dim3(1), &sl.sobelf);
         break;
       }
       case SET_PIPE_SAXPY_TANH_SUM_F32: {
-        const uint64_t q = ((uint64_t)kVecGridCap * 4 + 255) / 256 * 256;
-        sl.vec = VecArgs{t.dev_x_pool, t.dev_y_pool, (float*)(b + L.scratch), (uint32_t*)(b + L.scratch + q),
-                         (float*)(b + L.out + 64), sc, JobScalars{}};
+        sl.vec = VecArgs{t.dev_x_pool, t.dev_y_pool, (float*)(b + L.scratch), sc.hdr, JobScalars{}};
         sl.vec.js.n = t.max_n;
-        sl.nstages = 1;
-        sl.func[0] = (const void*)&k_saxpy_tanh_sum_f32;
-        sl.grid[0] = dim3(vec_blocks(t.max_n));
-        sl.argv[0][0] = &sl.vec;
+        sl.vecf = VecFinalArgs{(const float*)(b + L.scratch), (float*)(b + L.out + 64), sc};
+        stage((const void*)&k_saxpy_tanh_sum_f32, dim3(vec_blocks(t.max_n)), &sl.vec);
+        stage((const void*)&k_vec_final, dim3(1), &sl.vecf);
+        break;
+      }
+      case SET_PIPE_SAXPY_BATCH_F32: {
+        const uint64_t q = ((uint64_t)t.tiles_max * 4 + 255) / 256 * 256;
+        uint32_t* work = (uint32_t*)(b + L.scratch + q);
+        sl.vb = VecBatchArgs{(const uint8_t*)(b + L.in), t.dev_x_pool, t.dev_y_pool, (float*)(b + L.scratch), work,
+                             sc.hdr, JobScalars{}};
+        sl.vbf = VecBatchFinalArgs{(const uint8_t*)(b + L.in), (const float*)(b + L.scratch), work,
+                                   (float*)(b + L.out + 64), sc};
+        stage((const void*)&k_vec_batch_tiles, dim3(t.grid > 0 ? (unsigned)t.grid : (unsigned)kVecBatchGrid), &sl.vb);
+        stage((const void*)&k_vec_batch_final, dim3((t.batch_max + kBlock - 1) / kBlock), &sl.vbf);
         break;
       }
       case SET_PIPE_SCAN_I32_I64: {
-        const uint64_t T = scan_tiles(t.max_n);
-        const uint64_t q4 = (T * 4 + 255) / 256 * 256, q8 = (T * 8 + 255) / 256 * 256;
+        const unsigned T = scan_tiles(t.max_n);
+        const uint64_t q8 = ((uint64_t)T * 8 + 255) / 256 * 256;
         char* sb = b + L.scratch;
-        uint32_t* ctr = (uint32_t*)(sb + q4 + 2 * q8);
-        sl.scan = ScanArgs{(const int32_t*)(b + L.in), (void*)(b + L.out + 64), (uint32_t*)sb, (int64_t*)(sb + q4),
-                           (int64_t*)(sb + q4 + q8), ctr, ctr + 1, ctr + 2,
-                           (t.flags & SET_TF_SCAN_LOW32) ? 1 : 0, sc, JobScalars{}};
-        sl.scan.js.n = t.max_n;
-        sl.nstages = 1;
-        sl.func[0] = (const void*)&k_scan_i32_i64;
-        sl.grid[0] = dim3((unsigned)T);
-        sl.argv[0][0] = &sl.scan;
+        sl.scan_r = ScanReduceArgs{(const int32_t*)(b + L.in), (int64_t*)sb, T, sc.hdr, JobScalars{}};
+        sl.scan_r.js.n = t.max_n;
+        sl.scan_s = ScanSpineArgs{(const int64_t*)sb, (int64_t*)(sb + q8), sc};
+        sl.scan_d = ScanDownArgs{(const int32_t*)(b + L.in), (const int64_t*)(sb + q8), (void*)(b + L.out + 64),
+                                 (t.flags & SET_TF_SCAN_LOW32) ? 1 : 0, sc.hdr};
+        stage((const void*)&k_scan_reduce_i32, dim3(T), &sl.scan_r);
+        stage((const void*)&k_scan_spine_i64, dim3(1), &sl.scan_s);
+        stage((const void*)&k_scan_down_i32_i64, dim3(T), &sl.scan_d);
         break;
       }
     }
@@ -527,8 +552,11 @@ class HipBackend : public Backend {
         break;
       case SET_PIPE_SCAN_I32_I64:
         if (js.n == 0) js.n = p.t.max_n;
-        sl.scan.js = js;
-        sl.grid[0] = dim3(scan_tiles(js.n));
+        sl.scan_r.js = js;
+        break;
+      case SET_PIPE_SAXPY_BATCH_F32:
+        sl.vb.js = js;
+        sl.grid[0] = dim3(j->args.grid ? j->args.grid : (p.t.grid > 0 ? (unsigned)p.t.grid : (unsigned)kVecBatchGrid));
         break;
     }
     sl.host_in = j->args.host_in;
@@ -548,11 +576,29 @@ class HipBackend : public Backend {
     return kp;
   }
 
+  hipKernelNodeParams copy_params(void** argv) {
+    hipKernelNodeParams kp{};
+    kp.func = (void*)&k_copy_bytes;
+    kp.gridDim = dim3(kCopyBlocks);
+    kp.blockDim = dim3(kBlock);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = argv;
+    kp.extra = nullptr;
+    return kp;
+  }
+
   int add_chain(Pipe& p, Slot& sl, hipGraph_t g, ChainNodes* cn, std::string* err) {
+    const bool kcopy = p.t.copy_mode == SET_COPY_KERNELS;
     hipGraphNode_t prev = nullptr;
     if (p.L.in_cap > 0) {
-      HIPCK(hipGraphAddMemcpyNode1D(&cn->h2d, g, nullptr, 0, sl.base + p.L.in, p.placeholder, p.L.in_cap,
-                                    hipMemcpyHostToDevice));
+      if (kcopy) {
+        sl.h2d_copy = CopyArgs{p.placeholder, sl.base + p.L.in, p.L.in_cap};
+        hipKernelNodeParams kp = copy_params(sl.h2d_argv);
+        HIPCK(hipGraphAddKernelNode(&cn->h2d, g, nullptr, 0, &kp));
+      } else {
+        HIPCK(hipGraphAddMemcpyNode1D(&cn->h2d, g, nullptr, 0, sl.base + p.L.in, p.placeholder, p.L.in_cap,
+                                      hipMemcpyHostToDevice));
+      }
       prev = cn->h2d;
     }
     for (int i = 0; i < sl.nstages; ++i) {
@@ -560,21 +606,41 @@ class HipBackend : public Backend {
       HIPCK(hipGraphAddKernelNode(&cn->k[i], g, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
       prev = cn->k[i];
     }
-    HIPCK(hipGraphAddMemcpyNode1D(&cn->d2h, g, &prev, 1, p.placeholder, sl.base + p.L.out, p.L.out_cap,
-                                  hipMemcpyDeviceToHost));
+    if (kcopy) {
+      sl.d2h_copy = CopyArgs{sl.base + p.L.out, p.placeholder, p.L.out_cap};
+      hipKernelNodeParams kp = copy_params(sl.d2h_argv);
+      HIPCK(hipGraphAddKernelNode(&cn->d2h, g, &prev, 1, &kp));
+    } else {
+      HIPCK(hipGraphAddMemcpyNode1D(&cn->d2h, g, &prev, 1, p.placeholder, sl.base + p.L.out, p.L.out_cap,
+                                    hipMemcpyDeviceToHost));
+    }
     return SET_OK;
   }
 
   // UpdateGraphParams: retarget an executable's chain to the slot's current
   // binding (H2D source, first kernel's argument block and grid, D2H target).
   int update_exec(Pipe& p, Slot& sl, hipGraphExec_t ex, const ChainNodes& cn, std::string* err) {
-    if (sl.in_bytes)
-      HIPCK(hipGraphExecMemcpyNodeSetParams1D(ex, cn.h2d, sl.base + p.L.in, sl.host_in, sl.in_bytes,
-                                              hipMemcpyHostToDevice));
+    const bool kcopy = p.t.copy_mode == SET_COPY_KERNELS;
+    if (sl.in_bytes) {
+      if (kcopy) {
+        sl.h2d_copy = CopyArgs{sl.host_in, sl.base + p.L.in, sl.in_bytes};
+        hipKernelNodeParams kp = copy_params(sl.h2d_argv);
+        HIPCK(hipGraphExecKernelNodeSetParams(ex, cn.h2d, &kp));
+      } else {
+        HIPCK(hipGraphExecMemcpyNodeSetParams1D(ex, cn.h2d, sl.base + p.L.in, sl.host_in, sl.in_bytes,
+                                                hipMemcpyHostToDevice));
+      }
+    }
     hipKernelNodeParams kp = kparams(sl, 0);
     HIPCK(hipGraphExecKernelNodeSetParams(ex, cn.k[0], &kp));
-    HIPCK(hipGraphExecMemcpyNodeSetParams1D(ex, cn.d2h, sl.host_out, sl.base + p.L.out, sl.out_bytes,
-                                            hipMemcpyDeviceToHost));
+    if (kcopy) {
+      sl.d2h_copy = CopyArgs{sl.base + p.L.out, sl.host_out, sl.out_bytes};
+      hipKernelNodeParams kd = copy_params(sl.d2h_argv);
+      HIPCK(hipGraphExecKernelNodeSetParams(ex, cn.d2h, &kd));
+    } else {
+      HIPCK(hipGraphExecMemcpyNodeSetParams1D(ex, cn.d2h, sl.host_out, sl.base + p.L.out, sl.out_bytes,
+                                              hipMemcpyDeviceToHost));
+    }
     return SET_OK;
   }
 

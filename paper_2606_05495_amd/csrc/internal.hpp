@@ -52,10 +52,29 @@ struct DevSlotHdr {
   uint64_t user_tag;
   uint32_t worker;
   uint32_t slot;
-  uint32_t pad[6];
+  uint64_t n;  // job length (vector / scan pipelines), read by later stages
+  uint32_t pad[4];
 };
 static_assert(sizeof(DevSlotHdr) == 64, "DevSlotHdr layout");
 static_assert(sizeof(set_out_header) == 64, "set_out_header layout");
+
+// Descriptor table of a vector batch (host-written, copied to the slot by
+// the batch's H2D): a 64-byte header, then one 32-byte descriptor per job.
+struct VecBatchHdr {
+  uint32_t count;        // jobs in the batch
+  uint32_t tile_elems;   // elements per (job, tile) work item, multiple of 1024
+  uint32_t total_tiles;  // work items in the batch
+  uint32_t pad[13];
+};
+struct VecBatchDesc {
+  uint64_t x_off, y_off;
+  uint32_t n;
+  float a;
+  uint32_t tile_start;   // first work item of this job (non-decreasing)
+  uint32_t ntiles;       // ceil(n / tile_elems)
+};
+static_assert(sizeof(VecBatchHdr) == 64, "VecBatchHdr layout");
+static_assert(sizeof(VecBatchDesc) == 32, "VecBatchDesc layout");
 
 inline uint64_t canary_value(int tmpl, int w, int s, int which) {
   return 0x5E7CA9A200000000ull ^ ((uint64_t)which << 60) ^ ((uint64_t)tmpl << 24) ^ ((uint64_t)w << 12) ^
@@ -117,6 +136,9 @@ class Backend {
   virtual int run_batch(JobRec** jobs, int count, std::string* err) = 0;
   virtual int time_stage(int tmpl, int stage, int worker, int reps, double* avg_us, std::string* err) = 0;
   virtual uint64_t host_ns_sync() const { return 0; }
+  // Pinned host staging owned by the library (descriptor tables, results).
+  virtual void* alloc_host(uint64_t bytes) = 0;
+  virtual void free_host(void* p) = 0;
   virtual void shutdown() = 0;
 };
 

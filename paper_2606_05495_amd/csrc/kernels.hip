@@ -4,10 +4,13 @@
 // job's input and size (bit-identical whatever stream, slot or neighbour ran
 // beside it); the histogram uses LDS atomics on per-wave private bins.
 //
-// Every chain ends in a kernel whose last-arriving block (an agent-scope
-// counter) combines the per-block partials in block order, resets its
-// counters for the slot's next job, checks the slot's canaries and publishes
-// the output header.
+// Cross-block results are combined by a separate single-block kernel node
+// that runs after the producing kernel has finished (the kernel boundary is
+// the only synchronisation: no per-block device-scope fences, which on this
+// multi-XCD part write back the issuing XCD's L2 and cost tens of
+// microseconds when a thousand blocks issue them).  That last kernel combines
+// the per-block partials in block order, checks the slot's canaries and
+// publishes the output header.
 #include "kernels.hpp"
 
 namespace setrt {
@@ -19,6 +22,7 @@ __device__ inline void write_slot_hdr(DevSlotHdr* hdr, const JobScalars& js) {
   hdr->user_tag = js.user_tag;
   hdr->worker = js.worker;
   hdr->slot = js.slot;
+  hdr->n = js.n;
 }
 
 // One thread; the caller has acquired everything the job wrote.
@@ -36,23 +40,6 @@ __device__ inline void publish_out(const SlotConst& sc, bool extra_ok) {
   o->reserved[1] = 0;
   o->reserved[2] = 0;
   o->magic = extra_ok ? SET_OUT_MAGIC : 0xBAD0BAD0u;
-}
-
-// Returns true in every thread of the block that arrives last.  All global
-// writes the block made before the call are released (agent scope) and, in
-// the last block, every other block's writes are acquired.
-__device__ inline bool last_block_arrive(uint32_t* counter, unsigned nblocks) {
-  __shared__ int s_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (prev == nblocks - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  const bool last = s_last != 0;
-  if (last) __threadfence();
-  return last;
 }
 
 __device__ inline float wave_sum_f32(float v) {
@@ -86,6 +73,29 @@ __device__ inline uint32_t block_sum_u32(uint32_t v, uint32_t* s4) {
 }
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// ------------------------------------------------------------------ copy kernel (H2D pull / D2H push)
+// Grid-stride over 16-byte words with four independent loads in flight per
+// thread, then a byte tail.  Source and destination are 16-byte aligned (slot
+// buffers are 256-aligned; host buffers are checked by the binder).
+__global__ __launch_bounds__(kBlock) void k_copy_bytes(CopyArgs a) {
+  const uint64_t nvec = a.bytes >> 4;
+  const uint4* __restrict__ src = reinterpret_cast<const uint4*>(a.src);
+  uint4* __restrict__ dst = reinterpret_cast<uint4*>(a.dst);
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  for (; i + 3 * stride < nvec; i += 4 * stride) {
+    const uint4 v0 = src[i], v1 = src[i + stride], v2 = src[i + 2 * stride], v3 = src[i + 3 * stride];
+    dst[i] = v0;
+    dst[i + stride] = v1;
+    dst[i + 2 * stride] = v2;
+    dst[i + 3 * stride] = v3;
+  }
+  for (; i < nvec; i += stride) dst[i] = src[i];
+  const uint64_t tail = nvec << 4;
+  const uint64_t t = tail + (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t < a.bytes) reinterpret_cast<uint8_t*>(a.dst)[t] = reinterpret_cast<const uint8_t*>(a.src)[t];
+}
 
 // ------------------------------------------------------------------ 3x3 box sum (zero padded), uint8 -> uint16
 // Output tile kBoxTW x kBoxTH, input tile + 1-pixel halo staged in LDS.
@@ -137,8 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_div9_u16_u8(Div9Args a) {
 
 // ------------------------------------------------------------------ 256-bin histogram of uint8
 // Per-wave private LDS bins (4 x 256) take the LDS atomics; the block's sum of
-// them goes to partials[block]; the last block adds the partials in block
-// order (integer, so exact) into the output payload.
+// them goes to partials[block].
 __global__ __launch_bounds__(kBlock) void k_hist256_u8(HistArgs a) {
   __shared__ uint32_t wh[4][256];
   const int tid = threadIdx.x, wave = tid >> 6;
@@ -157,15 +166,15 @@ __global__ __launch_bounds__(kBlock) void k_hist256_u8(HistArgs a) {
   }
   __syncthreads();
   a.partials[(size_t)blockIdx.x * 256 + tid] = wh[0][tid] + wh[1][tid] + wh[2][tid] + wh[3][tid];
-  if (last_block_arrive(a.counter, gridDim.x)) {
-    uint32_t s = 0;
-    for (unsigned b = 0; b < gridDim.x; ++b) s += a.partials[(size_t)b * 256 + tid];
-    a.H[tid] = s;
-    if (tid == 0) {
-      *a.counter = 0u;
-      publish_out(a.sc, true);
-    }
-  }
+}
+
+// One block: bin tid = sum over blocks in block order (integer, exact).
+__global__ __launch_bounds__(kBlock) void k_hist256_final(HistFinalArgs a) {
+  const int tid = threadIdx.x;
+  uint32_t s = 0;
+  for (unsigned b = 0; b < a.nblocks; ++b) s += a.partials[(size_t)b * 256 + tid];
+  a.H[tid] = s;
+  if (tid == 0) publish_out(a.sc, true);
 }
 
 // ------------------------------------------------------------------ separable 5-tap Gaussian, replicated borders
@@ -211,8 +220,8 @@ __global__ __launch_bounds__(kBlock) void k_gauss5_f32(GaussArgs a) {
 
 // ------------------------------------------------------------------ Sobel magnitude + threshold + count/sum
 // gx = (right column) - (left column) with weights 1,2,1; gy = (row below) -
-// (row above); mag = sqrt(gx^2 + gy^2); mask = mag > thr.  Per-block count and
-// sum go to partials; the last block combines them in block order.
+// (row above); mag = sqrt(gx^2 + gy^2); mask = mag > thr.  Each block writes
+// its count and its magnitude sum (fixed-order block reduction).
 __global__ __launch_bounds__(kBlock) void k_sobel_thresh_f32(SobelArgs a) {
   constexpr int IW = kSobelTW + 2, IH = kSobelTH + 2;
   __shared__ float t[IH][IW + 1];
@@ -244,7 +253,6 @@ __global__ __launch_bounds__(kBlock) void k_sobel_thresh_f32(SobelArgs a) {
       sum += mag;
     }
   }
-  const unsigned nb = gridDim.x * gridDim.y;
   const unsigned b = blockIdx.y * gridDim.x + blockIdx.x;
   const float bs = block_sum_f32(sum, s4f);
   const uint32_t bc = block_sum_u32(cnt, s4u);
@@ -252,21 +260,24 @@ __global__ __launch_bounds__(kBlock) void k_sobel_thresh_f32(SobelArgs a) {
     a.psum[b] = bs;
     a.pcount[b] = bc;
   }
-  if (last_block_arrive(a.counter, nb)) {
-    float s = 0.f;
-    uint32_t c = 0;
-    for (unsigned k = threadIdx.x; k < nb; k += kBlock) {
-      s += a.psum[k];
-      c += a.pcount[k];
-    }
-    s = block_sum_f32(s, s4f);
-    c = block_sum_u32(c, s4u);
-    if (threadIdx.x == 0) {
-      *a.out_count = c;
-      *a.out_sum = s;
-      *a.counter = 0u;
-      publish_out(a.sc, true);
-    }
+}
+
+// One block: fixed-order combination of the per-block count and sum.
+__global__ __launch_bounds__(kBlock) void k_sobel_final(SobelFinalArgs a) {
+  __shared__ float s4f[4];
+  __shared__ uint32_t s4u[4];
+  float s = 0.f;
+  uint32_t c = 0;
+  for (unsigned k = threadIdx.x; k < a.nblocks; k += kBlock) {
+    s += a.psum[k];
+    c += a.pcount[k];
+  }
+  s = block_sum_f32(s, s4f);
+  c = block_sum_u32(c, s4u);
+  if (threadIdx.x == 0) {
+    *a.out_count = c;
+    *a.out_sum = s;
+    publish_out(a.sc, true);
   }
 }
 
@@ -276,7 +287,7 @@ __global__ __launch_bounds__(kBlock) void k_sobel_thresh_f32(SobelArgs a) {
 __global__ __launch_bounds__(kBlock) void k_saxpy_tanh_sum_f32(VecArgs a) {
   __shared__ float s4f[4];
   const JobScalars js = a.js;
-  if (blockIdx.x == 0 && threadIdx.x == 0) write_slot_hdr(a.sc.hdr, js);
+  if (blockIdx.x == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, js);
   const uint64_t n = js.n;
   const unsigned G = gridDim.x;
   const uint64_t C = vec_chunk(n, G);
@@ -305,126 +316,190 @@ __global__ __launch_bounds__(kBlock) void k_saxpy_tanh_sum_f32(VecArgs a) {
   }
   const float bs = block_sum_f32(acc, s4f);
   if (threadIdx.x == 0) a.partials[blockIdx.x] = bs;
-  if (last_block_arrive(a.counter, G)) {
-    float s = 0.f;
-    for (unsigned k = threadIdx.x; k < G; k += kBlock) s += a.partials[k];
-    s = block_sum_f32(s, s4f);
-    if (threadIdx.x == 0) {
-      *a.out_sum = s;
-      *a.counter = 0u;
-      publish_out(a.sc, true);
+}
+
+// One block: the job's partials (vec_blocks(n) of them) in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_vec_final(VecFinalArgs a) {
+  __shared__ float s4f[4];
+  const unsigned G = vec_blocks(a.sc.hdr->n);
+  float s = 0.f;
+  for (unsigned k = threadIdx.x; k < G; k += kBlock) s += a.partials[k];
+  s = block_sum_f32(s, s4f);
+  if (threadIdx.x == 0) {
+    *a.out_sum = s;
+    publish_out(a.sc, true);
+  }
+}
+
+// ------------------------------------------------------------------ vector batch: persistent (job, tile) kernel
+// Every block loops: take the next work item from the batch's counter, find
+// its job by binary search over the descriptors' first-item indices, reduce
+// that item's elements (fixed order within the item) and store the item's
+// partial.  Which block takes which item does not change any result.
+__device__ inline float vec_range_sum(const float* __restrict__ x, const float* __restrict__ y, float av,
+                                      uint64_t beg, uint64_t end, bool aligned) {
+  float acc = 0.f;
+  if (aligned) {
+    const uint64_t vend = beg + ((end - beg) & ~3ull);
+    for (uint64_t i = beg + 4ull * threadIdx.x; i < vend; i += 4ull * kBlock) {
+      const float4 xv = *reinterpret_cast<const float4*>(x + i);
+      const float4 yv = *reinterpret_cast<const float4*>(y + i);
+      acc += tanhf(fmaf(av, xv.x, yv.x));
+      acc += tanhf(fmaf(av, xv.y, yv.y));
+      acc += tanhf(fmaf(av, xv.z, yv.z));
+      acc += tanhf(fmaf(av, xv.w, yv.w));
     }
+    if (threadIdx.x == 0)
+      for (uint64_t i = vend; i < end; ++i) acc += tanhf(fmaf(av, x[i], y[i]));
+  } else {
+    for (uint64_t i = beg + threadIdx.x; i < end; i += kBlock) acc += tanhf(fmaf(av, x[i], y[i]));
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_vec_batch_tiles(VecBatchArgs a) {
+  __shared__ float s4f[4];
+  __shared__ uint32_t s_item;
+  __shared__ uint32_t s_job;
+  if (blockIdx.x == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
+  const VecBatchHdr* H = reinterpret_cast<const VecBatchHdr*>(a.tab);
+  const VecBatchDesc* D = reinterpret_cast<const VecBatchDesc*>(a.tab + sizeof(VecBatchHdr));
+  const uint32_t count = H->count, TE = H->tile_elems, T = H->total_tiles;
+  while (true) {
+    if (threadIdx.x == 0) {
+      const uint32_t t = __hip_atomic_fetch_add(a.work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_item = t;
+      if (t < T) {
+        uint32_t lo = 0, hi = count - 1;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi + 1) >> 1;
+          if (D[mid].tile_start <= t) lo = mid; else hi = mid - 1;
+        }
+        s_job = lo;
+      }
+    }
+    __syncthreads();
+    const uint32_t t = s_item;
+    if (t >= T) break;
+    const VecBatchDesc d = D[s_job];
+    const uint64_t beg = (uint64_t)(t - d.tile_start) * TE;
+    const uint64_t end = beg + TE < d.n ? beg + TE : (uint64_t)d.n;
+    const float acc = vec_range_sum(a.x + d.x_off, a.y + d.y_off, d.a, beg, end, ((d.x_off | d.y_off) & 3u) == 0);
+    const float bs = block_sum_f32(acc, s4f);
+    if (threadIdx.x == 0) a.partials[t] = bs;
+    __syncthreads();
+  }
+}
+
+// Job j = thread: its items' partials added in item order.  Block 0 also
+// rewinds the work counter for the slot's next batch and publishes the header.
+__global__ __launch_bounds__(kBlock) void k_vec_batch_final(VecBatchFinalArgs a) {
+  const VecBatchHdr* H = reinterpret_cast<const VecBatchHdr*>(a.tab);
+  const VecBatchDesc* D = reinterpret_cast<const VecBatchDesc*>(a.tab + sizeof(VecBatchHdr));
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < H->count) {
+    const VecBatchDesc d = D[j];
+    float s = 0.f;
+    for (uint32_t k = 0; k < d.ntiles; ++k) s += a.partials[d.tile_start + k];
+    a.results[j] = s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *a.work = 0u;
+    publish_out(a.sc, true);
   }
 }
 
 // ------------------------------------------------------------------ inclusive scan int32 -> int64
-// Single pass with decoupled look-back: tiles are numbered in arrival order
-// (an atomic counter), so every tile a block waits on belongs to a block that
-// is already running and publishes its tile sum before looking back itself.
-// Tile state words carry the job's epoch (its slot sequence number), so
-// states left by the slot's previous job are never mistaken for this job's.
-namespace {
-constexpr uint32_t kTileAgg = 1u, kTileInc = 2u;
-constexpr uint32_t kScanSpinLimit = 1u << 20;
-}  // namespace
+// Reduce-then-scan: tile sums, an exclusive scan of the tile sums in one
+// block, then each tile scans itself from its offset.  Integer addition is
+// exact, so any order gives the same sums; no block waits on another.
 
-__global__ __launch_bounds__(kBlock) void k_scan_i32_i64(ScanArgs a) {
-  __shared__ uint32_t s_tile;
-  __shared__ int64_t s_wave[4];
-  __shared__ int64_t s_excl;
-  const JobScalars js = a.js;
-  const uint64_t n = js.n;
-  const unsigned ntiles = gridDim.x;
-  const uint32_t epoch = (uint32_t)(js.seq & 0x3FFFFFFFull);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) s_tile = __hip_atomic_fetch_add(a.tile_counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  const unsigned t = s_tile;
-  if (t == 0 && tid == 0) write_slot_hdr(a.sc.hdr, js);
-
+// Loads the kScanItems values thread tid owns in tile t (zeros past n).
+__device__ inline void scan_load(const int32_t* in, uint64_t n, unsigned t, int tid, int64_t v[kScanItems]) {
   const uint64_t base = (uint64_t)t * kScanTile + (uint64_t)tid * kScanItems;
-  int64_t v[kScanItems];
   if (base + kScanItems <= n) {
-    const int4 p0 = *reinterpret_cast<const int4*>(a.in + base);
-    const int4 p1 = *reinterpret_cast<const int4*>(a.in + base + 4);
+    const int4 p0 = *reinterpret_cast<const int4*>(in + base);
+    const int4 p1 = *reinterpret_cast<const int4*>(in + base + 4);
     v[0] = p0.x; v[1] = p0.y; v[2] = p0.z; v[3] = p0.w;
     v[4] = p1.x; v[5] = p1.y; v[6] = p1.z; v[7] = p1.w;
   } else {
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? (int64_t)a.in[base + k] : 0;
+    for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? (int64_t)in[base + k] : 0;
   }
-#pragma unroll
-  for (int k = 1; k < kScanItems; ++k) v[k] += v[k - 1];
-  const int64_t tsum = v[kScanItems - 1];
-  int64_t xs = tsum;
+}
+
+// Exclusive block scan of one int64 per thread; returns the thread's exclusive
+// prefix and the block total.
+__device__ inline int64_t block_exclusive_i64(int64_t x, int64_t* s_wave, int64_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t inc = x;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
-    const int64_t yv = __shfl_up(xs, off, 64);
-    if (lane >= off) xs += yv;
+    const int64_t y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
   }
-  if (lane == 63) s_wave[wave] = xs;
+  __syncthreads();
+  if (lane == 63) s_wave[wave] = inc;
   __syncthreads();
   int64_t wave_excl = 0;
   for (int i = 0; i < wave; ++i) wave_excl += s_wave[i];
-  const int64_t block_total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
-  const int64_t thread_excl = wave_excl + xs - tsum;
+  *total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+  return wave_excl + inc - x;
+}
 
-  if (wave == 0) {
-    int64_t excl = 0;
-    if (t == 0) {
-      if (lane == 0) {
-        __hip_atomic_store(&a.tile_inc[0], block_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&a.tile_status[0], (epoch << 2) | kTileInc, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    } else {
-      if (lane == 0) {
-        __hip_atomic_store(&a.tile_agg[t], block_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&a.tile_status[t], (epoch << 2) | kTileAgg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      int64_t j = (int64_t)t - 1;
-      uint32_t spins = 0;
-      bool failed = false;
-      while (true) {
-        const int64_t idx = j - lane;
-        uint32_t st = kTileInc;
-        int64_t val = 0;
-        if (idx >= 0) {
-          const uint32_t w = __hip_atomic_load(&a.tile_status[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-          st = ((w >> 2) == epoch) ? (w & 3u) : 0u;
-          if (st == kTileInc)
-            val = __hip_atomic_load(&a.tile_inc[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          else if (st == kTileAgg)
-            val = __hip_atomic_load(&a.tile_agg[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        const uint64_t inc = __ballot(st == kTileInc);
-        const uint64_t inv = __ballot(st == 0u);
-        const int first = inc ? (__ffsll((unsigned long long)inc) - 1) : 64;
-        const uint64_t upto = (first >= 63) ? ~0ull : ((2ull << first) - 1ull);
-        if (inv & upto) {
-          if (++spins > kScanSpinLimit) {
-            failed = true;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        int64_t contrib = (lane <= first) ? val : 0;
+__global__ __launch_bounds__(kBlock) void k_scan_reduce_i32(ScanReduceArgs a) {
+  __shared__ int64_t s_wave[4];
+  const JobScalars js = a.js;
+  const unsigned t = blockIdx.x;
+  if (t == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, js);
+  if ((uint64_t)t * kScanTile >= js.n) return;
+  int64_t v[kScanItems];
+  scan_load(a.in, js.n, t, threadIdx.x, v);
+  int64_t s = 0;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off, 64);
-        excl += contrib;
-        if (first < 64) break;
-        j -= 64;
-      }
-      if (failed && lane == 0) __hip_atomic_store(a.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (lane == 0) {
-        __hip_atomic_store(&a.tile_inc[t], excl + block_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&a.tile_status[t], (epoch << 2) | kTileInc, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      }
+  for (int k = 0; k < kScanItems; ++k) s += v[k];
+  int64_t total;
+  block_exclusive_i64(s, s_wave, &total);
+  if (threadIdx.x == 0) a.tile_sum[t] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_spine_i64(ScanSpineArgs a) {
+  __shared__ int64_t s_wave[4];
+  const unsigned T = scan_tiles(a.sc.hdr->n);
+  int64_t carry = 0;
+  for (unsigned base = 0; base < T; base += kScanTile) {
+    int64_t v[kScanItems];
+    const unsigned i0 = base + threadIdx.x * kScanItems;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) v[k] = (i0 + k < T) ? a.tile_sum[i0 + k] : 0;
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) s += v[k];
+    int64_t total;
+    const int64_t ex = block_exclusive_i64(s, s_wave, &total);
+    int64_t run = carry + ex;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      if (i0 + k < T) a.tile_excl[i0 + k] = run;
+      run += v[k];
     }
-    if (lane == 0) s_excl = excl;
+    carry += total;
   }
-  __syncthreads();
-  const int64_t off0 = s_excl + thread_excl;
+  if (threadIdx.x == 0) publish_out(a.sc, true);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down_i32_i64(ScanDownArgs a) {
+  __shared__ int64_t s_wave[4];
+  const uint64_t n = a.hdr->n;
+  const unsigned t = blockIdx.x;
+  if ((uint64_t)t * kScanTile >= n) return;
+  int64_t v[kScanItems];
+  scan_load(a.in, n, t, threadIdx.x, v);
+#pragma unroll
+  for (int k = 1; k < kScanItems; ++k) v[k] += v[k - 1];
+  int64_t total;
+  const int64_t off0 = a.tile_excl[t] + block_exclusive_i64(v[kScanItems - 1], s_wave, &total);
+  const uint64_t base = (uint64_t)t * kScanTile + (uint64_t)threadIdx.x * kScanItems;
   if (!a.low32) {
     int64_t* o = reinterpret_cast<int64_t*>(a.out);
     if (base + kScanItems <= n) {
@@ -446,15 +521,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_i32_i64(ScanArgs a) {
     } else {
       for (int k = 0; k < kScanItems; ++k)
         if (base + k < n) o[base + k] = (uint32_t)(off0 + v[k]);
-    }
-  }
-  if (last_block_arrive(a.done_counter, ntiles)) {
-    if (tid == 0) {
-      const bool ok = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
-      *a.tile_counter = 0u;
-      *a.done_counter = 0u;
-      *a.err = 0u;
-      publish_out(a.sc, ok);
     }
   }
 }

@@ -37,7 +37,10 @@ struct HistArgs {
   const uint8_t* Q;
   int64_t npix;
   uint32_t* partials;  // [grid][256]
-  uint32_t* counter;
+};
+struct HistFinalArgs {
+  const uint32_t* partials;
+  unsigned nblocks;
   uint32_t* H;         // output payload
   SlotConst sc;
 };
@@ -56,7 +59,11 @@ struct SobelArgs {
   float thr;
   uint32_t* pcount;    // [grid]
   float* psum;         // [grid]
-  uint32_t* counter;
+};
+struct SobelFinalArgs {
+  const uint32_t* pcount;
+  const float* psum;
+  unsigned nblocks;
   uint32_t* out_count; // output payload
   float* out_sum;
   SlotConst sc;
@@ -65,31 +72,75 @@ struct VecArgs {
   const float* x;      // pool base
   const float* y;
   float* partials;     // [grid]
-  uint32_t* counter;
-  float* out_sum;
-  SlotConst sc;
+  DevSlotHdr* hdr;
   JobScalars js;       // n, a, x_off, y_off
 };
-struct ScanArgs {
-  const int32_t* in;
-  void* out;           // int64[n], or uint32[n] low words
-  uint32_t* tile_status;  // [ntiles] (epoch << 2) | state
-  int64_t* tile_agg;      // [ntiles] tile sums
-  int64_t* tile_inc;      // [ntiles] inclusive prefixes
-  uint32_t* tile_counter;
-  uint32_t* done_counter;
-  uint32_t* err;          // set when a look-back exceeded its spin bound
-  int low32;
+struct VecFinalArgs {
+  const float* partials;  // [vec_blocks(n)], n read from the slot header
+  float* out_sum;
   SlotConst sc;
-  JobScalars js;       // n, seq (epoch)
 };
+struct VecBatchArgs {
+  const uint8_t* tab;  // descriptor table in the slot (VecBatchHdr + VecBatchDesc[count])
+  const float* x;
+  const float* y;
+  float* partials;     // [total_tiles]
+  uint32_t* work;      // work-item counter (zero between batches)
+  DevSlotHdr* hdr;
+  JobScalars js;
+};
+struct VecBatchFinalArgs {
+  const uint8_t* tab;
+  const float* partials;
+  uint32_t* work;
+  float* results;      // output payload, one float per job
+  SlotConst sc;
+};
+// Scan as reduce -> spine -> downsweep; all three are launched with the grid
+// of the template's largest n and read the job's n from the slot header, so a
+// job of any length needs no grid update.
+struct ScanReduceArgs {
+  const int32_t* in;
+  int64_t* tile_sum;   // [tiles]
+  unsigned max_tiles;
+  DevSlotHdr* hdr;
+  JobScalars js;
+};
+struct ScanSpineArgs {
+  const int64_t* tile_sum;
+  int64_t* tile_excl;  // [tiles] exclusive prefix of tile sums
+  SlotConst sc;
+};
+struct ScanDownArgs {
+  const int32_t* in;
+  const int64_t* tile_excl;
+  void* out;           // int64[n], or uint32[n] low words
+  int low32;
+  const DevSlotHdr* hdr;
+};
+
+// Host<->device copy as a kernel: a small grid of 16-byte loads/stores that
+// keeps PCIe busy without occupying the whole device.
+struct CopyArgs {
+  const void* src;
+  void* dst;
+  uint64_t bytes;
+};
+__global__ void k_copy_bytes(CopyArgs a);
 
 __global__ void k_box3_u8_u16(BoxArgs a);
 __global__ void k_div9_u16_u8(Div9Args a);
 __global__ void k_hist256_u8(HistArgs a);
+__global__ void k_hist256_final(HistFinalArgs a);
 __global__ void k_gauss5_f32(GaussArgs a);
 __global__ void k_sobel_thresh_f32(SobelArgs a);
+__global__ void k_sobel_final(SobelFinalArgs a);
 __global__ void k_saxpy_tanh_sum_f32(VecArgs a);
-__global__ void k_scan_i32_i64(ScanArgs a);
+__global__ void k_vec_final(VecFinalArgs a);
+__global__ void k_vec_batch_tiles(VecBatchArgs a);
+__global__ void k_vec_batch_final(VecBatchFinalArgs a);
+__global__ void k_scan_reduce_i32(ScanReduceArgs a);
+__global__ void k_scan_spine_i64(ScanSpineArgs a);
+__global__ void k_scan_down_i32_i64(ScanDownArgs a);
 
 }  // namespace setrt

@@ -33,10 +33,18 @@ int pipeline_validate(const set_job_template& t, std::string* why) {
     case SET_PIPE_SCAN_I32_I64:
       if (t.max_n < 1 || t.max_n > (1ull << 31)) return bad("scan template needs 1 <= max_n <= 2^31");
       break;
+    case SET_PIPE_SAXPY_BATCH_F32:
+      if (t.max_n < 1 || t.max_n > (1ull << 32) - 1) return bad("vector batch template needs 1 <= max_n < 2^32");
+      if (t.dev_x_pool == nullptr || t.dev_y_pool == nullptr || t.pool_len < 1)
+        return bad("vector batch template needs device x/y pools");
+      if (t.batch_max < 1 || t.batch_max > (1u << 20)) return bad("vector batch template needs 1 <= batch_max <= 2^20");
+      if (t.tiles_max < t.batch_max || t.tiles_max > (1u << 26)) return bad("vector batch needs batch_max <= tiles_max <= 2^26");
+      break;
     default:
       return bad("unknown pipeline");
   }
   if (t.flags & ~(uint32_t)(SET_TF_DEBUG | SET_TF_SCAN_LOW32)) return bad("unknown template flags");
+  if (t.copy_mode != SET_COPY_NODES && t.copy_mode != SET_COPY_KERNELS) return bad("unknown copy mode");
   return SET_OK;
 }
 
@@ -70,7 +78,7 @@ static SlotLayout layout_of(const set_job_template& t) {
         off = up(off + npix);
       }
       L.scratch = off;
-      L.scratch_bytes = up((uint64_t)hist_blocks((int64_t)npix) * 256 * 4) + kAlign;  // partials + counter
+      L.scratch_bytes = up((uint64_t)hist_blocks((int64_t)npix) * 256 * 4);  // per-block partial histograms
       off = up(off + L.scratch_bytes);
       break;
     }
@@ -99,7 +107,7 @@ static SlotLayout layout_of(const set_job_template& t) {
       const Grid3 g = sobel_grid((int)t.height, (int)t.width);
       const uint64_t nb = (uint64_t)g.x * g.y;
       L.scratch = off;
-      L.scratch_bytes = up(nb * 4) + up(nb * 4) + kAlign;  // pcount, psum, counter
+      L.scratch_bytes = up(nb * 4) + up(nb * 4);  // per-block count, per-block sum
       off = up(off + L.scratch_bytes);
       break;
     }
@@ -110,7 +118,19 @@ static SlotLayout layout_of(const set_job_template& t) {
       L.out_cap = 64 + 4;
       off = up(off + L.out_cap);
       L.scratch = off;
-      L.scratch_bytes = up((uint64_t)kVecGridCap * 4) + kAlign;  // partials + counter
+      L.scratch_bytes = up((uint64_t)kVecGridCap * 4);  // per-block partial sums
+      off = up(off + L.scratch_bytes);
+      break;
+    }
+    case SET_PIPE_SAXPY_BATCH_F32: {
+      L.in = off;
+      L.in_cap = 64 + 32ull * t.batch_max;
+      off = up(off + L.in_cap);
+      L.out = off;
+      L.out_cap = 64 + 4ull * t.batch_max;
+      off = up(off + L.out_cap);
+      L.scratch = off;
+      L.scratch_bytes = up(4ull * t.tiles_max) + kAlign;  // per-work-item partials, work counter
       off = up(off + L.scratch_bytes);
       break;
     }
@@ -124,8 +144,7 @@ static SlotLayout layout_of(const set_job_template& t) {
       L.out_cap = 64 + ((t.flags & SET_TF_SCAN_LOW32) ? 4 * n : 8 * n);
       off = up(off + L.out_cap);
       L.scratch = off;
-      // status[tiles] u32, agg[tiles] i64, inc[tiles] i64, tile counter, done counter, err
-      L.scratch_bytes = up(tiles * 4) + up(tiles * 8) + up(tiles * 8) + kAlign;
+      L.scratch_bytes = up(tiles * 8) + up(tiles * 8);  // tile sums, exclusive tile offsets
       off = up(off + L.scratch_bytes);
       break;
     }
@@ -150,6 +169,8 @@ uint64_t pipeline_in_bytes(const set_job_template& t, uint64_t n) {
       return 0;
     case SET_PIPE_SCAN_I32_I64:
       return 4ull * (n ? n : t.max_n);
+    case SET_PIPE_SAXPY_BATCH_F32:
+      return 64 + 32ull * n;
   }
   return 0;
 }
@@ -163,6 +184,8 @@ uint64_t pipeline_out_bytes(const set_job_template& t, uint64_t n) {
       return 64 + 4;
     case SET_PIPE_SCAN_I32_I64:
       return 64 + ((t.flags & SET_TF_SCAN_LOW32) ? 4ull : 8ull) * (n ? n : t.max_n);
+    case SET_PIPE_SAXPY_BATCH_F32:
+      return 64 + 4ull * n;
   }
   return 0;
 }
@@ -182,9 +205,13 @@ int pipeline_validate_job(const set_job_template& t, const set_job_args& a, std:
     if (n == 0) n = t.max_n;
     if (n > t.max_n) return bad("scan job n exceeds template max_n");
   }
+  if (t.pipeline == SET_PIPE_SAXPY_BATCH_F32 && (n < 1 || n > t.batch_max))
+    return bad("vector batch job needs 1 <= n (jobs in the batch) <= batch_max");
   const uint64_t ib = pipeline_in_bytes(t, n), ob = pipeline_out_bytes(t, n);
   if (ib > 0 && (a.host_in == nullptr || a.in_bytes != ib)) return bad("host_in missing or in_bytes mismatch");
   if (a.host_out == nullptr || a.out_bytes < ob) return bad("host_out missing or out_bytes too small");
+  if (t.copy_mode == SET_COPY_KERNELS && ((((uintptr_t)a.host_in) | ((uintptr_t)a.host_out)) & 15u))
+    return bad("copy kernels need 16-byte aligned host buffers");
   return SET_OK;
 }
 
@@ -200,21 +227,41 @@ int pipeline_sizes(const set_job_template& t, TemplateSizes* out) {
   };
   const uint64_t npix = (uint64_t)t.width * t.height;
   switch (t.pipeline) {
-    case SET_PIPE_BOX_HIST_U8:
+    case SET_PIPE_BOX_HIST_U8: {
+      const uint64_t hb = hist_blocks((int64_t)npix);
       stage("box3_u8_u16", npix + 2 * npix);
       stage("div9_u16_u8", 2 * npix + npix);
-      stage("hist256_u8", npix + 1024);
+      stage("hist256_u8", npix + hb * 1024);
+      stage("hist256_final", hb * 1024 + 1024 + 64);
       break;
-    case SET_PIPE_GAUSS_SOBEL_F32:
+    }
+    case SET_PIPE_GAUSS_SOBEL_F32: {
+      const Grid3 g = sobel_grid((int)t.height, (int)t.width);
+      const uint64_t nb = (uint64_t)g.x * g.y;
       stage("gauss5_f32", 4 * npix + 4 * npix);
-      stage("sobel_thresh_f32", 4 * npix + npix + 8);
+      stage("sobel_thresh_f32", 4 * npix + npix + 8 * nb);
+      stage("sobel_final", 8 * nb + 8 + 64);
       break;
-    case SET_PIPE_SAXPY_TANH_SUM_F32:
-      stage("saxpy_tanh_sum_f32", 8 * t.max_n + 4);
+    }
+    case SET_PIPE_SAXPY_TANH_SUM_F32: {
+      const uint64_t G = vec_blocks(t.max_n);
+      stage("saxpy_tanh_sum_f32", 8 * t.max_n + 4 * G);
+      stage("vec_final", 4 * G + 4 + 64);
       break;
-    case SET_PIPE_SCAN_I32_I64:
-      stage("scan_i32_i64", 4 * t.max_n + ((t.flags & SET_TF_SCAN_LOW32) ? 4 : 8) * t.max_n);
+    }
+    case SET_PIPE_SAXPY_BATCH_F32:
+      // the streamed bytes depend on the batch (8 bytes per element of every job)
+      stage("vec_batch_tiles", 64 + 32ull * t.batch_max + 4ull * t.tiles_max);
+      stage("vec_batch_final", 64 + 32ull * t.batch_max + 4ull * t.tiles_max + 4ull * t.batch_max);
       break;
+    case SET_PIPE_SCAN_I32_I64: {
+      const uint64_t T = scan_tiles(t.max_n);
+      const uint64_t ob = ((t.flags & SET_TF_SCAN_LOW32) ? 4 : 8) * t.max_n;
+      stage("scan_reduce_i32", 4 * t.max_n + 8 * T);
+      stage("scan_spine_i64", 16 * T + 64);
+      stage("scan_down_i32_i64", 4 * t.max_n + 8 * T + ob);
+      break;
+    }
   }
   *out = s;
   return SET_OK;

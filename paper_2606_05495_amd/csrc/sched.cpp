@@ -695,6 +695,113 @@ class Context {
     return rc;
   }
 
+  // ------------------------------------------------------------------ bucketed persistent batching
+  int run_vector_jobs(int tmpl, const set_vec_job* jobs, uint64_t count, float* results, const set_vec_tuning* tune,
+                      uint64_t* nbatches_out) {
+    int st = check_sticky();
+    if (st != SET_OK) return st;
+    if (tmpl < 0 || tmpl >= (int)templates.size()) return fail(SET_EINVAL, "unknown template id");
+    const set_job_template& t = templates[tmpl];
+    if (t.pipeline != SET_PIPE_SAXPY_BATCH_F32) return fail(SET_EINVAL, "template is not a vector batch template");
+    if (count && (!jobs || !results)) return fail(SET_EINVAL, "null jobs or results");
+    std::vector<std::vector<uint32_t>> buckets(64);
+    for (uint64_t i = 0; i < count; ++i) {
+      const set_vec_job& j = jobs[i];
+      if (j.n < 1 || j.n > t.max_n) return fail(SET_EINVAL, "vector job n outside [1, max_n]");
+      if (j.x_off > t.pool_len || j.n > t.pool_len - j.x_off || j.y_off > t.pool_len || j.n > t.pool_len - j.y_off)
+        return fail(SET_EINVAL, "vector job window outside the pool");
+      buckets[63 - __builtin_clzll(j.n)].push_back((uint32_t)i);
+    }
+    struct Plan {
+      uint32_t te, grid;
+      std::vector<uint32_t> idx;
+      uint32_t tiles;
+    };
+    std::vector<Plan> plans;
+    for (int bk = 0; bk < 64; ++bk) {
+      if (buckets[bk].empty()) continue;
+      uint32_t te = (tune && tune->tile_elems[bk]) ? tune->tile_elems[bk] : vec_default_tile(bk);
+      uint32_t grid = (tune && tune->grid[bk]) ? tune->grid[bk] : (t.grid > 0 ? (uint32_t)t.grid : kVecBatchGrid);
+      if (te % 1024 != 0 || grid < 1) return fail(SET_EINVAL, "tile_elems must be a positive multiple of 1024");
+      Plan cur{te, grid, {}, 0};
+      for (uint32_t i : buckets[bk]) {
+        const uint64_t nt = (jobs[i].n + te - 1) / te;
+        if (nt > t.tiles_max) return fail(SET_EINVAL, "a job needs more work items than tiles_max");
+        if (cur.idx.size() >= t.batch_max || cur.tiles + nt > t.tiles_max) {
+          plans.push_back(std::move(cur));
+          cur = Plan{te, grid, {}, 0};
+        }
+        cur.idx.push_back(i);
+        cur.tiles += (uint32_t)nt;
+      }
+      if (!cur.idx.empty()) plans.push_back(std::move(cur));
+    }
+    auto up64 = [](uint64_t v) { return (v + 63) / 64 * 64; };
+    uint64_t total = 0;
+    for (const Plan& pl : plans) total += up64(64 + 32ull * pl.idx.size()) + up64(64 + 4ull * pl.idx.size());
+    if (plans.empty()) {
+      if (nbatches_out) *nbatches_out = 0;
+      return SET_OK;
+    }
+    char* stage_mem = (char*)be->alloc_host(total);
+    if (!stage_mem) return fail(SET_ENOMEM, "pinned staging for descriptor tables");
+    std::vector<char*> outs(plans.size());
+    uint64_t off = 0;
+    int rc = SET_OK;
+    for (size_t k = 0; k < plans.size() && rc == SET_OK; ++k) {
+      const Plan& pl = plans[k];
+      const uint32_t c = (uint32_t)pl.idx.size();
+      char* tab = stage_mem + off;
+      off += up64(64 + 32ull * c);
+      outs[k] = stage_mem + off;
+      off += up64(64 + 4ull * c);
+      VecBatchHdr* H = reinterpret_cast<VecBatchHdr*>(tab);
+      std::memset(H, 0, sizeof(*H));
+      H->count = c;
+      H->tile_elems = pl.te;
+      H->total_tiles = pl.tiles;
+      VecBatchDesc* D = reinterpret_cast<VecBatchDesc*>(tab + sizeof(VecBatchHdr));
+      uint32_t ts = 0;
+      for (uint32_t q = 0; q < c; ++q) {
+        const set_vec_job& j = jobs[pl.idx[q]];
+        D[q].x_off = j.x_off;
+        D[q].y_off = j.y_off;
+        D[q].n = (uint32_t)j.n;
+        D[q].a = j.a;
+        D[q].tile_start = ts;
+        D[q].ntiles = (uint32_t)((j.n + pl.te - 1) / pl.te);
+        ts += D[q].ntiles;
+      }
+      set_job_args a;
+      std::memset(&a, 0, sizeof(a));
+      a.host_in = tab;
+      a.in_bytes = 64 + 32ull * c;
+      a.host_out = outs[k];
+      a.out_bytes = 64 + 4ull * c;
+      a.n = c;
+      a.worker_hint = -1;
+      a.grid = pl.grid;
+      a.user_tag = k;
+      rc = submit(tmpl, &a, 0, nullptr);
+    }
+    int drc = drain(-1);
+    if (rc == SET_OK) rc = drc;
+    if (rc == SET_OK) {
+      for (size_t k = 0; k < plans.size(); ++k) {
+        const set_out_header* h = reinterpret_cast<const set_out_header*>(outs[k]);
+        if (h->magic != SET_OUT_MAGIC || h->canary_ok != 1 || h->user_tag != k) {
+          rc = fail(SET_EDEVICE, "vector batch output header check failed");
+          break;
+        }
+        const float* r = reinterpret_cast<const float*>(outs[k] + 64);
+        for (size_t q = 0; q < plans[k].idx.size(); ++q) results[plans[k].idx[q]] = r[q];
+      }
+    }
+    be->free_host(stage_mem);
+    if (nbatches_out) *nbatches_out = plans.size();
+    return rc;
+  }
+
   int drain(int64_t timeout_ns) {
     if (cfg.mode == SET_MODE_BATCH_SYNC) {
       std::lock_guard<std::mutex> g(base_mu);
@@ -918,6 +1025,12 @@ int set_stage_info(set_ctx* c, int template_id, int* num_stages, uint64_t* bytes
     snprintf(names, (size_t)names_len, "%s", s.c_str());
   }
   return SET_OK;
+}
+
+int set_run_vector_jobs(set_ctx* c, int template_id, const set_vec_job* jobs, uint64_t count, float* results,
+                        const set_vec_tuning* tuning, uint64_t* batches) {
+  if (!c) return SET_EINVAL;
+  return c->impl.run_vector_jobs(template_id, jobs, count, results, tuning, batches);
 }
 
 const char* set_last_error(const set_ctx* c) {

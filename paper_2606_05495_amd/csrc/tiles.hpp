@@ -22,6 +22,18 @@ constexpr int kVecChunk = 2048;               // vector job: elements per block 
 constexpr int kVecGridCap = 2048;             // vector job: most blocks per job
 constexpr int kScanItems = 8;                 // scan: items per thread
 constexpr int kScanTile = kBlock * kScanItems;
+constexpr int kCopyBlocks = 32;               // host<->device copy kernels: small grid, PCIe-bound
+constexpr int kVecBatchGrid = 1024;           // persistent vector-batch kernel: default grid
+
+// Default work-item size for vector jobs of size bucket b = floor(log2 n):
+// about eight items per job, a multiple of 1024 elements, within [1024, 65536].
+inline uint32_t vec_default_tile(int b) {
+  uint64_t t = (b >= 3) ? (1ull << (b - 3)) : 1ull;
+  t = (t + 1023) / 1024 * 1024;
+  if (t < 1024) t = 1024;
+  if (t > 65536) t = 65536;
+  return (uint32_t)t;
+}
 
 struct Grid3 {
   unsigned x, y, z;
@@ -56,7 +68,7 @@ SETRT_HD inline uint64_t vec_chunk(uint64_t n, unsigned g) {
   const uint64_t q = 4ull * kBlock;
   return (c + q - 1) / q * q;
 }
-inline unsigned scan_tiles(uint64_t n) { return (unsigned)((n + kScanTile - 1) / kScanTile); }
+SETRT_HD inline unsigned scan_tiles(uint64_t n) { return (unsigned)((n + kScanTile - 1) / kScanTile); }
 
 // Byte layout of one buffer slot of a template (offsets from the slot base,
 // all 256-byte aligned).  In debug templates the intermediate images live

@@ -17,6 +17,7 @@ PIPELINES = {
     "gauss_sobel": A.SET_PIPE_GAUSS_SOBEL_F32,
     "saxpy_tanh_sum": A.SET_PIPE_SAXPY_TANH_SUM_F32,
     "scan": A.SET_PIPE_SCAN_I32_I64,
+    "saxpy_batch": A.SET_PIPE_SAXPY_BATCH_F32,
 }
 
 
@@ -84,7 +85,7 @@ class Context:
 
     # ------------------------------------------------------------ templates
     def define(self, pipeline, width=0, height=0, max_n=0, flags=0, threshold=0.0, x_pool=None, y_pool=None,
-               borrow_arena=True, pool_ptrs=None):
+               borrow_arena=True, pool_ptrs=None, copy="nodes", batch_max=0, tiles_max=0, grid=0):
         t = A.set_job_template()
         t.pipeline = PIPELINES[pipeline] if isinstance(pipeline, str) else int(pipeline)
         t.flags = flags
@@ -92,6 +93,10 @@ class Context:
         t.height = height
         t.max_n = max_n
         t.threshold = threshold
+        t.copy_mode = A.COPY_MODES[copy] if isinstance(copy, str) else int(copy)
+        t.batch_max = batch_max
+        t.tiles_max = tiles_max
+        t.grid = grid
         if x_pool is not None:
             t.dev_x_pool = x_pool.data_ptr()
             t.dev_y_pool = y_pool.data_ptr()
@@ -137,6 +142,8 @@ class Context:
             return 64 + 8
         if t.pipeline == A.SET_PIPE_SAXPY_TANH_SUM_F32:
             return 64 + 4
+        if t.pipeline == A.SET_PIPE_SAXPY_BATCH_F32:
+            return 64 + 4 * n
         lo = bool(t.flags & A.SET_TF_SCAN_LOW32)
         return 64 + (4 if lo else 8) * (n or t.max_n)
 
@@ -154,6 +161,14 @@ class Context:
 
     def submit_many(self, tid, arr, flags=0):
         return A.set_submit_many(self.h, tid, np.ascontiguousarray(arr), flags)
+
+    def run_vector_jobs(self, tid, jobs, results=None, tuning=None):
+        """Bucketed persistent batching of vector jobs (structured array of VEC_JOB_DTYPE)."""
+        jobs = np.ascontiguousarray(jobs, dtype=A.VEC_JOB_DTYPE)
+        if results is None:
+            results = np.zeros(jobs.size, np.float32)
+        nb = A.set_run_vector_jobs(self.h, tid, jobs, results, tuning)
+        return results, nb
 
     def drain(self, timeout_ns=-1):
         return A.set_drain(self.h, timeout_ns)

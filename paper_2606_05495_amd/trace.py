@@ -1,0 +1,150 @@
+"""Timeline metrics from rocprofv3 traces (kernel-trace and memory-copy-trace CSVs).
+
+Definitions (the paper gives prose definitions; these are the readings):
+
+* kernel gap -- idle time between the end of one kernel and the start of the
+  next on the GPU timeline (Section 1, the white spaces of a profiler
+  timeline).  Kernels of all streams are merged by start time; gap_k =
+  max(0, start_{k+1} - max_{i<=k} end_i).  The headline is the mean over all
+  k (zeros included); the mean of the positive gaps is reported beside it.
+* GPU-idle fraction -- 1 - |union of kernel and copy intervals| / span, the
+  reading of the scheduling-overhead fraction t_schedule / T_measured
+  (Section 5.3 with Eq. 4): T_measured is the span of the timeline and
+  T_ideal the time some engine was busy, so t_schedule = T_measured - T_ideal.
+  Compute-idle uses kernels only, copy-idle the host-to-device copies only.
+* inter-batch overhead (Eq. 3) -- for a batch-synchronised run, the start of
+  batch i+1's first copy minus the end of batch i's last copy.
+
+    python -m paper_2606_05495_amd.trace <dir with *_kernel_trace.csv>
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import json
+import os
+import sys
+from typing import Iterable, List, Sequence, Tuple
+
+Interval = Tuple[float, float]
+
+
+def union_length(intervals: Iterable[Interval]) -> float:
+    iv = sorted((a, b) for a, b in intervals if b > a)
+    total = 0.0
+    cur_a = cur_b = None
+    for a, b in iv:
+        if cur_b is None or a > cur_b:
+            if cur_b is not None:
+                total += cur_b - cur_a
+            cur_a, cur_b = a, b
+        else:
+            cur_b = max(cur_b, b)
+    if cur_b is not None:
+        total += cur_b - cur_a
+    return total
+
+
+def kernel_gaps(kernels: Sequence[Interval]) -> List[float]:
+    ks = sorted(kernels)
+    gaps = []
+    end_max = None
+    for i, (a, b) in enumerate(ks):
+        if i > 0:
+            gaps.append(max(0.0, a - end_max))
+        end_max = b if end_max is None else max(end_max, b)
+    return gaps
+
+
+def timeline_metrics(kernels: Sequence[Interval], copies_h2d: Sequence[Interval] = (),
+                     copies_d2h: Sequence[Interval] = ()) -> dict:
+    """All times in one unit (the caller's); returns the metrics in that unit."""
+    allv = list(kernels) + list(copies_h2d) + list(copies_d2h)
+    if not allv:
+        return {}
+    t0 = min(a for a, _ in allv)
+    t1 = max(b for _, b in allv)
+    span = t1 - t0
+    busy = union_length(allv)
+    gaps = kernel_gaps(kernels)
+    pos = [g for g in gaps if g > 0]
+    out = {
+        "span": span,
+        "busy": busy,
+        "gpu_idle_fraction": (1.0 - busy / span) if span > 0 else 0.0,
+        "t_schedule": span - busy,
+        "kernels": len(kernels),
+        "mean_kernel_gap": (sum(gaps) / len(gaps)) if gaps else 0.0,
+        "mean_positive_kernel_gap": (sum(pos) / len(pos)) if pos else 0.0,
+        "compute_idle_fraction": (1.0 - union_length(kernels) / span) if span > 0 and kernels else None,
+        "h2d_idle_fraction": (1.0 - union_length(copies_h2d) / span) if span > 0 and copies_h2d else None,
+        "d2h_idle_fraction": (1.0 - union_length(copies_d2h) / span) if span > 0 and copies_d2h else None,
+    }
+    return out
+
+
+def inter_batch_gaps(h2d: Sequence[Interval], d2h: Sequence[Interval], batch: int) -> List[float]:
+    """Eq. 3 for consecutive batches of `batch` jobs (copies in time order)."""
+    hs = sorted(h2d)
+    ds = sorted(d2h, key=lambda x: x[1])
+    nb = min(len(hs), len(ds)) // batch
+    starts = [hs[i * batch][0] for i in range(nb)]
+    ends = [ds[(i + 1) * batch - 1][1] for i in range(nb)]
+    return [starts[i + 1] - ends[i] for i in range(nb - 1)]
+
+
+# ------------------------------------------------------------------ rocprofv3 CSV
+def _col(row, *names):
+    for n in names:
+        if n in row and row[n] != "":
+            return row[n]
+    raise KeyError(names)
+
+
+def load_rocprof(dirpath: str, kernel_filter=None):
+    """Kernel and copy intervals (ns) from rocprofv3 --kernel-trace
+    --memory-copy-trace --output-format csv output under dirpath."""
+    kfiles = glob.glob(os.path.join(dirpath, "**", "*kernel_trace.csv"), recursive=True)
+    cfiles = glob.glob(os.path.join(dirpath, "**", "*memory_copy_trace.csv"), recursive=True)
+    kernels, names = [], []
+    for f in kfiles:
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                name = _col(row, "Kernel_Name", "Kernel_name", "KernelName")
+                if kernel_filter and not kernel_filter(name):
+                    continue
+                kernels.append((float(_col(row, "Start_Timestamp", "BeginNs")),
+                                float(_col(row, "End_Timestamp", "EndNs"))))
+                names.append(name)
+    h2d, d2h = [], []
+    for f in cfiles:
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                d = _col(row, "Direction", "Kind", "Operation")
+                iv = (float(_col(row, "Start_Timestamp", "BeginNs")), float(_col(row, "End_Timestamp", "EndNs")))
+                if "HOST_TO_DEVICE" in d.upper() or "H2D" in d.upper():
+                    h2d.append(iv)
+                elif "DEVICE_TO_HOST" in d.upper() or "D2H" in d.upper():
+                    d2h.append(iv)
+    return kernels, names, h2d, d2h
+
+
+def analyze_dir(dirpath: str, batch: int = 0) -> dict:
+    kernels, names, h2d, d2h = load_rocprof(dirpath, kernel_filter=lambda n: "setrt" in n or "k_" in n)
+    m = timeline_metrics(kernels, h2d, d2h)
+    m = {k: (v / 1e3 if k in ("span", "busy", "t_schedule", "mean_kernel_gap", "mean_positive_kernel_gap")
+             and v is not None else v) for k, v in m.items()}  # ns -> us
+    m["unit"] = "us"
+    m["h2d_copies"] = len(h2d)
+    m["d2h_copies"] = len(d2h)
+    if h2d:
+        m["h2d_busy_GBps_hint"] = None
+    if batch and h2d and d2h:
+        g = inter_batch_gaps(h2d, d2h, batch)
+        m["mean_inter_batch_us"] = (sum(g) / len(g) / 1e3) if g else None
+    return m
+
+
+if __name__ == "__main__":
+    b = int(sys.argv[2]) if len(sys.argv) > 2 else 0
+    print(json.dumps(analyze_dir(sys.argv[1], batch=b), indent=1))

@@ -48,17 +48,19 @@ def _check_header(buf, job_id, tag=None):
 
 
 # ------------------------------------------------------------------ box / histogram
-def _run_images(mode, pipeline, imgs, in_dtype, workers=4, slots=4, flags=A.SET_TF_DEBUG, **kw):
+def _run_images(mode, pipeline, imgs, in_dtype, workers=4, slots=4, flags=A.SET_TF_DEBUG, copy="nodes", **kw):
     h, w = imgs[0].shape
     ctx = Context(mode=mode, workers=workers, slots=slots, **kw)
-    tid = ctx.define(pipeline, width=w, height=h, flags=flags)
+    tid = ctx.define(pipeline, width=w, height=h, flags=flags, copy=copy)
     ib, ob = ctx.in_bytes(tid), ctx.out_bytes(tid)
     stride = _up64(ob)
-    tin, nin = pinned(ib * len(imgs))
+    istride = _up64(ib)
+    tin, nin = pinned(istride * len(imgs))
     tout, nout = pinned(stride * len(imgs))
-    nin.view(in_dtype)[:] = np.concatenate([im.ravel() for im in imgs]).view(in_dtype)
+    for i, im in enumerate(imgs):
+        nin[i * istride:i * istride + ib].view(in_dtype)[:] = im.ravel()
     arr = ctx.job_array(len(imgs))
-    arr["host_in"] = tin.data_ptr() + np.arange(len(imgs), dtype=np.uint64) * ib
+    arr["host_in"] = tin.data_ptr() + np.arange(len(imgs), dtype=np.uint64) * istride
     arr["in_bytes"] = ib
     arr["host_out"] = tout.data_ptr() + np.arange(len(imgs), dtype=np.uint64) * stride
     arr["out_bytes"] = ob
@@ -190,10 +192,11 @@ def vec_pools(torch_gpu):
     return x, y, xd, yd
 
 
-def _run_vec(mode, pools, ns, offs_x, offs_y, avals, workers=4, slots=8, policy=A.SET_SUBMIT_ROUND_ROBIN):
+def _run_vec(mode, pools, ns, offs_x, offs_y, avals, workers=4, slots=8, policy=A.SET_SUBMIT_ROUND_ROBIN,
+             copy="nodes"):
     x, y, xd, yd = pools
     ctx = Context(mode=mode, workers=workers, slots=slots, submit_policy=policy)
-    tid = ctx.define("saxpy_tanh_sum", max_n=int(max(ns)), x_pool=xd, y_pool=yd)
+    tid = ctx.define("saxpy_tanh_sum", max_n=int(max(ns)), x_pool=xd, y_pool=yd, copy=copy)
     k = len(ns)
     tout, nout = pinned(128 * k)
     arr = ctx.job_array(k)
@@ -270,9 +273,9 @@ def test_vector_workload_sample(torch_gpu, vec_pools):
 
 
 # ------------------------------------------------------------------ scan
-def _run_scan(mode, inputs, max_n, low32=False, workers=4, slots=4):
+def _run_scan(mode, inputs, max_n, low32=False, workers=4, slots=4, copy="nodes"):
     ctx = Context(mode=mode, workers=workers, slots=slots)
-    tid = ctx.define("scan", max_n=max_n, flags=A.SET_TF_SCAN_LOW32 if low32 else 0)
+    tid = ctx.define("scan", max_n=max_n, flags=A.SET_TF_SCAN_LOW32 if low32 else 0, copy=copy)
     k = len(inputs)
     ib = [4 * len(v) for v in inputs]
     ob = [ctx.out_bytes(tid, len(v)) for v in inputs]
@@ -357,3 +360,88 @@ def test_set_mode_callbacks_and_steals(torch_gpu, callback):
         assert np.array_equal(o[64:64 + 1024].view(np.uint32), oracle.box_hist(imgs[j])[2])
     assert st.completed == 96
     assert st.stolen > 0
+
+
+# ------------------------------------------------------------------ copy kernels instead of memcpy nodes
+@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "set"])
+def test_copy_kernels_all_pipelines(torch_gpu, vec_pools, mode):
+    """The same chains with the H2D/D2H performed by the small-grid copy kernels."""
+    _say("copy kernels", mode)
+    imgs8 = [synth.box_image(0, j, 37, 201) for j in range(5)]
+    outs, _ = _run_images(mode, "box_hist", imgs8, np.uint8, copy="kernels")
+    s_off = _up64(64 + 1024)
+    q_off = _up64(s_off + 2 * 37 * 201)
+    for img, o in zip(imgs8, outs):
+        S, Q, H = oracle.box_hist(img)
+        assert np.array_equal(o[64:64 + 1024].view(np.uint32), H)
+        assert np.array_equal(o[q_off:q_off + 37 * 201].reshape(37, 201), Q)
+    imgsf = [synth.normal_image(0, k, 70, 99) for k in range(5)]
+    outs, _ = _run_images(mode, "gauss_sobel", imgsf, np.float32, copy="kernels")
+    for img, o in zip(imgsf, outs):
+        _check_gauss(img, o)
+    big = [synth.normal_image(0, k) for k in range(3)]
+    outs, _ = _run_images(mode, "gauss_sobel", big, np.float32, workers=8, slots=4, flags=0, copy="kernels")
+    for img, o in zip(big, outs):
+        ref = oracle.gauss_sobel(img, want_images=False)
+        assert abs(int(o[64:68].view(np.uint32)[0]) - ref["count"]) <= ref["band"]
+        assert abs(float(o[68:72].view(np.float32)[0]) - ref["sum"]) <= 1e-5 * abs(ref["sum"])
+    rng = np.random.default_rng(11)
+    ins = [rng.integers(-(1 << 20), (1 << 20) + 1, n).astype(np.int32) for n in (1, 5, 4097, 1 << 21)]
+    for v, r in zip(ins, _run_scan(mode, ins, max_n=1 << 21, copy="kernels")):
+        assert np.array_equal(r, oracle.scan(v))
+    x, y = vec_pools[0], vec_pools[1]
+    ns = np.array([3, 4096, 70001], np.int64)
+    got, _ = _run_vec(mode, vec_pools, ns, np.array([0, 64, 128]), np.array([64, 0, 4]),
+                      np.full(3, 1.25, np.float32), copy="kernels")
+    for i, n in enumerate(ns):
+        xo, yo = [0, 64, 128][i], [64, 0, 4][i]
+        S, E = oracle.saxpy_tanh_sum(x[xo:xo + n], y[yo:yo + n], 1.25)
+        assert abs(got[i] - S) <= oracle.vec_tolerance(S, E)
+
+
+# ------------------------------------------------------------------ bucketed persistent batching
+@pytest.mark.parametrize("mode,copy", [("set", "nodes"), ("set", "kernels"), ("sync", "kernels"), ("batch", "nodes")])
+def test_vector_batching_parity(torch_gpu, vec_pools, mode, copy):
+    """Uneven vector jobs through size-bucketed persistent batches: each result matches the oracle,
+    and re-batching the same jobs in another order gives bit-identical results (a job's reduction
+    order depends only on its length and its bucket's work-item size)."""
+    _say("vector batching", mode, copy)
+    x, y, xd, yd = vec_pools
+    js = synth.vec_jobs(2, 200, pool_len=len(x))
+    jobs = np.zeros(200, dtype=A.VEC_JOB_DTYPE)
+    for f in ("n", "a", "x_off", "y_off"):
+        jobs[f] = js[f]
+    jobs["x_off"][:5] += 1  # misaligned windows take the scalar path
+    ctx = Context(mode=mode, workers=4, slots=4)
+    tid = ctx.define("saxpy_batch", max_n=1 << 22, x_pool=xd, y_pool=yd, batch_max=32, tiles_max=1024, copy=copy)
+    res, nb = ctx.run_vector_jobs(tid, jobs)
+    assert nb >= 10
+    for i in range(200):
+        n = int(jobs["n"][i])
+        xo, yo = int(jobs["x_off"][i]), int(jobs["y_off"][i])
+        S, E = oracle.saxpy_tanh_sum(x[xo:xo + n], y[yo:yo + n], jobs["a"][i])
+        assert abs(res[i] - S) <= oracle.vec_tolerance(S, E), (i, n, res[i], S, E)
+    perm = np.random.default_rng(9).permutation(200)
+    res2, _ = ctx.run_vector_jobs(tid, jobs[perm])
+    assert np.array_equal(res2, res[perm])
+    st = ctx.stats()
+    assert st.failed == 0
+    ctx.close()
+
+
+def test_vector_batching_pins(torch_gpu):
+    """Saturated tanh gives S = n exactly through the batched path too."""
+    _say("vector batching pins")
+    import torch
+    L = 1 << 22
+    ones = torch.ones(L, dtype=torch.float32, device="cuda")
+    zeros = torch.zeros(L, dtype=torch.float32, device="cuda")
+    ns = np.array([1, 3, 4096, 4097, 65536, 1 << 20, 4194303, 4194304], np.int64)
+    jobs = np.zeros(len(ns), dtype=A.VEC_JOB_DTYPE)
+    jobs["n"] = ns
+    jobs["a"] = 16.0
+    ctx = Context(mode="set", workers=2, slots=4)
+    tid = ctx.define("saxpy_batch", max_n=1 << 22, x_pool=ones, y_pool=zeros, batch_max=4, tiles_max=4096)
+    res, _ = ctx.run_vector_jobs(tid, jobs)
+    assert np.array_equal(res, ns.astype(np.float32))
+    ctx.close()

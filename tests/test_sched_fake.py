@@ -262,3 +262,58 @@ def test_thread_sanitizer_stress():
                        env=dict(os.environ, TSAN_OPTIONS="halt_on_error=1"))
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
+
+
+# ------------------------------------------------------------------ bucketed persistent batching (host planning)
+def _vec_job_array(ns, offs=0):
+    jobs = np.zeros(len(ns), dtype=A.VEC_JOB_DTYPE)
+    jobs["n"] = ns
+    jobs["a"] = 1.0
+    jobs["x_off"] = offs
+    jobs["y_off"] = offs
+    return jobs
+
+
+def test_vector_batching_plans_buckets_and_limits():
+    with _fake(workers=4, slots=4) as ctx:
+        tid = ctx.define("saxpy_batch", max_n=1 << 22, pool_ptrs=DUMMY_POOL, batch_max=16, tiles_max=256)
+        rng = np.random.default_rng(4)
+        ns = np.floor(4096 * 1024.0 ** rng.random(300)).astype(np.int64)
+        res, nb = ctx.run_vector_jobs(tid, _vec_job_array(ns))
+        # expected plan: per bucket (floor log2 n) in input order, <= 16 jobs and <= 256 items per batch
+        exp = 0
+        for b in range(64):
+            idx = [i for i, n in enumerate(ns) if int(n).bit_length() - 1 == b]
+            if not idx:
+                continue
+            te = max(1024, min(65536, ((1 << max(b - 3, 0)) + 1023) // 1024 * 1024))
+            cnt = tiles = 0
+            exp += 1
+            for i in idx:
+                nt = -(-int(ns[i]) // te)
+                if cnt >= 16 or tiles + nt > 256:
+                    exp += 1
+                    cnt = tiles = 0
+                cnt += 1
+                tiles += nt
+        assert nb == exp
+        st = ctx.stats()
+        assert st.completed == nb and st.failed == 0
+
+
+def test_vector_batching_rejects_bad_jobs_and_tuning():
+    with _fake(workers=2, slots=2) as ctx:
+        tid = ctx.define("saxpy_batch", max_n=1 << 20, pool_ptrs=DUMMY_POOL, batch_max=8, tiles_max=8)
+        with pytest.raises(A.SetError):
+            ctx.run_vector_jobs(tid, _vec_job_array([1 << 21]))  # n > max_n
+        tune = A.set_vec_tuning()
+        tune.tile_elems[12] = 1000  # not a multiple of 1024
+        with pytest.raises(A.SetError):
+            ctx.run_vector_jobs(tid, _vec_job_array([5000]), tuning=tune)
+        tune.tile_elems[12] = 1024
+        tune.tile_elems[19] = 1024  # 2^19-element job would need 512 items > tiles_max
+        with pytest.raises(A.SetError):
+            ctx.run_vector_jobs(tid, _vec_job_array([1 << 19]), tuning=tune)
+        # one bucket; default 1024-element items: 4 + 5 + 8 items > tiles_max = 8 -> three batches
+        res, nb = ctx.run_vector_jobs(tid, _vec_job_array([4096, 5000, 8191]), tuning=None)
+        assert nb == 3

@@ -1,0 +1,41 @@
+"""Timeline metrics against hand-computed timelines (tests/golden/trace_timelines.json)."""
+import json
+import os
+
+import pytest
+
+from paper_2606_05495_amd import trace
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "trace_timelines.json")))
+
+
+@pytest.mark.parametrize("case", GOLD["cases"], ids=[c["name"] for c in GOLD["cases"]])
+def test_timeline_metrics_golden(case):
+    m = trace.timeline_metrics([tuple(x) for x in case["kernels"]], [tuple(x) for x in case["h2d"]],
+                               [tuple(x) for x in case["d2h"]])
+    for k in ("mean_kernel_gap", "mean_positive_kernel_gap", "span", "busy", "gpu_idle_fraction", "t_schedule",
+              "compute_idle_fraction", "h2d_idle_fraction"):
+        if k in case:
+            assert m[k] == pytest.approx(case[k], abs=1e-12), k
+
+
+def test_inter_batch_golden():
+    ib = GOLD["inter_batch"]
+    g = trace.inter_batch_gaps([tuple(x) for x in ib["h2d"]], [tuple(x) for x in ib["d2h"]], ib["batch"])
+    assert g == pytest.approx(ib["gaps"])
+
+
+def test_union_and_gap_invariants():
+    import random
+    rnd = random.Random(7)
+    for _ in range(200):
+        iv = []
+        for _ in range(rnd.randint(1, 20)):
+            a = rnd.uniform(0, 100)
+            iv.append((a, a + rnd.uniform(0, 10)))
+        u = trace.union_length(iv)
+        span = max(b for _, b in iv) - min(a for a, _ in iv)
+        assert 0 <= u <= span + 1e-9
+        assert u <= sum(b - a for a, b in iv) + 1e-9
+        # the gaps plus the busy union tile the kernel span exactly
+        assert sum(trace.kernel_gaps(iv)) + u == pytest.approx(span)
