@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import concurrent.futures
+import ctypes
 import hashlib
 import json
 import os
@@ -172,7 +173,7 @@ def bench_vectors(args, torch):
                          "effective_GBps": round(total_bytes / dt / 1e9, 1)}
     ctx.close()
     # ---- per-job graphs / baselines on the per-job template
-    for mode in ("set", "batch", "sync"):
+    for mode in ("set", "batch", "sync", "queue"):
         c = Context(mode=mode, workers=args.workers, slots=16 if mode == "set" else 1,
                     batch_size=args.batch if mode == "batch" else 0, callback=args.callback)
         t2 = c.define("saxpy_tanh_sum", max_n=int(js["n"].max()), x_pool=xd, y_pool=yd, copy=args.copy)
@@ -202,9 +203,91 @@ def bench_vectors(args, torch):
             "speedup_vs_batch_sync": round(p / out["per_job_batch"]["jobs_per_s"], 2),
             "speedup_vs_sync": round(p / out["per_job_sync"]["jobs_per_s"], 2),
             "speedup_vs_per_job_set": round(p / out["per_job_set"]["jobs_per_s"], 2),
+            "speedup_vs_queue": round(p / out["per_job_queue"]["jobs_per_s"], 2),
             "modes": out, "config": {"workers": args.workers, "batch_max": args.batch_max,
                                      "tiles_max": args.tiles_max, "copy": args.copy, "callback": args.callback,
                                      "tuned": tuning is not None}}
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args, torch):
+    """Open-loop serving: Poisson arrivals at each rate for a fixed window; half
+    image jobs (Gaussian/Sobel at 256^2, 512^2, 1024^2, 2048^2, uniform) and
+    half vector jobs (as the uneven vector family), under an 8 GB
+    device-memory admission cap.  Latency = arrival -> result in host memory."""
+    from paper_2606_05495_amd import _abi as A
+    from paper_2606_05495_amd import autotune, synth
+    from paper_2606_05495_amd.runtime import Context, pinned
+    sides = synth.SERVE_SIDES
+    P = args.serve_pool
+    log("generating serving pools (%d images per size)" % P)
+    imgs = {s_: synth.serve_image_pool(0, s_, count=P) for s_ in sides}
+    off, offs = 0, {}
+    for s_ in sides:
+        offs[s_] = off
+        off += P * 4 * s_ * s_
+    tin, nin = pinned(off)
+    for s_ in sides:
+        nin[offs[s_]:offs[s_] + P * 4 * s_ * s_].view(np.float32)[:] = imgs[s_].ravel()
+    L = synth.VEC_POOL_LEN
+    xd = torch.from_numpy(synth.vec_pool(0, "x", L)).cuda()
+    yd = torch.from_numpy(synth.vec_pool(0, "y", L)).cuda()
+    results = []
+    for rate in [float(r) for r in args.rates.split(",")]:
+        ctx = Context(mode="set", workers=args.workers, slots=args.slots, mem_budget=int(args.mem_budget),
+                      callback=args.callback, inflight=args.inflight)
+        timg = {s_: ctx.define("gauss_sobel", width=s_, height=s_, copy=args.copy) for s_ in sides}
+        tvec = ctx.define("saxpy_batch", max_n=4194303, x_pool=xd, y_pool=yd, batch_max=args.batch_max,
+                          tiles_max=args.tiles_max, copy=args.copy)
+        tuning = None if args.no_tune else autotune.load()
+        arr = synth.poisson_arrivals(int(rate), rate, args.serve_seconds)
+        n = len(arr)
+        mix = synth.serve_mix(int(rate), n)
+        vj = synth.vec_jobs(int(rate), n, pool_len=L, cfg=synth.CFG_SERVE)
+        req = np.zeros(n, dtype=A.REQUEST_DTYPE)
+        req["t_arrival_ns"] = (arr * 1e9).astype(np.uint64)
+        req["worker_hint"] = -1
+        isimg = mix["kind"] == 0
+        side = np.array(sides)[mix["side_idx"]]
+        tout, nout = pinned(128 * n)
+        req["template_id"] = np.where(isimg, [timg[s_] for s_ in side], tvec)
+        base = np.array([offs[s_] for s_ in side], dtype=np.uint64)
+        req["host_in"] = np.where(isimg, tin.data_ptr() + base + (mix["pool_idx"] % P).astype(np.uint64) *
+                                  (4 * side * side).astype(np.uint64), 0)
+        req["in_bytes"] = np.where(isimg, 4 * side * side, 0)
+        req["host_out"] = np.where(isimg, tout.data_ptr() + np.arange(n, dtype=np.uint64) * 128, 0)
+        req["out_bytes"] = np.where(isimg, 72, 0)
+        for f in ("n", "a", "x_off", "y_off"):
+            req[f] = np.where(isimg, 0, vj[f])
+        vres = np.zeros(n, np.float32)
+        cfg = A.set_serve_config()
+        if tuning is not None:
+            cfg.tuning = ctypes.pointer(tuning)
+        log("serving %.0f jobs/s: %d requests over %.1f s" % (rate, n, args.serve_seconds))
+        done, st = A.set_serve(ctx.h, req, cfg, vres)
+        ok = done > 0
+        lat = (done[ok].astype(np.float64) - req["t_arrival_ns"][ok].astype(np.float64)) / 1e3
+        span = (st.t_end_ns - st.t_start_ns) / 1e9
+        h2d_offered = float(np.sum(req["in_bytes"])) / args.serve_seconds / 1e9
+        res = {"rate": rate, "requests": int(n), "completed": int(st.completed), "failed": int(st.failed),
+               "throughput_jobs_per_s": round(st.completed / span, 1) if span > 0 else None,
+               "p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
+               "p50_image_us": round(float(np.percentile(lat[isimg[ok]], 50)), 1),
+               "p99_image_us": round(float(np.percentile(lat[isimg[ok]], 99)), 1),
+               "p50_vector_us": round(float(np.percentile(lat[~isimg[ok]], 50)), 1),
+               "p99_vector_us": round(float(np.percentile(lat[~isimg[ok]], 99)), 1),
+               "max_backlog": int(st.max_backlog), "vec_batches": int(st.vec_batches),
+               "offered_h2d_GBps": round(h2d_offered, 1), "mem_high_water_GB": round(ctx.stats().mem_high_water / 1e9, 2),
+               "drain_after_window_s": round(span - args.serve_seconds, 3)}
+        log(json.dumps(res))
+        results.append(res)
+        ctx.close()
+    line = {"metric": METRIC, "workload": "serving: Poisson arrivals, 50%% images {256,512,1024,2048}^2 + 50%% "
+            "vector jobs, %.0f GB admission cap, %.0f s window" % (args.mem_budget / 1e9, args.serve_seconds),
+            "value": results[0]["throughput_jobs_per_s"], "unit": "jobs/s", "n_gpus": 1, "dtype": "f32",
+            "data": "synthetic", "higher_is_better": True, "vs_baseline": None, "rates": results,
+            "config": {"workers": args.workers, "slots": args.slots, "copy": args.copy, "callback": args.callback,
+                       "image_pool_per_size": P}}
     print(json.dumps(line), flush=True)
 
 
@@ -219,7 +302,7 @@ def main():
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--inflight", type=int, default=0)
     ap.add_argument("--spin-us", type=int, default=0)
-    ap.add_argument("--callback", default="event_chain", choices=["event_chain", "same_stream", "event_poll"])
+    ap.add_argument("--callback", default="event_poll", choices=["event_chain", "same_stream", "event_poll"])
     ap.add_argument("--copy", default="kernels", choices=["nodes", "kernels"],
                     help="job copies as graph memcpy nodes or as small-grid copy kernels")
     ap.add_argument("--baseline-steps", type=int, default=1)
@@ -227,13 +310,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-passes", type=int, default=5)
     ap.add_argument("--stage-reps", type=int, default=200)
-    ap.add_argument("--workload", choices=["images", "vectors"], default="images")
+    ap.add_argument("--workload", choices=["images", "vectors", "serve"], default="images")
+    ap.add_argument("--rates", default="2000,10000,40000")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-pool", type=int, default=16)
+    ap.add_argument("--mem-budget", type=float, default=8e9)
     ap.add_argument("--vjobs", type=int, default=100000)
     ap.add_argument("--vsample", type=int, default=400)
     ap.add_argument("--batch-max", type=int, default=1024)
     ap.add_argument("--tiles-max", type=int, default=16384)
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--only", choices=["set", "batch", "sync"], default=None,
+    ap.add_argument("--only", choices=["set", "batch", "sync", "queue"], default=None,
                     help="run one mode only (for traced runs); prints its line")
     args = ap.parse_args()
 
@@ -249,6 +336,9 @@ def main():
     if args.workload == "vectors":
         bench_vectors(args, torch)
         return
+    if args.workload == "serve":
+        bench_serve(args, torch)
+        return
     from paper_2606_05495_amd import synth
     from paper_2606_05495_amd.runtime import pinned
     import oracle
@@ -262,7 +352,7 @@ def main():
     tout, _ = pinned(128 * args.jobs)
     refs = [oracle.gauss_sobel(imgs[k], want_images=False) for k in range(pool)]
 
-    if args.only in ("batch", "sync"):
+    if args.only in ("batch", "sync", "queue"):
         log("%s only: %d jobs x %d steps" % (args.only, args.jobs, args.steps))
         c2, _, dt2, st2, _ = run_mode(args.only, args, args.jobs, args.steps, args.warmup, tin, tout, pool, torch)
         c2.close()
@@ -293,7 +383,7 @@ def main():
 
     extra = {}
     if not args.no_baselines and args.only is None:
-        for mode in ("batch", "sync"):
+        for mode in ("batch", "sync", "queue"):
             log("%s baseline: %d jobs x %d steps" % (mode, args.jobs, args.baseline_steps))
             tout.zero_()
             c2, _, dt2, st2, _ = run_mode(mode, args, args.jobs, args.baseline_steps, 1, tin, tout, pool, torch)
@@ -330,6 +420,8 @@ def main():
         "batch_sync_jobs_per_s": extra.get("batch", {}).get("jobs_per_s"),
         "speedup_vs_batch_sync": round(set_jps / extra["batch"]["jobs_per_s"], 3) if "batch" in extra else None,
         "sync_jobs_per_s": extra.get("sync", {}).get("jobs_per_s"),
+        "queue_jobs_per_s": extra.get("queue", {}).get("jobs_per_s"),
+        "speedup_vs_queue": round(set_jps / extra["queue"]["jobs_per_s"], 3) if "queue" in extra else None,
         "speedup_vs_sync": round(set_jps / extra["sync"]["jobs_per_s"], 3) if "sync" in extra else None,
         "baselines": extra,
         "job_latency_us": {"launch_to_done_p50": round(float(np.percentile(lat_dev, 50)), 1),

@@ -74,7 +74,12 @@ enum set_mode {
      * fixed stream, parameters updated per batch, host synchronisation per
      * batch (Section 2; Section 3.2 "Inter-Batch Overheads"; Section 5.1,
      * model 3). */
-    SET_MODE_BATCH_SYNC = 3
+    SET_MODE_BATCH_SYNC = 3,
+    /* Queue model: one global issue queue under a mutex; an issuer thread
+     * repeatedly takes the mutex and queries every worker (O(b) per round),
+     * completing finished jobs and launching the next queued job's graph on
+     * each idle worker (Section 2; Section 5.1, model 4). */
+    SET_MODE_QUEUE = 4
 };
 
 enum set_backend {
@@ -82,17 +87,21 @@ enum set_backend {
     SET_BACKEND_FAKE = 1  /* CPU stand-in (threads as streams) for scheduler tests; computes no pipeline */
 };
 
-/* Completion mechanism of SET mode ("AddCallback", Algorithm 2; Algorithm 3). */
+/* Completion mechanism of SET mode ("AddCallback", Algorithm 2; the
+ * asynchronous resource return of Algorithm 3). */
 enum set_callback_mode {
+    /* hipEventRecord on the worker stream after the job's graph; a library
+     * completion thread observes each worker's events in launch order
+     * (hipEventQuery reads a host-visible signal) and runs the release.  The
+     * device queues hold only event markers.  Default: with 4 hardware queues
+     * per process on MI355X, a host-function packet in a queue blocks every
+     * stream sharing it, which the two variants below do. */
+    SET_CB_EVENT_POLL = 0,
     /* hipEventRecord on the worker stream, hipStreamWaitEvent on a per-worker
-     * callback stream, hipLaunchHostFunc there: the worker stream never waits
-     * for the host callback (event chaining). */
-    SET_CB_EVENT_CHAIN = 0,
+     * callback stream, hipLaunchHostFunc there (event chaining). */
+    SET_CB_EVENT_CHAIN = 1,
     /* hipLaunchHostFunc directly on the worker stream after the graph. */
-    SET_CB_SAME_STREAM = 1,
-    /* hipEventRecord only; a library completion thread observes the events
-     * in launch order (ablation; polls instead of using driver callbacks). */
-    SET_CB_EVENT_POLL = 2
+    SET_CB_SAME_STREAM = 2
 };
 
 enum set_submit_policy {
@@ -127,7 +136,8 @@ enum set_pipeline {
      * SET_TF_SCAN_LOW32). */
     SET_PIPE_SCAN_I32_I64 = 3,
     /* A batch of vector jobs in one launch graph: H2D of a descriptor table
-     * (64-byte header + one 32-byte descriptor per job) -> a persistent
+     * (64-byte header + one 48-byte descriptor per job, each with its own
+     * work-item size) -> a persistent
      * kernel whose blocks pull (job, tile) work items from an atomic counter
      * -> a kernel summing each job's tile partials in tile order -> D2H of
      * set_out_header + one float32 S per job, in descriptor order.  Jobs are
@@ -138,14 +148,17 @@ enum set_pipeline {
 
 /* How a job's host<->device copies execute (both are part of the job's graph). */
 enum set_copy_mode {
-    SET_COPY_NODES = 0,   /* graph memcpy nodes (hipMemcpyAsync in the synchronous model) */
-    SET_COPY_KERNELS = 1  /* small-grid copy kernels that pull the input from / push the output to pinned
-                             host memory; host buffers must then be 16-byte aligned */
+    SET_COPY_KERNELS = 0, /* small-grid copy kernels that pull the input from / push the output to pinned
+                             host memory; host buffers must be 16-byte aligned.  Default: ROCm runs graph
+                             memcpy nodes as large-grid blit kernels that crowd out the stage kernels */
+    SET_COPY_NODES = 1    /* graph memcpy nodes (hipMemcpyAsync in the synchronous model) */
 };
 
 /* template flags */
 #define SET_TF_DEBUG 0x1u       /* also copy intermediate images back (parity tests) */
 #define SET_TF_SCAN_LOW32 0x2u  /* scan: copy back only the low 32 bits of each sum */
+#define SET_TF_CAPTURE 0x4u     /* build each slot's graph by stream capture of the job's launch sequence
+                                   (Section 4.1's capture path) instead of explicit node construction */
 
 /* submit flags */
 #define SET_NONBLOCK 0x1  /* return SET_EAGAIN instead of waiting for staging room */
@@ -158,8 +171,8 @@ typedef struct set_config {
     int32_t device;              /* HIP device ordinal */
     int32_t num_workers;         /* b: workers, one stream each (Section 4.2 (1)); 1..64 */
     int32_t slots_per_worker;    /* d: buffer slots (one graph exec each) per worker; 1..64 */
-    int32_t queue_capacity;      /* capacity of each per-worker queue Q_i; 0 = d - inflight */
-    int32_t inflight_per_worker; /* launch permits per worker in the free pool; 0 = max(1, d/2) */
+    int32_t queue_capacity;      /* capacity of each per-worker queue Q_i; 0 = max(1, d - inflight) */
+    int32_t inflight_per_worker; /* launch permits per worker in the free pool; 0 = min(2, d) */
     int32_t work_stealing;       /* 1: FindJob steals from (w+k) mod b (Algorithm 2); 0: local only */
     int32_t batch_size;          /* SET_MODE_BATCH_SYNC: job chains per batch graph; 0 = num_workers */
     int32_t callback_mode;       /* enum set_callback_mode (SET mode) */
@@ -339,6 +352,46 @@ int set_time_stage(set_ctx *c, int template_id, int stage, int worker, int reps,
  * batches submitted. */
 int set_run_vector_jobs(set_ctx *c, int template_id, const set_vec_job *jobs, uint64_t count,
                         float *results, const set_vec_tuning *tuning, uint64_t *batches);
+
+/* ---------------------------------------------------------------- serving */
+/* One request of an open-loop arrival schedule. */
+typedef struct set_request {
+    uint64_t t_arrival_ns;       /* arrival, ns after the start of the run; non-decreasing */
+    int32_t template_id;         /* a per-job template, or a vector batch template */
+    uint32_t reserved;
+    set_job_args args;           /* per-job template: as for set_submit.  Vector batch template:
+                                    n, a, x_off, y_off of one vector job; host buffers unused */
+} set_request;
+
+typedef struct set_serve_config {
+    uint32_t vec_inflight;       /* vector batches in flight at once (0 = num_workers) */
+    uint32_t vec_batch_max;      /* most vector requests per batch (0 = the template's batch_max) */
+    uint64_t window_ns;          /* requests arriving later are not admitted (0 = admit all) */
+    const set_vec_tuning *tuning;/* work-item size per size bucket (NULL = defaults) */
+} set_serve_config;
+
+typedef struct set_serve_stats {
+    uint64_t arrived, completed, failed, not_admitted;
+    uint64_t vec_batches;
+    uint64_t t_start_ns, t_end_ns;  /* steady clock: first arrival slot, last completion */
+    uint64_t max_backlog;        /* most arrived requests waiting for admission at once */
+} set_serve_stats;
+
+/* Serve an open-loop request schedule (SET mode only).  The calling thread
+ * releases each request at its arrival time; per-job requests enter the
+ * scheduler at once and are admitted as worker slots and the device-memory
+ * budget (set_config.mem_budget_bytes) allow; vector requests are batched
+ * continuously: whenever a vector-batch slot is free, every vector request
+ * that has arrived (up to vec_batch_max) forms the next batch, mixing size
+ * buckets (each job keeps its bucket's work-item size, so its result equals
+ * its result alone).  Requests of different kinds overlap on the device.
+ * done_ns[i] receives the completion time of request i in ns after the start
+ * of the run (the arrival time is reqs[i].t_arrival_ns; 0 = not completed);
+ * vec_results[i] receives S of vector request i (may be NULL if there are
+ * none).  Blocks until every admitted request completed.  The per-job
+ * requests' host buffers follow set_submit's rules. */
+int set_serve(set_ctx *c, const set_request *reqs, uint64_t count, const set_serve_config *cfg,
+              uint64_t *done_ns, float *vec_results, set_serve_stats *stats);
 
 /* Number of kernels in the template's chain and the algorithmic HBM bytes one
  * launch of each moves (reads + writes of its operands, counted once). */

@@ -26,20 +26,21 @@ SET_ABI_VERSION = 1
 SET_OK, SET_EINVAL, SET_ENOMEM, SET_EDEVICE, SET_EAGAIN, SET_ETIMEOUT, SET_ECLOSED, SET_EUNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6, -7)
 # modes
-SET_MODE_SET, SET_MODE_SYNC, SET_MODE_GRAPH, SET_MODE_BATCH_SYNC = 0, 1, 2, 3
+SET_MODE_SET, SET_MODE_SYNC, SET_MODE_GRAPH, SET_MODE_BATCH_SYNC, SET_MODE_QUEUE = 0, 1, 2, 3, 4
 SET_BACKEND_HIP, SET_BACKEND_FAKE = 0, 1
-SET_CB_EVENT_CHAIN, SET_CB_SAME_STREAM, SET_CB_EVENT_POLL = 0, 1, 2
+SET_CB_EVENT_POLL, SET_CB_EVENT_CHAIN, SET_CB_SAME_STREAM = 0, 1, 2
 SET_SUBMIT_ROUND_ROBIN, SET_SUBMIT_SHORTEST, SET_SUBMIT_SKEW0 = 0, 1, 2
 # pipelines
 SET_PIPE_BOX_HIST_U8, SET_PIPE_GAUSS_SOBEL_F32, SET_PIPE_SAXPY_TANH_SUM_F32, SET_PIPE_SCAN_I32_I64 = 0, 1, 2, 3
 SET_PIPE_SAXPY_BATCH_F32 = 4
-SET_TF_DEBUG, SET_TF_SCAN_LOW32 = 0x1, 0x2
-SET_COPY_NODES, SET_COPY_KERNELS = 0, 1
+SET_TF_DEBUG, SET_TF_SCAN_LOW32, SET_TF_CAPTURE = 0x1, 0x2, 0x4
+SET_COPY_KERNELS, SET_COPY_NODES = 0, 1
 COPY_MODES = {"nodes": SET_COPY_NODES, "kernels": SET_COPY_KERNELS}
 SET_NONBLOCK = 0x1
 SET_OUT_MAGIC = 0x5E7D0A11
 
-MODES = {"set": SET_MODE_SET, "sync": SET_MODE_SYNC, "graph": SET_MODE_GRAPH, "batch": SET_MODE_BATCH_SYNC}
+MODES = {"set": SET_MODE_SET, "sync": SET_MODE_SYNC, "graph": SET_MODE_GRAPH, "batch": SET_MODE_BATCH_SYNC,
+         "queue": SET_MODE_QUEUE}
 CALLBACKS = {"event_chain": SET_CB_EVENT_CHAIN, "same_stream": SET_CB_SAME_STREAM, "event_poll": SET_CB_EVENT_POLL}
 
 
@@ -171,6 +172,28 @@ JOB_TIMES_DTYPE = np.dtype([("job_id", np.uint64), ("t_submit", np.uint64), ("t_
                             ("t_done", np.uint64), ("worker", np.int32), ("slot", np.int32), ("stolen", np.int32),
                             ("status", np.int32)])
 
+# numpy mirror of set_request (arrival, template, job args)
+REQUEST_DTYPE = np.dtype({
+    "names": ["t_arrival_ns", "template_id", "reserved_r", "host_in", "in_bytes", "host_out", "out_bytes", "n", "a",
+              "worker_hint", "x_off", "y_off", "user_tag", "grid", "reserved"],
+    "formats": [np.uint64, np.int32, np.uint32, np.uint64, np.uint64, np.uint64, np.uint64, np.uint64, np.float32,
+                np.int32, np.uint64, np.uint64, np.uint64, np.uint32, np.uint32],
+    "offsets": [0, 8, 12, 16, 24, 32, 40, 48, 56, 60, 64, 72, 80, 88, 92],
+    "itemsize": 96,
+})
+
+
+class set_serve_config(ctypes.Structure):
+    _fields_ = [("vec_inflight", ctypes.c_uint32), ("vec_batch_max", ctypes.c_uint32), ("window_ns", ctypes.c_uint64),
+                ("tuning", ctypes.POINTER(set_vec_tuning))]
+
+
+class set_serve_stats(ctypes.Structure):
+    _fields_ = [("arrived", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("not_admitted", ctypes.c_uint64), ("vec_batches", ctypes.c_uint64), ("t_start_ns", ctypes.c_uint64),
+                ("t_end_ns", ctypes.c_uint64), ("max_backlog", ctypes.c_uint64)]
+
+
 set_completion_fn = ctypes.CFUNCTYPE(None, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p)
 
 # every entry point the header declares (checked by the export test)
@@ -178,7 +201,7 @@ EXPORTS = [
     "set_ctx_create", "set_ctx_destroy", "set_template_footprint", "set_template_define", "set_submit",
     "set_submit_many", "set_set_completion_cb", "set_drain", "set_get_stats", "set_reset_stats",
     "set_get_job_times", "set_time_stage", "set_stage_info", "set_last_error", "set_strerror",
-    "set_run_vector_jobs",
+    "set_run_vector_jobs", "set_serve",
 ]
 
 _lib = None
@@ -212,6 +235,7 @@ def load():
         "set_time_stage": (I, [P, I, I, I, I, ctypes.POINTER(ctypes.c_double)]),
         "set_stage_info": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(U64), I, ctypes.c_char_p, I]),
         "set_run_vector_jobs": (I, [P, I, P, U64, P, ctypes.POINTER(set_vec_tuning), ctypes.POINTER(U64)]),
+        "set_serve": (I, [P, P, U64, ctypes.POINTER(set_serve_config), P, P, ctypes.POINTER(set_serve_stats)]),
         "set_last_error": (ctypes.c_char_p, [P]),
         "set_strerror": (ctypes.c_char_p, [I]),
     }
@@ -322,6 +346,17 @@ def set_run_vector_jobs(ctx, template_id: int, jobs: np.ndarray, results: np.nda
     check(load().set_run_vector_jobs(ctx, template_id, jobs.ctypes.data, jobs.size, results.ctypes.data,
                                      ctypes.byref(tuning) if tuning is not None else None, ctypes.byref(nb)), ctx)
     return nb.value
+
+
+def set_serve(ctx, reqs: np.ndarray, cfg: set_serve_config = None, vec_results: np.ndarray = None):
+    """Returns (done_ns array, stats)."""
+    assert reqs.dtype == REQUEST_DTYPE and reqs.flags["C_CONTIGUOUS"]
+    done = np.zeros(reqs.size, np.uint64)
+    st = set_serve_stats()
+    vr = vec_results.ctypes.data if vec_results is not None else None
+    check(load().set_serve(ctx, reqs.ctypes.data, reqs.size, ctypes.byref(cfg) if cfg is not None else None,
+                           done.ctypes.data, vr, ctypes.byref(st)), ctx)
+    return done, st
 
 
 def set_last_error(ctx) -> str:

@@ -12,6 +12,7 @@
 #include <deque>
 #include <random>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.hpp"
@@ -71,6 +72,32 @@ class FakeBackend : public Backend {
       w.q.push_back(Pending{job, done, ctx});
     }
     w.cv.notify_one();
+    return SET_OK;
+  }
+
+  int launch_polled(JobRec* job, std::string* err) override {
+    const int n = ++launches_;
+    if (cfg_.fake_fail_after > 0 && n >= cfg_.fake_fail_after) {
+      if (err) *err = "injected launch failure";
+      return SET_EDEVICE;
+    }
+    {
+      std::lock_guard<std::mutex> g(done_mu_);
+      done_[job] = false;
+    }
+    Worker& w = *workers_[job->worker];
+    {
+      std::lock_guard<std::mutex> g(w.mu);
+      w.q.push_back(Pending{job, nullptr, nullptr});
+    }
+    w.cv.notify_one();
+    return SET_OK;
+  }
+  int is_done(JobRec* job, bool* done, std::string*) override {
+    std::lock_guard<std::mutex> g(done_mu_);
+    auto it = done_.find(job);
+    *done = (it != done_.end() && it->second);
+    if (*done) done_.erase(it);
     return SET_OK;
   }
 
@@ -164,6 +191,11 @@ class FakeBackend : public Backend {
         w.q.pop_front();
       }
       execute(p.job);
+      if (!p.done) {  // queue model: completion is observed by polling
+        std::lock_guard<std::mutex> g(done_mu_);
+        done_[p.job] = true;
+        continue;
+      }
       {
         std::lock_guard<std::mutex> g(cb_mu_);
         cb_q_.push_back(p);
@@ -200,6 +232,8 @@ class FakeBackend : public Backend {
   std::atomic<bool> stop_{false};
   std::atomic<int> launches_{0};
   std::atomic<int> violations_{0};
+  std::mutex done_mu_;
+  std::unordered_map<JobRec*, bool> done_;
 };
 
 }  // namespace

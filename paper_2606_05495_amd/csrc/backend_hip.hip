@@ -193,17 +193,23 @@ class HipBackend : public Backend {
         HIPCK(hipMemcpy(sl.base + p.L.tail, &ct, 8, hipMemcpyHostToDevice));
       }
     }
-    if (cfg_.mode == SET_MODE_SET || cfg_.mode == SET_MODE_GRAPH) {
-      const int ds = (cfg_.mode == SET_MODE_GRAPH) ? 1 : d_;
+    if (cfg_.mode == SET_MODE_SET || cfg_.mode == SET_MODE_GRAPH || cfg_.mode == SET_MODE_QUEUE) {
+      const int ds = (cfg_.mode == SET_MODE_SET) ? d_ : 1;
       for (int w = 0; w < b_; ++w) {
         for (int s = 0; s < ds; ++s) {
           Slot& sl = p.slots[(size_t)w * d_ + s];
-          HIPCK(hipGraphCreate(&sl.graph, 0));
-          int rc = add_chain(p, sl, sl.graph, &sl.nodes, err);
+          int rc;
+          if (t.flags & SET_TF_CAPTURE) {
+            rc = capture_chain(p, sl, streams_[w], &sl.graph, &sl.nodes, err);
+          } else {
+            HIPCK(hipGraphCreate(&sl.graph, 0));
+            rc = add_chain(p, sl, sl.graph, &sl.nodes, err);
+          }
           if (rc != SET_OK) return rc;
           HIPCK(hipGraphInstantiateWithFlags(&sl.exec, sl.graph, 0));
           HIPCK(hipGraphUpload(sl.exec, streams_[w]));
-          if (cfg_.mode == SET_MODE_SET) HIPCK(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+          if (cfg_.mode == SET_MODE_SET || cfg_.mode == SET_MODE_QUEUE)
+            HIPCK(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
         }
       }
     }
@@ -249,6 +255,32 @@ class HipBackend : public Backend {
       }
     }
     return SET_OK;
+  }
+
+  int launch_polled(JobRec* j, std::string* err) override {
+    ensure_dev();
+    Pipe& p = *pipes_[j->tmpl];
+    Slot& sl = p.slots[(size_t)j->worker * d_ + j->slot];
+    hipStream_t st = streams_[j->worker];
+    HIPCK(hipGraphLaunch(sl.exec, st));
+    HIPCK(hipEventRecord(sl.ev, st));
+    return SET_OK;
+  }
+
+  int is_done(JobRec* j, bool* done, std::string* err) override {
+    Pipe& p = *pipes_[j->tmpl];
+    Slot& sl = p.slots[(size_t)j->worker * d_ + j->slot];
+    const hipError_t e = hipEventQuery(sl.ev);
+    if (e == hipSuccess) {
+      *done = true;
+      return SET_OK;
+    }
+    if (e == hipErrorNotReady) {
+      *done = false;
+      return SET_OK;
+    }
+    if (err) *err = std::string("hipEventQuery failed: ") + hipGetErrorString(e);
+    return SET_EDEVICE;
   }
 
   int run_sync(JobRec* j, int si, std::string* err) override {
@@ -614,6 +646,76 @@ class HipBackend : public Backend {
       HIPCK(hipGraphAddMemcpyNode1D(&cn->d2h, g, &prev, 1, p.placeholder, sl.base + p.L.out, p.L.out_cap,
                                     hipMemcpyDeviceToHost));
     }
+    return SET_OK;
+  }
+
+  // Stream capture of the job's launch sequence (the copies bound to the
+  // placeholder), then the captured chain is walked from its root to find
+  // the nodes the binder updates.
+  int capture_chain(Pipe& p, Slot& sl, hipStream_t st, hipGraph_t* out, ChainNodes* cn, std::string* err) {
+    const bool kcopy = p.t.copy_mode == SET_COPY_KERNELS;
+    HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    if (p.L.in_cap > 0) {
+      if (kcopy) {
+        sl.h2d_copy = CopyArgs{p.placeholder, sl.base + p.L.in, p.L.in_cap};
+        HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(kCopyBlocks), dim3(kBlock), sl.h2d_argv, 0, st));
+      } else {
+        HIPCK(hipMemcpyAsync(sl.base + p.L.in, p.placeholder, p.L.in_cap, hipMemcpyHostToDevice, st));
+      }
+    }
+    for (int i = 0; i < sl.nstages; ++i)
+      HIPCK(hipLaunchKernel(sl.func[i], sl.grid[i], dim3(kBlock), sl.argv[i], 0, st));
+    if (kcopy) {
+      sl.d2h_copy = CopyArgs{sl.base + p.L.out, p.placeholder, p.L.out_cap};
+      HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(kCopyBlocks), dim3(kBlock), sl.d2h_argv, 0, st));
+    } else {
+      HIPCK(hipMemcpyAsync(p.placeholder, sl.base + p.L.out, p.L.out_cap, hipMemcpyDeviceToHost, st));
+    }
+    HIPCK(hipStreamEndCapture(st, out));
+    size_t n = 0;
+    HIPCK(hipGraphGetNodes(*out, nullptr, &n));
+    std::vector<hipGraphNode_t> nodes(n);
+    HIPCK(hipGraphGetNodes(*out, nodes.data(), &n));
+    const size_t expect = (p.L.in_cap > 0 ? 1 : 0) + sl.nstages + 1;
+    if (n != expect) {
+      if (err) *err = "captured graph has an unexpected number of nodes";
+      return SET_EDEVICE;
+    }
+    // order the linear chain: start at the node with no dependencies
+    std::vector<hipGraphNode_t> order;
+    hipGraphNode_t cur = nullptr;
+    for (hipGraphNode_t nd : nodes) {
+      size_t deps = 0;
+      HIPCK(hipGraphNodeGetDependencies(nd, nullptr, &deps));
+      if (deps == 0) cur = nd;
+    }
+    while (cur && order.size() < n) {
+      order.push_back(cur);
+      size_t nd = 0;
+      HIPCK(hipGraphNodeGetDependentNodes(cur, nullptr, &nd));
+      if (nd == 0) break;
+      if (nd != 1) {
+        if (err) *err = "captured graph is not a chain";
+        return SET_EDEVICE;
+      }
+      HIPCK(hipGraphNodeGetDependentNodes(cur, &cur, &nd));
+    }
+    if (order.size() != n) {
+      if (err) *err = "captured graph is not a chain";
+      return SET_EDEVICE;
+    }
+    size_t k = 0;
+    if (p.L.in_cap > 0) cn->h2d = order[k++];
+    for (int i = 0; i < sl.nstages; ++i) {
+      hipKernelNodeParams kp{};
+      HIPCK(hipGraphKernelNodeGetParams(order[k], &kp));
+      if (kp.func != sl.func[i]) {
+        if (err) *err = "captured stage order differs from the template";
+        return SET_EDEVICE;
+      }
+      cn->k[i] = order[k++];
+    }
+    cn->d2h = order[k];
     return SET_OK;
   }
 

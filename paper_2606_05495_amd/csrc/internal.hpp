@@ -59,12 +59,13 @@ static_assert(sizeof(DevSlotHdr) == 64, "DevSlotHdr layout");
 static_assert(sizeof(set_out_header) == 64, "set_out_header layout");
 
 // Descriptor table of a vector batch (host-written, copied to the slot by
-// the batch's H2D): a 64-byte header, then one 32-byte descriptor per job.
+// the batch's H2D): a 64-byte header, then one 48-byte descriptor per job.
+// Each job carries its own work-item size, so one batch may mix size buckets
+// while every job's result still depends only on (n, its item size).
 struct VecBatchHdr {
   uint32_t count;        // jobs in the batch
-  uint32_t tile_elems;   // elements per (job, tile) work item, multiple of 1024
   uint32_t total_tiles;  // work items in the batch
-  uint32_t pad[13];
+  uint32_t pad[14];
 };
 struct VecBatchDesc {
   uint64_t x_off, y_off;
@@ -72,9 +73,11 @@ struct VecBatchDesc {
   float a;
   uint32_t tile_start;   // first work item of this job (non-decreasing)
   uint32_t ntiles;       // ceil(n / tile_elems)
+  uint32_t tile_elems;   // elements per work item, multiple of 1024
+  uint32_t pad[3];
 };
 static_assert(sizeof(VecBatchHdr) == 64, "VecBatchHdr layout");
-static_assert(sizeof(VecBatchDesc) == 32, "VecBatchDesc layout");
+static_assert(sizeof(VecBatchDesc) == 48, "VecBatchDesc layout");
 
 inline uint64_t canary_value(int tmpl, int w, int s, int which) {
   return 0x5E7CA9A200000000ull ^ ((uint64_t)which << 60) ^ ((uint64_t)tmpl << 24) ^ ((uint64_t)w << 12) ^
@@ -93,6 +96,7 @@ struct JobRec {
   uint64_t footprint;
   uint64_t t_submit, t_launch, t_done;
   int status;
+  int64_t serve_ref;  // serving: request index (>= 0), vector batch -(2 + ring entry), or -1
   JobRec* next;   // free list / intrusive links
 };
 
@@ -130,6 +134,10 @@ class Backend {
   // GraphLaunch + AddCallback: launch the bound slot's executable on the
   // worker's stream and arrange for done(ctx, job, status) after it finishes.
   virtual int launch(JobRec* job, DoneFn done, void* ctx, std::string* err) = 0;
+  // Queue model: launch the bound slot's executable and record its completion
+  // event without any callback; is_done() queries that event.
+  virtual int launch_polled(JobRec* job, std::string* err) = 0;
+  virtual int is_done(JobRec* job, bool* done, std::string* err) = 0;
   // Baselines, run on the caller's thread.
   virtual int run_sync(JobRec* job, int stream_index, std::string* err) = 0;
   virtual int run_graph(JobRec* job, int stream_index, std::string* err) = 0;

@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_vec_batch_tiles(VecBatchArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
   const VecBatchHdr* H = reinterpret_cast<const VecBatchHdr*>(a.tab);
   const VecBatchDesc* D = reinterpret_cast<const VecBatchDesc*>(a.tab + sizeof(VecBatchHdr));
-  const uint32_t count = H->count, TE = H->tile_elems, T = H->total_tiles;
+  const uint32_t count = H->count, T = H->total_tiles;
   while (true) {
     if (threadIdx.x == 0) {
       const uint32_t t = __hip_atomic_fetch_add(a.work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -382,8 +382,8 @@ __global__ __launch_bounds__(kBlock) void k_vec_batch_tiles(VecBatchArgs a) {
     const uint32_t t = s_item;
     if (t >= T) break;
     const VecBatchDesc d = D[s_job];
-    const uint64_t beg = (uint64_t)(t - d.tile_start) * TE;
-    const uint64_t end = beg + TE < d.n ? beg + TE : (uint64_t)d.n;
+    const uint64_t beg = (uint64_t)(t - d.tile_start) * d.tile_elems;
+    const uint64_t end = beg + d.tile_elems < d.n ? beg + d.tile_elems : (uint64_t)d.n;
     const float acc = vec_range_sum(a.x + d.x_off, a.y + d.y_off, d.a, beg, end, ((d.x_off | d.y_off) & 3u) == 0);
     const float bs = block_sum_f32(acc, s4f);
     if (threadIdx.x == 0) a.partials[t] = bs;

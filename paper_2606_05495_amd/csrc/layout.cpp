@@ -43,8 +43,8 @@ int pipeline_validate(const set_job_template& t, std::string* why) {
     default:
       return bad("unknown pipeline");
   }
-  if (t.flags & ~(uint32_t)(SET_TF_DEBUG | SET_TF_SCAN_LOW32)) return bad("unknown template flags");
-  if (t.copy_mode != SET_COPY_NODES && t.copy_mode != SET_COPY_KERNELS) return bad("unknown copy mode");
+  if (t.flags & ~(uint32_t)(SET_TF_DEBUG | SET_TF_SCAN_LOW32 | SET_TF_CAPTURE)) return bad("unknown template flags");
+  if (t.copy_mode != SET_COPY_KERNELS && t.copy_mode != SET_COPY_NODES) return bad("unknown copy mode");
   return SET_OK;
 }
 
@@ -124,7 +124,7 @@ static SlotLayout layout_of(const set_job_template& t) {
     }
     case SET_PIPE_SAXPY_BATCH_F32: {
       L.in = off;
-      L.in_cap = 64 + 32ull * t.batch_max;
+      L.in_cap = 64 + 48ull * t.batch_max;
       off = up(off + L.in_cap);
       L.out = off;
       L.out_cap = 64 + 4ull * t.batch_max;
@@ -170,7 +170,7 @@ uint64_t pipeline_in_bytes(const set_job_template& t, uint64_t n) {
     case SET_PIPE_SCAN_I32_I64:
       return 4ull * (n ? n : t.max_n);
     case SET_PIPE_SAXPY_BATCH_F32:
-      return 64 + 32ull * n;
+      return 64 + 48ull * n;
   }
   return 0;
 }
@@ -251,8 +251,8 @@ int pipeline_sizes(const set_job_template& t, TemplateSizes* out) {
     }
     case SET_PIPE_SAXPY_BATCH_F32:
       // the streamed bytes depend on the batch (8 bytes per element of every job)
-      stage("vec_batch_tiles", 64 + 32ull * t.batch_max + 4ull * t.tiles_max);
-      stage("vec_batch_final", 64 + 32ull * t.batch_max + 4ull * t.tiles_max + 4ull * t.batch_max);
+      stage("vec_batch_tiles", 64 + 48ull * t.batch_max + 4ull * t.tiles_max);
+      stage("vec_batch_final", 64 + 48ull * t.batch_max + 4ull * t.tiles_max + 4ull * t.batch_max);
       break;
     case SET_PIPE_SCAN_I32_I64: {
       const uint64_t T = scan_tiles(t.max_n);

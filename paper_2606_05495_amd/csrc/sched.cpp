@@ -146,6 +146,11 @@ class Context {
   std::thread submitter, dispatcher;
   std::atomic<bool> stopping{false};
 
+  // ---- queue model (SET_MODE_QUEUE)
+  std::mutex gq_mu;            // the global issue-queue mutex
+  std::deque<JobRec*> gq;
+  std::thread issuer;
+
   // ---- baseline modes
   std::mutex base_mu;
   std::vector<JobRec*> batch;
@@ -167,6 +172,31 @@ class Context {
 
   std::atomic<set_completion_fn> user_fn{nullptr};
   std::atomic<void*> user_arg{nullptr};
+
+  // ---- serving (set_serve)
+  struct VecRing {
+    char* tab = nullptr;
+    char* res = nullptr;
+    std::vector<uint32_t> idx;
+    bool busy = false;
+  };
+  struct ServeState {
+    const set_request* reqs = nullptr;
+    uint64_t* done_ns = nullptr;
+    float* vec_results = nullptr;
+    uint64_t t0 = 0;
+    int vtmpl = -1;
+    uint32_t vec_batch_max = 0, vec_inflight_max = 0;
+    const set_vec_tuning* tuning = nullptr;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<uint32_t> pending;
+    std::vector<VecRing> ring;
+    uint32_t inflight = 0;
+    bool arrivals_done = false;
+    std::atomic<uint64_t> completed{0}, failed{0}, batches{0}, t_last{0};
+  };
+  ServeState* serve_st = nullptr;
 
   ~Context() { shutdown(); }
 
@@ -199,6 +229,7 @@ class Context {
     JobRec* j = job_free;
     job_free = j->next;
     std::memset(j, 0, sizeof(*j));
+    j->serve_ref = -1;
     return j;
   }
   void free_job(JobRec* j) {
@@ -255,12 +286,15 @@ class Context {
     cfg = c;
     b = c.num_workers;
     d = c.slots_per_worker;
-    kperm = c.inflight_per_worker > 0 ? c.inflight_per_worker : std::max(1, d / 2);
+    kperm = c.inflight_per_worker > 0 ? c.inflight_per_worker : std::min(2, d);
     qcap = c.queue_capacity > 0 ? c.queue_capacity : std::max(1, d - kperm);
     staging_cap = c.staging_capacity > 0 ? c.staging_capacity : 4096;
     for (int i = 0; i < kMaxWorkers; ++i) st_launch[i] = 0;
-    if (c.mode == SET_MODE_SET && qcap + kperm > d)
-      return fail(SET_EINVAL, "queue_capacity + inflight_per_worker must not exceed slots_per_worker");
+    // A thief steals only into a FREE slot of its own; with an empty queue and a
+    // permit in hand it has at most kperm - 1 slots in flight, so kperm <= d
+    // guarantees progress (q + k <= d additionally guarantees every steal finds a slot).
+    if (c.mode == SET_MODE_SET && kperm > d)
+      return fail(SET_EINVAL, "inflight_per_worker must not exceed slots_per_worker");
     be.reset(c.backend == SET_BACKEND_FAKE ? make_fake_backend() : make_hip_backend());
     if (!be) return fail(SET_EUNSUPPORTED, "backend not available in this build");
     std::string err;
@@ -278,6 +312,7 @@ class Context {
       submitter = std::thread([this] { submitter_loop(); });
       dispatcher = std::thread([this] { dispatcher_loop(); });
     }
+    if (cfg.mode == SET_MODE_QUEUE) issuer = std::thread([this] { issuer_loop(); });
     return SET_OK;
   }
 
@@ -298,6 +333,7 @@ class Context {
       }
       if (submitter.joinable()) submitter.join();
       if (dispatcher.joinable()) dispatcher.join();
+      if (issuer.joinable()) issuer.join();
       if (be) be->shutdown();
     }
   }
@@ -341,8 +377,45 @@ class Context {
         times.push_back(set_job_times{j->id, j->t_submit, j->t_launch, j->t_done, j->worker, j->slot, j->stolen,
                                       status});
     }
+    if (j->serve_ref != -1 && serve_st) serve_complete(j, status);
     set_completion_fn fn = user_fn.load();
     if (fn) fn(j->id, status, user_arg.load());
+  }
+
+  void serve_complete(JobRec* j, int status) {
+    ServeState& S = *serve_st;
+    const uint64_t now = now_ns() - S.t0;
+    update_max(S.t_last, now);
+    if (j->serve_ref >= 0) {
+      if (status == SET_OK) {
+        S.done_ns[j->serve_ref] = now;
+        ++S.completed;
+      } else {
+        ++S.failed;
+      }
+      return;
+    }
+    const int r = (int)(-2 - j->serve_ref);
+    VecRing& R = S.ring[r];
+    const set_out_header* h = reinterpret_cast<const set_out_header*>(R.res);
+    const bool ok = status == SET_OK && h->magic == SET_OUT_MAGIC && h->canary_ok == 1;
+    if (ok) {
+      const float* v = reinterpret_cast<const float*>(R.res + 64);
+      for (size_t q = 0; q < R.idx.size(); ++q) {
+        if (S.vec_results) S.vec_results[R.idx[q]] = v[q];
+        S.done_ns[R.idx[q]] = now;
+      }
+      S.completed += R.idx.size();
+    } else {
+      S.failed += R.idx.size();
+    }
+    {
+      std::lock_guard<std::mutex> g(S.mu);
+      R.busy = false;
+      R.idx.clear();
+      --S.inflight;
+    }
+    S.cv.notify_all();
   }
 
   void on_done(JobRec* j, int status) {
@@ -407,63 +480,81 @@ class Context {
     return -1;
   }
 
+  // Admission (Algorithm 1): scan up to kAdmitWindow staged jobs in order.  A
+  // job whose template has no free slot on a worker with queue room is
+  // skipped together with every later job of that template (per-template
+  // order is kept); the memory budget is strictly first-come first-served: a
+  // job blocked by the budget is never overtaken, so large jobs cannot starve.
+  // Returns 1 if a job was admitted, 0 if none could be, -1 on a bind error.
+  static constexpr size_t kAdmitWindow = 32;
+
+  int admit_one() {
+    JobRec* window[kAdmitWindow];
+    size_t nw = 0;
+    {
+      std::lock_guard<std::mutex> g(stage_mu);
+      for (; nw < kAdmitWindow && nw < staging.size(); ++nw) window[nw] = staging[nw];
+    }
+    uint64_t blocked = 0;  // templates with no free slot this round
+    for (size_t k = 0; k < nw; ++k) {
+      JobRec* j = window[k];
+      if (blocked & (1ull << j->tmpl)) continue;
+      if (!budget_allows(j->footprint)) return 0;
+      int s = -1;
+      const int w = pick_worker(j, &s);
+      if (w < 0) {
+        if (cfg.mem_budget_bytes) mem_in_use -= j->footprint;
+        blocked |= 1ull << j->tmpl;
+        continue;
+      }
+      {
+        std::lock_guard<std::mutex> g(stage_mu);
+        staging.erase(std::find(staging.begin(), staging.begin() + (k + 1), j));
+      }
+      stage_room_cv.notify_all();
+      if (bind_to(j, w, s) != SET_OK) {
+        release_slot(j->tmpl, w, s);
+        if (cfg.mem_budget_bytes) mem_in_use -= j->footprint;
+        fail_unlaunched(j);
+        return -1;
+      }
+      uint32_t sz = 0;
+      queues[w]->try_push(j, &sz);  // cannot fail: only this thread pushes and pick_worker saw room
+      update_max(st_q_hw, sz);
+      {
+        std::lock_guard<std::mutex> g(pool_mu);
+        ++queued;
+        ++push_gen;
+      }
+      disp_cv.notify_one();
+      return 1;
+    }
+    return 0;
+  }
+
   void submitter_loop() {
     while (true) {
-      JobRec* j = nullptr;
       {
         std::unique_lock<std::mutex> lk(stage_mu);
         stage_cv.wait(lk, [&] { return stopping.load() || !staging.empty(); });
         if (staging.empty()) return;  // stopping and nothing left
-        j = staging.front();
       }
-      // admission: memory budget, then a queue with room and a free slot
-      bool admitted = false;
-      while (!admitted) {
-        if (check_sticky() != SET_OK) break;
-        const uint64_t gen = room_gen.load();
-        if (budget_allows(j->footprint)) {
-          int s = -1;
-          const int w = pick_worker(j, &s);
-          if (w >= 0) {
-            if (bind_to(j, w, s) != SET_OK) {
-              release_slot(j->tmpl, w, s);
-              if (cfg.mem_budget_bytes) mem_in_use -= j->footprint;
-              break;
-            }
-            admitted = true;
-            {
-              std::lock_guard<std::mutex> g(stage_mu);
-              staging.pop_front();
-            }
-            stage_room_cv.notify_all();
-            uint32_t sz = 0;
-            queues[w]->try_push(j, &sz);  // cannot fail: only this thread pushes and pick_worker saw room
-            update_max(st_q_hw, sz);
-            {
-              std::lock_guard<std::mutex> g(pool_mu);
-              ++queued;
-              ++push_gen;
-            }
-            disp_cv.notify_one();
-            break;
-          }
-          if (cfg.mem_budget_bytes) mem_in_use -= j->footprint;
-        }
-        if (stopping.load() && c_done.load() == c_next.load()) return;
-        std::unique_lock<std::mutex> lk(sub_mu);
-        timed_wait(sub_cv, lk, std::chrono::milliseconds(50), [&] { return room_gen.load() != gen || stopping.load(); });
-      }
-      if (!admitted) {
-        // the context is latched into an error: complete the job as failed
+      if (check_sticky() != SET_OK) {
+        // the context is latched into an error: staged jobs complete as failed
+        JobRec* j = nullptr;
         {
           std::lock_guard<std::mutex> g(stage_mu);
+          j = staging.front();
           staging.pop_front();
         }
         stage_room_cv.notify_all();
-        j->worker = 0;
-        j->slot = 0;
         fail_unlaunched(j);
+        continue;
       }
+      const uint64_t gen = room_gen.load();
+      if (admit_one() != 0) continue;
+      std::unique_lock<std::mutex> lk(sub_mu);
+      timed_wait(sub_cv, lk, std::chrono::milliseconds(50), [&] { return room_gen.load() != gen || stopping.load(); });
     }
   }
 
@@ -592,8 +683,77 @@ class Context {
     }
   }
 
+  // ------------------------------------------------------------------ queue model (baseline)
+  // The issuer holds the global mutex for a whole round in which it queries
+  // every worker: finished jobs complete, idle workers get the next job.
+  void complete_polled(JobRec* j, int status) {
+    record_done(j, status);
+    free_job(j);
+    {
+      std::lock_guard<std::mutex> g(done_mu);
+      c_done.fetch_add(1);
+    }
+    done_cv.notify_all();
+  }
+
+  void issuer_loop() {
+    std::vector<JobRec*> running(b, nullptr);
+    while (true) {
+      bool progressed = false, busy = false;
+      {
+        std::lock_guard<std::mutex> g(gq_mu);
+        for (int w = 0; w < b; ++w) {
+          std::string err;
+          if (running[w]) {
+            bool done = false;
+            const int rc = be->is_done(running[w], &done, &err);
+            if (rc != SET_OK) {
+              fail(rc, "queue model: " + err);
+              done = true;
+            }
+            if (done) {
+              complete_polled(running[w], rc);
+              running[w] = nullptr;
+              progressed = true;
+            }
+          }
+          if (!running[w] && !gq.empty()) {
+            JobRec* j = gq.front();
+            gq.pop_front();
+            j->worker = w;
+            j->slot = 0;
+            j->seq = ++slot_seq[j->tmpl][(size_t)w * d];
+            int rc = check_sticky();
+            if (rc == SET_OK) {
+              const uint64_t t0 = now_ns();
+              rc = be->bind(j, &err);
+              st_ns_bind += now_ns() - t0;
+            }
+            if (rc == SET_OK) {
+              j->t_launch = now_ns();
+              ++st_launch[w];
+              const uint64_t t1 = now_ns();
+              rc = be->launch_polled(j, &err);
+              st_ns_launch += now_ns() - t1;
+            }
+            if (rc != SET_OK) {
+              if (rc != check_sticky()) fail(rc, "queue model: " + err);
+              complete_polled(j, SET_EDEVICE);
+            } else {
+              running[w] = j;
+            }
+            progressed = true;
+          }
+          busy |= running[w] != nullptr;
+        }
+        if (!busy && gq.empty() && stopping.load()) return;
+      }
+      if (!progressed) std::this_thread::yield();
+    }
+  }
+
   // ------------------------------------------------------------------ submit
-  int submit(int tmpl, const set_job_args* a, int flags, uint64_t* id_out) {
+  int submit(int tmpl, const set_job_args* a, int flags, uint64_t* id_out, int64_t serve_ref = -1) {
     int st = check_sticky();
     if (st != SET_OK) return st;
     if (stopping.load()) return SET_ECLOSED;
@@ -601,14 +761,17 @@ class Context {
     if (!a) return fail(SET_EINVAL, "null job args");
     std::string why;
     if (pipeline_validate_job(templates[tmpl], *a, &why) != SET_OK) return fail(SET_EINVAL, why);
+    if (cfg.mem_budget_bytes && tsizes[tmpl].slot_bytes > cfg.mem_budget_bytes)
+      return fail(SET_EINVAL, "the template's slot footprint exceeds the memory budget");
     JobRec* j = alloc_job();
     j->tmpl = tmpl;
     j->args = *a;
+    j->serve_ref = serve_ref;
     if (templates[tmpl].pipeline == SET_PIPE_SCAN_I32_I64 && j->args.n == 0) j->args.n = templates[tmpl].max_n;
     j->footprint = tsizes[tmpl].slot_bytes;
     if (cfg.mode == SET_MODE_SET) {
       std::unique_lock<std::mutex> lk(stage_mu);
-      if ((int)staging.size() >= staging_cap) {
+      if ((int)staging.size() >= staging_cap && serve_ref == -1) {
         if (flags & SET_NONBLOCK) {
           lk.unlock();
           free_job(j);
@@ -629,6 +792,16 @@ class Context {
       if (id_out) *id_out = j->id;
       lk.unlock();
       stage_cv.notify_one();
+      return SET_OK;
+    }
+    if (cfg.mode == SET_MODE_QUEUE) {
+      std::lock_guard<std::mutex> g(gq_mu);
+      j->id = c_next.fetch_add(1);
+      j->t_submit = now_ns();
+      uint64_t zero = 0;
+      t_first_submit.compare_exchange_strong(zero, j->t_submit);
+      if (id_out) *id_out = j->id;
+      gq.push_back(j);
       return SET_OK;
     }
     std::lock_guard<std::mutex> g(base_mu);
@@ -738,7 +911,7 @@ class Context {
     }
     auto up64 = [](uint64_t v) { return (v + 63) / 64 * 64; };
     uint64_t total = 0;
-    for (const Plan& pl : plans) total += up64(64 + 32ull * pl.idx.size()) + up64(64 + 4ull * pl.idx.size());
+    for (const Plan& pl : plans) total += up64(64 + 48ull * pl.idx.size()) + up64(64 + 4ull * pl.idx.size());
     if (plans.empty()) {
       if (nbatches_out) *nbatches_out = 0;
       return SET_OK;
@@ -752,13 +925,12 @@ class Context {
       const Plan& pl = plans[k];
       const uint32_t c = (uint32_t)pl.idx.size();
       char* tab = stage_mem + off;
-      off += up64(64 + 32ull * c);
+      off += up64(64 + 48ull * c);
       outs[k] = stage_mem + off;
       off += up64(64 + 4ull * c);
       VecBatchHdr* H = reinterpret_cast<VecBatchHdr*>(tab);
       std::memset(H, 0, sizeof(*H));
       H->count = c;
-      H->tile_elems = pl.te;
       H->total_tiles = pl.tiles;
       VecBatchDesc* D = reinterpret_cast<VecBatchDesc*>(tab + sizeof(VecBatchHdr));
       uint32_t ts = 0;
@@ -770,12 +942,14 @@ class Context {
         D[q].a = j.a;
         D[q].tile_start = ts;
         D[q].ntiles = (uint32_t)((j.n + pl.te - 1) / pl.te);
+        D[q].tile_elems = pl.te;
+        D[q].pad[0] = D[q].pad[1] = D[q].pad[2] = 0;
         ts += D[q].ntiles;
       }
       set_job_args a;
       std::memset(&a, 0, sizeof(a));
       a.host_in = tab;
-      a.in_bytes = 64 + 32ull * c;
+      a.in_bytes = 64 + 48ull * c;
       a.host_out = outs[k];
       a.out_bytes = 64 + 4ull * c;
       a.n = c;
@@ -799,6 +973,186 @@ class Context {
     }
     be->free_host(stage_mem);
     if (nbatches_out) *nbatches_out = plans.size();
+    return rc;
+  }
+
+  // Vector requests -> batches, whenever a batch slot is free (continuous batching).
+  void serve_batcher() {
+    ServeState& S = *serve_st;
+    const set_job_template& t = templates[S.vtmpl];
+    while (true) {
+      int r = -1;
+      std::vector<uint32_t> take;
+      {
+        std::unique_lock<std::mutex> lk(S.mu);
+        S.cv.wait(lk, [&] {
+          return (!S.pending.empty() && S.inflight < S.vec_inflight_max) || (S.arrivals_done && S.pending.empty()) ||
+                 check_sticky() != SET_OK;
+        });
+        if (S.pending.empty() || check_sticky() != SET_OK) {
+          if (S.arrivals_done || check_sticky() != SET_OK) return;
+          continue;
+        }
+        for (size_t k = 0; k < S.ring.size(); ++k)
+          if (!S.ring[k].busy) {
+            r = (int)k;
+            break;
+          }
+        uint64_t tiles = 0;
+        while (!S.pending.empty() && take.size() < S.vec_batch_max) {
+          const set_job_args& a = S.reqs[S.pending.front()].args;
+          const int bk = 63 - __builtin_clzll(a.n);
+          const uint32_t te = (S.tuning && S.tuning->tile_elems[bk]) ? S.tuning->tile_elems[bk] : vec_default_tile(bk);
+          const uint64_t nt = (a.n + te - 1) / te;
+          if (!take.empty() && tiles + nt > t.tiles_max) break;
+          tiles += nt;
+          take.push_back(S.pending.front());
+          S.pending.pop_front();
+        }
+        S.ring[r].busy = true;
+        S.ring[r].idx = take;
+        ++S.inflight;
+      }
+      VecRing& R = S.ring[r];
+      VecBatchHdr* H = reinterpret_cast<VecBatchHdr*>(R.tab);
+      std::memset(H, 0, sizeof(*H));
+      VecBatchDesc* D = reinterpret_cast<VecBatchDesc*>(R.tab + sizeof(VecBatchHdr));
+      uint32_t ts = 0;
+      for (size_t q = 0; q < take.size(); ++q) {
+        const set_job_args& a = S.reqs[take[q]].args;
+        const int bk = 63 - __builtin_clzll(a.n);
+        const uint32_t te = (S.tuning && S.tuning->tile_elems[bk]) ? S.tuning->tile_elems[bk] : vec_default_tile(bk);
+        D[q].x_off = a.x_off;
+        D[q].y_off = a.y_off;
+        D[q].n = (uint32_t)a.n;
+        D[q].a = a.a;
+        D[q].tile_start = ts;
+        D[q].ntiles = (uint32_t)((a.n + te - 1) / te);
+        D[q].tile_elems = te;
+        D[q].pad[0] = D[q].pad[1] = D[q].pad[2] = 0;
+        ts += D[q].ntiles;
+      }
+      H->count = (uint32_t)take.size();
+      H->total_tiles = ts;
+      set_job_args b;
+      std::memset(&b, 0, sizeof(b));
+      b.host_in = R.tab;
+      b.in_bytes = 64 + 48ull * take.size();
+      b.host_out = R.res;
+      b.out_bytes = 64 + 4ull * take.size();
+      b.n = take.size();
+      b.worker_hint = -1;
+      ++S.batches;
+      if (submit(S.vtmpl, &b, 0, nullptr, -2 - (int64_t)r) != SET_OK) {
+        std::lock_guard<std::mutex> g(S.mu);
+        S.failed += take.size();
+        R.busy = false;
+        --S.inflight;
+      }
+    }
+  }
+
+  int serve(const set_request* reqs, uint64_t count, const set_serve_config* cfgp, uint64_t* done_ns,
+            float* vec_results, set_serve_stats* out) {
+    int st = check_sticky();
+    if (st != SET_OK) return st;
+    if (cfg.mode != SET_MODE_SET) return fail(SET_EUNSUPPORTED, "set_serve needs SET mode");
+    if (count && (!reqs || !done_ns)) return fail(SET_EINVAL, "null requests or done_ns");
+    set_serve_config sc{};
+    if (cfgp) sc = *cfgp;
+    std::unique_ptr<ServeState> S(new ServeState());
+    S->reqs = reqs;
+    S->done_ns = done_ns;
+    S->vec_results = vec_results;
+    S->tuning = sc.tuning;
+    uint64_t nvec = 0;
+    for (uint64_t i = 0; i < count; ++i) {
+      const set_request& q = reqs[i];
+      if (q.template_id < 0 || q.template_id >= (int)templates.size()) return fail(SET_EINVAL, "unknown template id");
+      if (i && q.t_arrival_ns < reqs[i - 1].t_arrival_ns) return fail(SET_EINVAL, "arrivals must be non-decreasing");
+      const set_job_template& t = templates[q.template_id];
+      std::string why;
+      if (t.pipeline == SET_PIPE_SAXPY_BATCH_F32) {
+        if (S->vtmpl >= 0 && S->vtmpl != q.template_id) return fail(SET_EINVAL, "one vector batch template per run");
+        S->vtmpl = q.template_id;
+        if (q.args.n < 1 || q.args.n > t.max_n || q.args.x_off > t.pool_len || q.args.n > t.pool_len - q.args.x_off ||
+            q.args.y_off > t.pool_len || q.args.n > t.pool_len - q.args.y_off)
+          return fail(SET_EINVAL, "vector request outside the template's limits");
+        ++nvec;
+      } else if (pipeline_validate_job(t, q.args, &why) != SET_OK) {
+        return fail(SET_EINVAL, why);
+      }
+      done_ns[i] = 0;
+    }
+    if (nvec && !vec_results) return fail(SET_EINVAL, "vector requests need vec_results");
+    char* ring_mem = nullptr;
+    if (S->vtmpl >= 0) {
+      const set_job_template& t = templates[S->vtmpl];
+      S->vec_batch_max = sc.vec_batch_max ? std::min(sc.vec_batch_max, t.batch_max) : t.batch_max;
+      S->vec_inflight_max = sc.vec_inflight ? sc.vec_inflight : (uint32_t)b;
+      const uint64_t tb = (64 + 48ull * S->vec_batch_max + 255) / 256 * 256;
+      const uint64_t rb = (64 + 4ull * S->vec_batch_max + 255) / 256 * 256;
+      ring_mem = (char*)be->alloc_host((tb + rb) * S->vec_inflight_max);
+      if (!ring_mem) return fail(SET_ENOMEM, "pinned staging for vector batches");
+      S->ring.resize(S->vec_inflight_max);
+      for (uint32_t k = 0; k < S->vec_inflight_max; ++k) {
+        S->ring[k].tab = ring_mem + (tb + rb) * k;
+        S->ring[k].res = S->ring[k].tab + tb;
+      }
+    }
+    serve_st = S.get();
+    std::thread batcher;
+    if (S->vtmpl >= 0) batcher = std::thread([this] { serve_batcher(); });
+    uint64_t arrived = 0, max_backlog = 0;
+    int rc = SET_OK;
+    S->t0 = now_ns();
+    for (uint64_t i = 0; i < count; ++i) {
+      const set_request& q = reqs[i];
+      if (sc.window_ns && q.t_arrival_ns > sc.window_ns) break;
+      const uint64_t target = S->t0 + q.t_arrival_ns;
+      uint64_t now = now_ns();
+      while (now < target) {
+        if (target - now > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(target - now - 100000));
+        now = now_ns();
+      }
+      ++arrived;
+      uint64_t backlog = 0;
+      {
+        std::lock_guard<std::mutex> g(stage_mu);
+        backlog = staging.size();
+      }
+      if (q.template_id == S->vtmpl) {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->pending.push_back((uint32_t)i);
+        backlog += S->pending.size();
+      } else {
+        rc = submit(q.template_id, &q.args, 0, nullptr, (int64_t)i);
+        if (rc != SET_OK) break;
+      }
+      max_backlog = std::max(max_backlog, backlog);
+      if (q.template_id == S->vtmpl) S->cv.notify_all();
+    }
+    {
+      std::lock_guard<std::mutex> g(S->mu);
+      S->arrivals_done = true;
+    }
+    S->cv.notify_all();
+    if (batcher.joinable()) batcher.join();
+    const int drc = drain(-1);
+    if (rc == SET_OK) rc = drc;
+    serve_st = nullptr;
+    if (ring_mem) be->free_host(ring_mem);
+    if (out) {
+      std::memset(out, 0, sizeof(*out));
+      out->arrived = arrived;
+      out->completed = S->completed.load();
+      out->failed = S->failed.load();
+      out->not_admitted = count - arrived;
+      out->vec_batches = S->batches.load();
+      out->t_start_ns = S->t0;
+      out->t_end_ns = S->t0 + S->t_last.load();
+      out->max_backlog = max_backlog;
+    }
     return rc;
   }
 
@@ -897,9 +1251,9 @@ int set_ctx_create(const set_config* cfg, set_ctx** out) {
     return SET_EINVAL;
   }
   if (cfg->num_workers < 1 || cfg->num_workers > setrt::kMaxWorkers || cfg->slots_per_worker < 1 ||
-      cfg->slots_per_worker > setrt::kMaxSlots || cfg->mode < SET_MODE_SET || cfg->mode > SET_MODE_BATCH_SYNC ||
-      cfg->batch_size < 0 || cfg->batch_size > cfg->num_workers || cfg->callback_mode < SET_CB_EVENT_CHAIN ||
-      cfg->callback_mode > SET_CB_EVENT_POLL || cfg->submit_policy < 0 || cfg->submit_policy > SET_SUBMIT_SKEW0 ||
+      cfg->slots_per_worker > setrt::kMaxSlots || cfg->mode < SET_MODE_SET || cfg->mode > SET_MODE_QUEUE ||
+      cfg->batch_size < 0 || cfg->batch_size > cfg->num_workers || cfg->callback_mode < SET_CB_EVENT_POLL ||
+      cfg->callback_mode > SET_CB_SAME_STREAM || cfg->submit_policy < 0 || cfg->submit_policy > SET_SUBMIT_SKEW0 ||
       cfg->inflight_per_worker < 0 || cfg->queue_capacity < 0 || cfg->spin_us < 0 || cfg->staging_capacity < 0 ||
       (cfg->backend != SET_BACKEND_HIP && cfg->backend != SET_BACKEND_FAKE)) {
     setrt::g_create_error = "invalid configuration";
@@ -1031,6 +1385,12 @@ int set_run_vector_jobs(set_ctx* c, int template_id, const set_vec_job* jobs, ui
                         const set_vec_tuning* tuning, uint64_t* batches) {
   if (!c) return SET_EINVAL;
   return c->impl.run_vector_jobs(template_id, jobs, count, results, tuning, batches);
+}
+
+int set_serve(set_ctx* c, const set_request* reqs, uint64_t count, const set_serve_config* cfg, uint64_t* done_ns,
+              float* vec_results, set_serve_stats* stats) {
+  if (!c) return SET_EINVAL;
+  return c->impl.serve(reqs, count, cfg, done_ns, vec_results, stats);
 }
 
 const char* set_last_error(const set_ctx* c) {

@@ -80,6 +80,7 @@ int main() {
   rc |= run(SET_MODE_SET, 8, 16, SET_SUBMIT_SHORTEST, 1, 1, 4, 300) << 3;
   rc |= run(SET_MODE_SYNC, 4, 2, 0, 1, 0, 2, 100) << 4;
   rc |= run(SET_MODE_BATCH_SYNC, 4, 2, 0, 1, 0, 2, 100) << 5;
+  rc |= run(SET_MODE_QUEUE, 4, 2, 0, 1, 0, 3, 200) << 6;
   std::printf("tsan stress rc=%d\n", rc);
   return rc;
 }

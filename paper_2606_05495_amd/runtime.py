@@ -45,7 +45,7 @@ class Context:
     """One SET context: b workers (streams), d slots each, and its templates."""
 
     def __init__(self, mode="set", workers=8, slots=16, backend="hip", queue_capacity=0, inflight=0,
-                 stealing=True, batch_size=0, callback="event_chain", submit_policy=A.SET_SUBMIT_ROUND_ROBIN,
+                 stealing=True, batch_size=0, callback="event_poll", submit_policy=A.SET_SUBMIT_ROUND_ROBIN,
                  spin_us=0, staging=0, mem_budget=0, device=0, seed=0, borrow_streams=True,
                  fake_fail_after=0, fake_reorder=False):
         self.backend = backend
@@ -85,7 +85,7 @@ class Context:
 
     # ------------------------------------------------------------ templates
     def define(self, pipeline, width=0, height=0, max_n=0, flags=0, threshold=0.0, x_pool=None, y_pool=None,
-               borrow_arena=True, pool_ptrs=None, copy="nodes", batch_max=0, tiles_max=0, grid=0):
+               borrow_arena=True, pool_ptrs=None, copy="kernels", batch_max=0, tiles_max=0, grid=0):
         t = A.set_job_template()
         t.pipeline = PIPELINES[pipeline] if isinstance(pipeline, str) else int(pipeline)
         t.flags = flags

@@ -1,0 +1,62 @@
+"""Launch each stage kernel of a template back to back (for rocprofv3 kernel
+traces and hardware-counter runs), plus a plain device copy of known size
+that calibrates the byte counters.
+
+    python -m paper_2606_05495_amd.stage_probe --side 1024 --reps 50
+"""
+from __future__ import annotations
+
+import argparse
+import json
+
+import numpy as np
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--pipeline", default="gauss_sobel", choices=["gauss_sobel", "box_hist", "scan"])
+    ap.add_argument("--side", type=int, default=1024)
+    ap.add_argument("--n", type=int, default=1 << 21)
+    ap.add_argument("--reps", type=int, default=50)
+    ap.add_argument("--copy-mib", type=int, default=64)
+    args = ap.parse_args()
+    import torch
+    from paper_2606_05495_amd import synth
+    from paper_2606_05495_amd.runtime import Context, pinned
+
+    ctx = Context(mode="set", workers=1, slots=2)
+    if args.pipeline == "scan":
+        tid = ctx.define("scan", max_n=args.n)
+        data = synth.scan_input(0, 0, args.n).view(np.uint8)
+    elif args.pipeline == "box_hist":
+        tid = ctx.define("box_hist", width=args.side, height=args.side)
+        data = synth.box_image(0, 0, args.side, args.side).ravel()
+    else:
+        tid = ctx.define("gauss_sobel", width=args.side, height=args.side)
+        data = synth.normal_image(0, 0, args.side, args.side).view(np.uint8).ravel()
+    ib, ob = ctx.in_bytes(tid), ctx.out_bytes(tid)
+    tin, nin = pinned(ib)
+    nin[:] = data
+    tout, _ = pinned(max(ob, 64))
+    for _ in range(4):
+        ctx.submit(tid, host_in=tin.data_ptr(), in_bytes=ib, host_out=tout.data_ptr(), out_bytes=ob)
+    ctx.drain()
+    out = {}
+    for i, (name, nbytes) in enumerate(ctx.stage_info(tid)):
+        out[name] = {"avg_us": round(ctx.time_stage(tid, i, 0, args.reps), 3), "bytes": int(nbytes)}
+    # calibration: a plain device-to-device copy of known size
+    n = args.copy_mib << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(args.reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    out["calibration_copy_bytes"] = n
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

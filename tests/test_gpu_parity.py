@@ -48,7 +48,7 @@ def _check_header(buf, job_id, tag=None):
 
 
 # ------------------------------------------------------------------ box / histogram
-def _run_images(mode, pipeline, imgs, in_dtype, workers=4, slots=4, flags=A.SET_TF_DEBUG, copy="nodes", **kw):
+def _run_images(mode, pipeline, imgs, in_dtype, workers=4, slots=4, flags=A.SET_TF_DEBUG, copy="kernels", **kw):
     h, w = imgs[0].shape
     ctx = Context(mode=mode, workers=workers, slots=slots, **kw)
     tid = ctx.define(pipeline, width=w, height=h, flags=flags, copy=copy)
@@ -96,7 +96,7 @@ def test_box_hist_parity(torch_gpu, mode, shape):
         assert np.array_equal(o[q_off:q_off + h * w].reshape(h, w), Q)
 
 
-@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "set"])
+@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "queue", "set"])
 def test_box_hist_workload_64_jobs(torch_gpu, mode):
     """64 jobs of 256x256 uint8 (uniform, stream key = seed + job id), 4 streams."""
     _say("box_hist 64 jobs", mode)
@@ -163,7 +163,7 @@ def test_gauss_sobel_pins_on_gpu(torch_gpu):
     assert np.all(mask[:, 3:w - 3] == 1)
 
 
-@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "set"])
+@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "queue", "set"])
 def test_gauss_sobel_full_size(torch_gpu, mode):
     """1024x1024 N(0,1) images from the 61-image pool, 8 workers x 16 slots."""
     _say("gauss_sobel 1024^2", mode)
@@ -193,7 +193,7 @@ def vec_pools(torch_gpu):
 
 
 def _run_vec(mode, pools, ns, offs_x, offs_y, avals, workers=4, slots=8, policy=A.SET_SUBMIT_ROUND_ROBIN,
-             copy="nodes"):
+             copy="kernels"):
     x, y, xd, yd = pools
     ctx = Context(mode=mode, workers=workers, slots=slots, submit_policy=policy)
     tid = ctx.define("saxpy_tanh_sum", max_n=int(max(ns)), x_pool=xd, y_pool=yd, copy=copy)
@@ -219,7 +219,7 @@ def _run_vec(mode, pools, ns, offs_x, offs_y, avals, workers=4, slots=8, policy=
     return np.array(res), st
 
 
-@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "set"])
+@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "queue", "set"])
 def test_vector_parity(torch_gpu, vec_pools, mode):
     _say("vector", mode)
     x, y = vec_pools[0], vec_pools[1]
@@ -273,9 +273,13 @@ def test_vector_workload_sample(torch_gpu, vec_pools):
 
 
 # ------------------------------------------------------------------ scan
-def _run_scan(mode, inputs, max_n, low32=False, workers=4, slots=4, copy="nodes"):
+def _run_scan_flags(mode, inputs, max_n, flags, copy):
+    return _run_scan(mode, inputs, max_n, copy=copy, extra_flags=flags)
+
+
+def _run_scan(mode, inputs, max_n, low32=False, workers=4, slots=4, copy="kernels", extra_flags=0):
     ctx = Context(mode=mode, workers=workers, slots=slots)
-    tid = ctx.define("scan", max_n=max_n, flags=A.SET_TF_SCAN_LOW32 if low32 else 0, copy=copy)
+    tid = ctx.define("scan", max_n=max_n, flags=(A.SET_TF_SCAN_LOW32 if low32 else 0) | extra_flags, copy=copy)
     k = len(inputs)
     ib = [4 * len(v) for v in inputs]
     ob = [ctx.out_bytes(tid, len(v)) for v in inputs]
@@ -305,7 +309,7 @@ def _run_scan(mode, inputs, max_n, low32=False, workers=4, slots=4, copy="nodes"
     return res
 
 
-@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "set"])
+@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "queue", "set"])
 def test_scan_parity(torch_gpu, mode):
     _say("scan", mode)
     rng = np.random.default_rng(3)
@@ -362,13 +366,13 @@ def test_set_mode_callbacks_and_steals(torch_gpu, callback):
     assert st.stolen > 0
 
 
-# ------------------------------------------------------------------ copy kernels instead of memcpy nodes
+# ------------------------------------------------------------------ graph memcpy nodes instead of copy kernels
 @pytest.mark.parametrize("mode", ["sync", "graph", "batch", "set"])
-def test_copy_kernels_all_pipelines(torch_gpu, vec_pools, mode):
-    """The same chains with the H2D/D2H performed by the small-grid copy kernels."""
-    _say("copy kernels", mode)
+def test_memcpy_nodes_all_pipelines(torch_gpu, vec_pools, mode):
+    """The same chains with the H2D/D2H as graph memcpy nodes (hipMemcpyAsync in the synchronous model)."""
+    _say("memcpy nodes", mode)
     imgs8 = [synth.box_image(0, j, 37, 201) for j in range(5)]
-    outs, _ = _run_images(mode, "box_hist", imgs8, np.uint8, copy="kernels")
+    outs, _ = _run_images(mode, "box_hist", imgs8, np.uint8, copy="nodes")
     s_off = _up64(64 + 1024)
     q_off = _up64(s_off + 2 * 37 * 201)
     for img, o in zip(imgs8, outs):
@@ -376,23 +380,23 @@ def test_copy_kernels_all_pipelines(torch_gpu, vec_pools, mode):
         assert np.array_equal(o[64:64 + 1024].view(np.uint32), H)
         assert np.array_equal(o[q_off:q_off + 37 * 201].reshape(37, 201), Q)
     imgsf = [synth.normal_image(0, k, 70, 99) for k in range(5)]
-    outs, _ = _run_images(mode, "gauss_sobel", imgsf, np.float32, copy="kernels")
+    outs, _ = _run_images(mode, "gauss_sobel", imgsf, np.float32, copy="nodes")
     for img, o in zip(imgsf, outs):
         _check_gauss(img, o)
     big = [synth.normal_image(0, k) for k in range(3)]
-    outs, _ = _run_images(mode, "gauss_sobel", big, np.float32, workers=8, slots=4, flags=0, copy="kernels")
+    outs, _ = _run_images(mode, "gauss_sobel", big, np.float32, workers=8, slots=4, flags=0, copy="nodes")
     for img, o in zip(big, outs):
         ref = oracle.gauss_sobel(img, want_images=False)
         assert abs(int(o[64:68].view(np.uint32)[0]) - ref["count"]) <= ref["band"]
         assert abs(float(o[68:72].view(np.float32)[0]) - ref["sum"]) <= 1e-5 * abs(ref["sum"])
     rng = np.random.default_rng(11)
     ins = [rng.integers(-(1 << 20), (1 << 20) + 1, n).astype(np.int32) for n in (1, 5, 4097, 1 << 21)]
-    for v, r in zip(ins, _run_scan(mode, ins, max_n=1 << 21, copy="kernels")):
+    for v, r in zip(ins, _run_scan(mode, ins, max_n=1 << 21, copy="nodes")):
         assert np.array_equal(r, oracle.scan(v))
     x, y = vec_pools[0], vec_pools[1]
     ns = np.array([3, 4096, 70001], np.int64)
     got, _ = _run_vec(mode, vec_pools, ns, np.array([0, 64, 128]), np.array([64, 0, 4]),
-                      np.full(3, 1.25, np.float32), copy="kernels")
+                      np.full(3, 1.25, np.float32), copy="nodes")
     for i, n in enumerate(ns):
         xo, yo = [0, 64, 128][i], [64, 0, 4][i]
         S, E = oracle.saxpy_tanh_sum(x[xo:xo + n], y[yo:yo + n], 1.25)
@@ -444,4 +448,113 @@ def test_vector_batching_pins(torch_gpu):
     tid = ctx.define("saxpy_batch", max_n=1 << 22, x_pool=ones, y_pool=zeros, batch_max=4, tiles_max=4096)
     res, _ = ctx.run_vector_jobs(tid, jobs)
     assert np.array_equal(res, ns.astype(np.float32))
+    ctx.close()
+
+
+# ------------------------------------------------------------------ serving: alone vs in the mix
+def test_serve_alone_vs_mix(torch_gpu, vec_pools):
+    """Requests arriving while others run are admitted as slots and memory free up; every result
+    equals the same request run alone, bit for bit, and matches the oracle."""
+    _say("serve alone vs mix")
+    x, y, xd, yd = vec_pools
+    sides = (64, 128, 256)
+    ctx = Context(mode="set", workers=8, slots=4, mem_budget=256 << 20, callback="event_poll")
+    timg = {s: ctx.define("gauss_sobel", width=s, height=s, copy="kernels") for s in sides}
+    tvec = ctx.define("saxpy_batch", max_n=1 << 20, x_pool=xd, y_pool=yd, batch_max=64, tiles_max=4096, copy="kernels")
+    pools = {s: [synth.normal_image(4, k, s, s) for k in range(5)] for s in sides}
+    n_req = 240
+    arr = synth.poisson_arrivals(7, 4000.0, 1.0)[:n_req]
+    mix = synth.serve_mix(7, n_req)
+    vj = synth.vec_jobs(7, n_req, pool_len=len(x), n_span=256.0)
+    req = np.zeros(n_req, dtype=A.REQUEST_DTYPE)
+    req["t_arrival_ns"] = (arr * 1e9).astype(np.uint64)
+    req["worker_hint"] = -1
+    tin, nin = pinned(n_req * 4 * 256 * 256)
+    tout, nout = pinned(n_req * 128)
+    for i in range(n_req):
+        if mix["kind"][i] == 0:
+            s = sides[mix["side_idx"][i] % 3]
+            img = pools[s][mix["pool_idx"][i] % 5]
+            off = i * 4 * 256 * 256
+            nin[off:off + 4 * s * s].view(np.float32)[:] = img.ravel()
+            req[i]["template_id"] = timg[s]
+            req[i]["host_in"] = tin.data_ptr() + off
+            req[i]["in_bytes"] = 4 * s * s
+            req[i]["host_out"] = tout.data_ptr() + 128 * i
+            req[i]["out_bytes"] = 72
+        else:
+            req[i]["template_id"] = tvec
+            req[i]["n"] = vj["n"][i]
+            req[i]["a"] = vj["a"][i]
+            req[i]["x_off"] = vj["x_off"][i]
+            req[i]["y_off"] = vj["y_off"][i]
+    vres = np.zeros(n_req, np.float32)
+    done, st = A.set_serve(ctx.h, req, None, vres)
+    assert st.completed == n_req and st.failed == 0, (st.completed, st.failed)
+    assert np.all(done >= req["t_arrival_ns"])
+    assert st.vec_batches < int(np.sum(mix["kind"] == 1))  # vector requests shared batches
+    assert ctx.stats().mem_high_water <= 256 << 20
+    mixed_img = nout.reshape(n_req, 128)[:, 64:72].copy()
+    # alone: one request at a time through the same templates
+    alone_vec = np.zeros(n_req, np.float32)
+    for i in range(n_req):
+        if mix["kind"][i] == 0:
+            s = sides[mix["side_idx"][i] % 3]
+            r = ctx.submit(timg[s], host_in=int(req[i]["host_in"]), in_bytes=4 * s * s,
+                           host_out=tout.data_ptr() + 128 * i, out_bytes=72)
+            ctx.drain()
+            img = pools[s][mix["pool_idx"][i] % 5]
+            ref = oracle.gauss_sobel(img, want_images=False)
+            o = nout[128 * i:128 * i + 128]
+            assert abs(int(o[64:68].view(np.uint32)[0]) - ref["count"]) <= ref["band"]
+            assert abs(float(o[68:72].view(np.float32)[0]) - ref["sum"]) <= 1e-5 * abs(ref["sum"])
+        else:
+            one = np.zeros(1, dtype=A.VEC_JOB_DTYPE)
+            for f in ("n", "a", "x_off", "y_off"):
+                one[f] = req[i][f]
+            res, _ = ctx.run_vector_jobs(tvec, one)
+            alone_vec[i] = res[0]
+            n, xo, yo = int(req[i]["n"]), int(req[i]["x_off"]), int(req[i]["y_off"])
+            S, E = oracle.saxpy_tanh_sum(x[xo:xo + n], y[yo:yo + n], req[i]["a"])
+            assert abs(res[0] - S) <= oracle.vec_tolerance(S, E)
+    alone_img = nout.reshape(n_req, 128)[:, 64:72].copy()
+    vec = mix["kind"] == 1
+    assert np.array_equal(alone_vec[vec], vres[vec])
+    assert np.array_equal(alone_img[~vec], mixed_img[~vec])
+    ctx.close()
+
+
+# ------------------------------------------------------------------ stream-captured templates
+@pytest.mark.parametrize("mode,copy", [("set", "kernels"), ("set", "nodes"), ("graph", "kernels")])
+def test_captured_templates_match_explicit(torch_gpu, vec_pools, mode, copy):
+    """Graphs built by stream capture of the launch sequence give bit-identical results to
+    explicitly built graphs, for every pipeline, with per-job rebinding working on captured nodes."""
+    _say("captured templates", mode, copy)
+    imgs = [synth.normal_image(0, k, 96, 130) for k in range(6)]
+    a, _ = _run_images(mode, "gauss_sobel", imgs, np.float32, copy=copy)
+    b, _ = _run_images(mode, "gauss_sobel", imgs, np.float32, copy=copy, flags=A.SET_TF_DEBUG | A.SET_TF_CAPTURE)
+    for x, y in zip(a, b):
+        assert np.array_equal(x[64:], y[64:])
+    imgs8 = [synth.box_image(0, j, 64, 200) for j in range(6)]
+    a, _ = _run_images(mode, "box_hist", imgs8, np.uint8, copy=copy, flags=0)
+    b, _ = _run_images(mode, "box_hist", imgs8, np.uint8, copy=copy, flags=A.SET_TF_CAPTURE)
+    for x, y, im in zip(a, b, imgs8):
+        assert np.array_equal(x[64:64 + 1024], y[64:64 + 1024])
+        assert np.array_equal(y[64:64 + 1024].view(np.uint32), oracle.box_hist(im)[2])
+    rng = np.random.default_rng(2)
+    ins = [rng.integers(-(1 << 20), (1 << 20) + 1, n).astype(np.int32) for n in (7, 4097, 1 << 20)]
+    for v, r in zip(ins, _run_scan_flags(mode, ins, 1 << 20, A.SET_TF_CAPTURE, copy)):
+        assert np.array_equal(r, oracle.scan(v))
+    x, y, xd, yd = vec_pools
+    ctx = Context(mode=mode, workers=2, slots=4)
+    tv = ctx.define("saxpy_tanh_sum", max_n=1 << 20, x_pool=xd, y_pool=yd, flags=A.SET_TF_CAPTURE, copy=copy)
+    tout, nout = pinned(128 * 3)
+    ns = [5, 4096, 1 << 20]
+    for i, n in enumerate(ns):
+        ctx.submit(tv, host_out=tout.data_ptr() + 128 * i, out_bytes=68, n=n, a=1.5, x_off=64 * i, y_off=128)
+    ctx.drain()
+    for i, n in enumerate(ns):
+        S, E = oracle.saxpy_tanh_sum(x[64 * i:64 * i + n], y[128:128 + n], 1.5)
+        got = float(nout[128 * i + 64:128 * i + 68].view(np.float32)[0])
+        assert abs(got - S) <= oracle.vec_tolerance(S, E)
     ctx.close()
