@@ -210,6 +210,75 @@ def bench_vectors(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def bench_scan(args, torch):
+    """Copy-engine-bound jobs: 8 MiB int32 H2D -> inclusive int64 scan -> 16 MiB
+    D2H (pool of 31 inputs), SET at several stream counts with stealing on and
+    off, against the batch-synchronised graph and synchronous baselines."""
+    from paper_2606_05495_amd import synth
+    from paper_2606_05495_amd.runtime import Context, pinned
+    import oracle
+    n = 1 << 21
+    P = synth.SCAN_POOL
+    log("generating scan pool (%d x %d int32)" % (P, n))
+    pool = synth.scan_pool(0, P, n)
+    tin, nin = pinned(P * 4 * n)
+    nin.view(np.int32)[:] = pool.ravel()
+    R = args.scan_ring
+    ob = 64 + 8 * n
+    ostride = (ob + 4095) // 4096 * 4096
+    tout, nout = pinned(R * ostride)
+    J = args.scan_jobs
+
+    def job_array(ctx, tid, count):
+        arr = ctx.job_array(count)
+        j = np.arange(count, dtype=np.uint64)
+        arr["host_in"] = tin.data_ptr() + (j % np.uint64(P)) * np.uint64(4 * n)
+        arr["in_bytes"] = 4 * n
+        arr["host_out"] = tout.data_ptr() + (j % np.uint64(R)) * np.uint64(ostride)
+        arr["out_bytes"] = ob
+        arr["n"] = n
+        return arr
+
+    def verify(count):
+        for j in range(min(count, R)):
+            o = nout[j * ostride + 64:j * ostride + ob].view(np.int64)
+            if not np.array_equal(o, oracle.scan(pool[j % P])):
+                return False
+        return True
+
+    runs = []
+    configs = [("set", w, st) for w in (4, 8, 16) for st in (True, False)] + [("batch", 8, False), ("sync", 8, False)]
+    for mode, workers, steal in configs:
+        ctx = Context(mode=mode, workers=workers, slots=4 if mode == "set" else 1, stealing=steal,
+                      batch_size=min(args.batch, workers) if mode == "batch" else 0, callback=args.callback)
+        tid = ctx.define("scan", max_n=n, copy=args.copy)
+        warm = job_array(ctx, tid, min(R, J))
+        ctx.submit_many(tid, warm)
+        ctx.drain()
+        ok = verify(min(R, J))
+        arr = job_array(ctx, tid, J)
+        ctx.reset_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.submit_many(tid, arr)
+        ctx.drain()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = ctx.stats()
+        runs.append({"mode": mode, "workers": workers, "stealing": steal, "jobs_per_s": round(J / dt, 1),
+                     "h2d_GBps": round(J * 4 * n / dt / 1e9, 2), "d2h_GBps": round(J * 8 * n / dt / 1e9, 2),
+                     "stolen": int(st.stolen), "verified": ok})
+        log(json.dumps(runs[-1]))
+        ctx.close()
+    best = max((r for r in runs if r["mode"] == "set"), key=lambda r: r["jobs_per_s"])
+    bsync = next(r for r in runs if r["mode"] == "batch")["jobs_per_s"]
+    line = {"metric": METRIC, "workload": "scan jobs: %d x (8 MiB int32 H2D -> int64 inclusive scan -> 16 MiB D2H)" % J,
+            "value": best["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1, "dtype": "int64", "data": "synthetic",
+            "higher_is_better": True, "vs_baseline": None, "speedup_vs_batch_sync": round(best["jobs_per_s"] / bsync, 3),
+            "best": best, "runs": runs, "config": {"copy": args.copy, "callback": args.callback}}
+    print(json.dumps(line), flush=True)
+
+
 def bench_serve(args, torch):
     """Open-loop serving: Poisson arrivals at each rate for a fixed window; half
     image jobs (Gaussian/Sobel at 256^2, 512^2, 1024^2, 2048^2, uniform) and
@@ -310,7 +379,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-passes", type=int, default=5)
     ap.add_argument("--stage-reps", type=int, default=200)
-    ap.add_argument("--workload", choices=["images", "vectors", "serve"], default="images")
+    ap.add_argument("--workload", choices=["images", "vectors", "serve", "scan"], default="images")
+    ap.add_argument("--scan-jobs", type=int, default=4000)
+    ap.add_argument("--scan-ring", type=int, default=48)
     ap.add_argument("--rates", default="2000,10000,40000")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-pool", type=int, default=16)
@@ -338,6 +409,9 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(args, torch)
+        return
+    if args.workload == "scan":
+        bench_scan(args, torch)
         return
     from paper_2606_05495_amd import synth
     from paper_2606_05495_amd.runtime import pinned
