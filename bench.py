@@ -371,7 +371,7 @@ def main():
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--inflight", type=int, default=0)
     ap.add_argument("--spin-us", type=int, default=0)
-    ap.add_argument("--callback", default="event_poll", choices=["event_chain", "same_stream", "event_poll"])
+    ap.add_argument("--callback", default="event_poll", choices=["event_chain", "same_stream", "event_poll", "host_flag"])
     ap.add_argument("--copy", default="kernels", choices=["nodes", "kernels"],
                     help="job copies as graph memcpy nodes or as small-grid copy kernels")
     ap.add_argument("--baseline-steps", type=int, default=1)
@@ -442,6 +442,10 @@ def main():
     set_ok, set_bad = verify(tout, args.jobs, imgs, refs)
     lat_dev = (times["t_done"] - times["t_launch"]) / 1e3
     lat_sub = (times["t_done"] - times["t_submit"]) / 1e3
+    if args.only == "set":
+        ctx.close()
+        print(json.dumps({"mode": "set", "jobs_per_s": round(set_jps, 1), "verified": bool(set_ok)}), flush=True)
+        return
 
     # dominant kernel of the chain, timed with HIP events on worker 0's stream
     stages = ctx.stage_info(tid)

@@ -101,7 +101,14 @@ enum set_callback_mode {
      * callback stream, hipLaunchHostFunc there (event chaining). */
     SET_CB_EVENT_CHAIN = 1,
     /* hipLaunchHostFunc directly on the worker stream after the graph. */
-    SET_CB_SAME_STREAM = 2
+    SET_CB_SAME_STREAM = 2,
+    /* The job's graph ends with a one-thread kernel node that stores the
+     * job's binding sequence number into the slot's word of a pinned host
+     * array (system-scope release store, after the device-to-host copy node
+     * has finished).  The completion thread watches each worker's oldest
+     * word with plain host loads and calls no HIP function, so it never
+     * contends with the dispatcher inside the HIP runtime.  SET mode only. */
+    SET_CB_HOST_FLAG = 3
 };
 
 enum set_submit_policy {

@@ -36,7 +36,7 @@ struct CbCtx {
 };
 
 struct ChainNodes {
-  hipGraphNode_t h2d = nullptr, d2h = nullptr;
+  hipGraphNode_t h2d = nullptr, d2h = nullptr, flag = nullptr;
   hipGraphNode_t k[kMaxStages] = {};
 };
 
@@ -60,6 +60,9 @@ struct Slot {
   CopyArgs h2d_copy, d2h_copy;
   void* h2d_argv[1] = {&h2d_copy};
   void* d2h_argv[1] = {&d2h_copy};
+  DoneFlagArgs flag{};
+  void* flag_argv[1] = {&flag};
+  uint64_t flag_seq = 0;  // sequence number the completion word will hold when the launched job is done
   int nstages = 0;
   const void* func[kMaxStages] = {};
   dim3 grid[kMaxStages];
@@ -87,6 +90,7 @@ struct Pipe {
   char* arena = nullptr;
   bool own_arena = false;
   void* placeholder = nullptr;  // pinned host buffer the memcpy nodes point at before the first bind
+  uint64_t* words = nullptr;    // completion words, one 64-byte line per slot (SET_CB_HOST_FLAG)
   std::vector<Slot> slots;      // [w * d + s]
   std::vector<BatchGraph> batch;  // [count - 1]
 };
@@ -139,8 +143,9 @@ class HipBackend : public Backend {
       cb_streams_.resize(b_);
       for (int i = 0; i < b_; ++i) HIPCK(hipStreamCreateWithFlags(&cb_streams_[i], hipStreamNonBlocking));
     }
-    if (cfg.mode == SET_MODE_SET && cfg.callback_mode == SET_CB_EVENT_POLL) {
-      poll_q_.resize(b_);
+    flag_mode_ = cfg.mode == SET_MODE_SET && cfg.callback_mode == SET_CB_HOST_FLAG;
+    if (cfg.mode == SET_MODE_SET && (cfg.callback_mode == SET_CB_EVENT_POLL || flag_mode_)) {
+      poll_in_.resize(b_);
       poller_ = std::thread([this] { poll_loop(); });
     }
     return SET_OK;
@@ -177,6 +182,10 @@ class HipBackend : public Backend {
     const uint64_t ph = std::max<uint64_t>(std::max(p.L.in_cap, p.L.out_cap), 64);
     HIPCK(hipHostMalloc(&p.placeholder, ph, hipHostMallocDefault));
     std::memset(p.placeholder, 0, ph);
+    if (flag_mode_) {
+      HIPCK(hipHostMalloc((void**)&p.words, (size_t)b_ * d_ * 64, hipHostMallocDefault));
+      std::memset(p.words, 0, (size_t)b_ * d_ * 64);
+    }
     float taps[3];
     gaussian_taps(taps);
     p.slots.resize((size_t)b_ * d_);
@@ -188,6 +197,8 @@ class HipBackend : public Backend {
         sl.s = s;
         sl.base = p.arena + p.L.total * ((uint64_t)w * d_ + s);
         setup_slot(p, sl, taps);
+        if (p.words) sl.flag = DoneFlagArgs{reinterpret_cast<const DevSlotHdr*>(sl.base + p.L.hdr),
+                                            p.words + ((size_t)w * d_ + s) * 8};
         const uint64_t ch = canary_value(id, w, s, 0), ct = canary_value(id, w, s, 1);
         HIPCK(hipMemcpy(sl.base + p.L.hdr, &ch, 8, hipMemcpyHostToDevice));
         HIPCK(hipMemcpy(sl.base + p.L.tail, &ct, 8, hipMemcpyHostToDevice));
@@ -233,6 +244,7 @@ class HipBackend : public Backend {
     const int w = j->worker;
     hipStream_t st = streams_[w];
     sl.cb = CbCtx{j, done, ctx};
+    sl.flag_seq = j->seq;
     HIPCK(hipGraphLaunch(sl.exec, st));
     switch (cfg_.callback_mode) {
       case SET_CB_EVENT_CHAIN:
@@ -243,14 +255,17 @@ class HipBackend : public Backend {
       case SET_CB_SAME_STREAM:
         HIPCK(hipLaunchHostFunc(st, &HipBackend::host_cb, &sl.cb));
         break;
-      case SET_CB_EVENT_POLL: {
-        HIPCK(hipEventRecord(sl.ev, st));
+      case SET_CB_EVENT_POLL:
+      case SET_CB_HOST_FLAG: {
+        if (!flag_mode_) HIPCK(hipEventRecord(sl.ev, st));
+        bool wake;
         {
           std::lock_guard<std::mutex> g(poll_mu_);
-          poll_q_[w].push_back(&sl);
-          ++poll_pending_;
+          poll_in_[w].push_back(&sl);
+          poll_new_.store(true, std::memory_order_release);
+          wake = poll_idle_;
         }
-        poll_cv_.notify_one();
+        if (wake) poll_cv_.notify_one();
         break;
       }
     }
@@ -425,6 +440,7 @@ class HipBackend : public Backend {
       }
       if (p.own_arena && p.arena) (void)hipFree(p.arena);
       if (p.placeholder) (void)hipHostFree(p.placeholder);
+      if (p.words) (void)hipHostFree(p.words);
     }
     pipes_.clear();
     for (hipStream_t s : cb_streams_) (void)hipStreamDestroy(s);
@@ -447,30 +463,59 @@ class HipBackend : public Backend {
     c.done(c.ctx, c.job, SET_OK);
   }
 
-  // Completion thread of SET_CB_EVENT_POLL: observes each worker's events in
-  // launch order.
+  // Completion thread of SET_CB_EVENT_POLL and SET_CB_HOST_FLAG.  A worker's
+  // jobs complete in launch order (one stream), so only the oldest pending
+  // job of each worker is checked.  New launches are taken over from the
+  // shared lists under the mutex; the checks themselves run without it, so
+  // the dispatcher never waits on a sweep.
+  bool job_done(Slot* sl) {
+    if (flag_mode_) return __atomic_load_n(sl->flag.word, __ATOMIC_ACQUIRE) == sl->flag_seq;
+    return hipEventQuery(sl->ev) == hipSuccess;
+  }
+
   void poll_loop() {
     ensure_dev();
+    std::vector<std::deque<Slot*>> mine(b_);
     std::vector<Slot*> ready;
+    int64_t pending = 0;
     while (true) {
-      {
+      if (pending == 0 || poll_new_.load(std::memory_order_acquire)) {
         std::unique_lock<std::mutex> lk(poll_mu_);
-        poll_cv_.wait(lk, [&] { return poll_stop_ || poll_pending_ > 0; });
-        if (poll_stop_ && poll_pending_ == 0) return;
+        if (pending == 0) {
+          poll_idle_ = true;
+          poll_cv_.wait(lk, [&] {
+            if (poll_stop_) return true;
+            for (auto& v : poll_in_)
+              if (!v.empty()) return true;
+            return false;
+          });
+          poll_idle_ = false;
+        }
+        for (int w = 0; w < b_; ++w) {
+          for (Slot* sl : poll_in_[w]) mine[w].push_back(sl);
+          pending += (int64_t)poll_in_[w].size();
+          poll_in_[w].clear();
+        }
+        poll_new_.store(false, std::memory_order_relaxed);
+        if (poll_stop_ && pending == 0) return;
       }
       ready.clear();
-      {
-        std::lock_guard<std::mutex> g(poll_mu_);
-        for (auto& q : poll_q_) {
-          while (!q.empty() && hipEventQuery(q.front()->ev) == hipSuccess) {
-            ready.push_back(q.front());
-            q.pop_front();
-            --poll_pending_;
-          }
+      for (int w = 0; w < b_; ++w) {
+        auto& q = mine[w];
+        while (!q.empty() && job_done(q.front())) {
+          ready.push_back(q.front());
+          q.pop_front();
+          --pending;
         }
       }
       for (Slot* sl : ready) host_cb(&sl->cb);
-      if (ready.empty()) std::this_thread::yield();
+      if (ready.empty()) {
+        if (flag_mode_) {
+          for (int k = 0; k < 64; ++k) __builtin_ia32_pause();
+        } else {
+          std::this_thread::yield();
+        }
+      }
     }
   }
 
@@ -646,7 +691,22 @@ class HipBackend : public Backend {
       HIPCK(hipGraphAddMemcpyNode1D(&cn->d2h, g, &prev, 1, p.placeholder, sl.base + p.L.out, p.L.out_cap,
                                     hipMemcpyDeviceToHost));
     }
+    if (p.words && g == sl.graph) {
+      hipKernelNodeParams kf = flag_params(sl);
+      HIPCK(hipGraphAddKernelNode(&cn->flag, g, &cn->d2h, 1, &kf));
+    }
     return SET_OK;
+  }
+
+  hipKernelNodeParams flag_params(Slot& sl) {
+    hipKernelNodeParams kp{};
+    kp.func = (void*)&k_done_flag;
+    kp.gridDim = dim3(1);
+    kp.blockDim = dim3(64);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = sl.flag_argv;
+    kp.extra = nullptr;
+    return kp;
   }
 
   // Stream capture of the job's launch sequence (the copies bound to the
@@ -671,12 +731,13 @@ class HipBackend : public Backend {
     } else {
       HIPCK(hipMemcpyAsync(p.placeholder, sl.base + p.L.out, p.L.out_cap, hipMemcpyDeviceToHost, st));
     }
+    if (p.words) HIPCK(hipLaunchKernel((const void*)&k_done_flag, dim3(1), dim3(64), sl.flag_argv, 0, st));
     HIPCK(hipStreamEndCapture(st, out));
     size_t n = 0;
     HIPCK(hipGraphGetNodes(*out, nullptr, &n));
     std::vector<hipGraphNode_t> nodes(n);
     HIPCK(hipGraphGetNodes(*out, nodes.data(), &n));
-    const size_t expect = (p.L.in_cap > 0 ? 1 : 0) + sl.nstages + 1;
+    const size_t expect = (p.L.in_cap > 0 ? 1 : 0) + sl.nstages + 1 + (p.words ? 1 : 0);
     if (n != expect) {
       if (err) *err = "captured graph has an unexpected number of nodes";
       return SET_EDEVICE;
@@ -715,7 +776,8 @@ class HipBackend : public Backend {
       }
       cn->k[i] = order[k++];
     }
-    cn->d2h = order[k];
+    cn->d2h = order[k++];
+    if (p.words) cn->flag = order[k];
     return SET_OK;
   }
 
@@ -756,9 +818,11 @@ class HipBackend : public Backend {
   std::thread poller_;
   std::mutex poll_mu_;
   std::condition_variable poll_cv_;
-  std::vector<std::deque<Slot*>> poll_q_;
-  int64_t poll_pending_ = 0;
+  std::vector<std::vector<Slot*>> poll_in_;  // launched, not yet taken over by the completion thread
+  bool poll_idle_ = false;                     // completion thread waits on poll_cv_
+  std::atomic<bool> poll_new_{false};          // poll_in_ holds entries
   bool poll_stop_ = false;
+  bool flag_mode_ = false;
 };
 
 }  // namespace

@@ -97,6 +97,13 @@ __global__ __launch_bounds__(kBlock) void k_copy_bytes(CopyArgs a) {
   if (t < a.bytes) reinterpret_cast<uint8_t*>(a.dst)[t] = reinterpret_cast<const uint8_t*>(a.src)[t];
 }
 
+// ------------------------------------------------------------------ completion word
+// Runs after the job's device-to-host copy node; the kernel boundary orders
+// the copy's host writes before this store.
+__global__ __launch_bounds__(64) void k_done_flag(DoneFlagArgs a) {
+  if (threadIdx.x == 0) __hip_atomic_store(a.word, a.hdr->seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // ------------------------------------------------------------------ 3x3 box sum (zero padded), uint8 -> uint16
 // Output tile kBoxTW x kBoxTH, input tile + 1-pixel halo staged in LDS.
 __global__ __launch_bounds__(kBlock) void k_box3_u8_u16(BoxArgs a) {

@@ -128,6 +128,14 @@ struct CopyArgs {
 };
 __global__ void k_copy_bytes(CopyArgs a);
 
+// Completion word: one thread stores the job's binding sequence number (from
+// the slot header) into a pinned host word with a system-scope release.
+struct DoneFlagArgs {
+  const DevSlotHdr* hdr;
+  uint64_t* word;
+};
+__global__ void k_done_flag(DoneFlagArgs a);
+
 __global__ void k_box3_u8_u16(BoxArgs a);
 __global__ void k_div9_u16_u8(Div9Args a);
 __global__ void k_hist256_u8(HistArgs a);

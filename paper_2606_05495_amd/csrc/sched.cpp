@@ -1253,7 +1253,7 @@ int set_ctx_create(const set_config* cfg, set_ctx** out) {
   if (cfg->num_workers < 1 || cfg->num_workers > setrt::kMaxWorkers || cfg->slots_per_worker < 1 ||
       cfg->slots_per_worker > setrt::kMaxSlots || cfg->mode < SET_MODE_SET || cfg->mode > SET_MODE_QUEUE ||
       cfg->batch_size < 0 || cfg->batch_size > cfg->num_workers || cfg->callback_mode < SET_CB_EVENT_POLL ||
-      cfg->callback_mode > SET_CB_SAME_STREAM || cfg->submit_policy < 0 || cfg->submit_policy > SET_SUBMIT_SKEW0 ||
+      cfg->callback_mode > SET_CB_HOST_FLAG || cfg->submit_policy < 0 || cfg->submit_policy > SET_SUBMIT_SKEW0 ||
       cfg->inflight_per_worker < 0 || cfg->queue_capacity < 0 || cfg->spin_us < 0 || cfg->staging_capacity < 0 ||
       (cfg->backend != SET_BACKEND_HIP && cfg->backend != SET_BACKEND_FAKE)) {
     setrt::g_create_error = "invalid configuration";

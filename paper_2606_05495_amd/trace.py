@@ -83,6 +83,34 @@ def timeline_metrics(kernels: Sequence[Interval], copies_h2d: Sequence[Interval]
     return out
 
 
+def stream_gaps(kernels: Sequence[Interval], streams: Sequence, names: Sequence[str] = (),
+                is_copy=lambda n: "copy" in n.lower()) -> dict:
+    """Gaps between consecutive kernels of the same stream.
+
+    On one stream a job's kernels run in order (host-to-device copy, stages,
+    device-to-host copy), so a gap there is dispatch latency: either between
+    two kernels of one job (dependency resolution inside a graph) or between
+    one job's last copy and the next job's first copy (the launch path).
+    A pair of two copies is counted as a job boundary; every other pair as a
+    gap inside a job."""
+    by = {}
+    for i, (iv, s) in enumerate(zip(kernels, streams)):
+        by.setdefault(s, []).append((iv[0], iv[1], names[i] if names else ""))
+    allg, intra, inter = [], [], []
+    for s, ks in by.items():
+        ks.sort()
+        for (a0, a1, an), (b0, b1, bn) in zip(ks, ks[1:]):
+            g = max(0.0, b0 - a1)
+            allg.append(g)
+            if names and is_copy(an) and is_copy(bn):
+                inter.append(g)
+            else:
+                intra.append(g)
+    mean = lambda v: (sum(v) / len(v)) if v else None
+    return {"streams": len(by), "mean_stream_gap": mean(allg), "mean_intra_job_gap": mean(intra),
+            "mean_job_boundary_gap": mean(inter) if names else None}
+
+
 def inter_batch_gaps(h2d: Sequence[Interval], d2h: Sequence[Interval], batch: int) -> List[float]:
     """Eq. 3 for consecutive batches of `batch` jobs (copies in time order)."""
     hs = sorted(h2d)
@@ -106,7 +134,7 @@ def load_rocprof(dirpath: str, kernel_filter=None):
     --memory-copy-trace --output-format csv output under dirpath."""
     kfiles = glob.glob(os.path.join(dirpath, "**", "*kernel_trace.csv"), recursive=True)
     cfiles = glob.glob(os.path.join(dirpath, "**", "*memory_copy_trace.csv"), recursive=True)
-    kernels, names = [], []
+    kernels, names, streams = [], [], []
     for f in kfiles:
         with open(f) as fh:
             for row in csv.DictReader(fh):
@@ -116,6 +144,7 @@ def load_rocprof(dirpath: str, kernel_filter=None):
                 kernels.append((float(_col(row, "Start_Timestamp", "BeginNs")),
                                 float(_col(row, "End_Timestamp", "EndNs"))))
                 names.append(name)
+                streams.append(row.get("Stream_Id") or row.get("Queue_Id") or "0")
     h2d, d2h = [], []
     for f in cfiles:
         with open(f) as fh:
@@ -126,14 +155,17 @@ def load_rocprof(dirpath: str, kernel_filter=None):
                     h2d.append(iv)
                 elif "DEVICE_TO_HOST" in d.upper() or "D2H" in d.upper():
                     d2h.append(iv)
-    return kernels, names, h2d, d2h
+    return kernels, names, h2d, d2h, streams
 
 
 def analyze_dir(dirpath: str, batch: int = 0) -> dict:
-    kernels, names, h2d, d2h = load_rocprof(dirpath, kernel_filter=lambda n: "setrt" in n or "k_" in n)
+    kernels, names, h2d, d2h, streams = load_rocprof(
+        dirpath, kernel_filter=lambda n: "setrt" in n or "copyBuffer" in n)
     m = timeline_metrics(kernels, h2d, d2h)
-    m = {k: (v / 1e3 if k in ("span", "busy", "t_schedule", "mean_kernel_gap", "mean_positive_kernel_gap")
-             and v is not None else v) for k, v in m.items()}  # ns -> us
+    m.update(stream_gaps(kernels, streams, names))
+    us_keys = ("span", "busy", "t_schedule", "mean_kernel_gap", "mean_positive_kernel_gap", "mean_stream_gap",
+               "mean_intra_job_gap", "mean_job_boundary_gap")
+    m = {k: (v / 1e3 if k in us_keys and v is not None else v) for k, v in m.items()}  # ns -> us
     m["unit"] = "us"
     m["h2d_copies"] = len(h2d)
     m["d2h_copies"] = len(d2h)
@@ -145,6 +177,66 @@ def analyze_dir(dirpath: str, batch: int = 0) -> dict:
     return m
 
 
+def kernel_stats(dirpath: str) -> dict:
+    """Per-kernel summary of a rocprofv3 --stats run (*_kernel_stats.csv)."""
+    out = {}
+    for f in glob.glob(os.path.join(dirpath, "**", "*kernel_stats.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                out[row["Name"]] = {"calls": int(row["Calls"]), "avg_us": float(row["AverageNs"]) / 1e3,
+                                    "min_us": float(row["MinNs"]) / 1e3, "max_us": float(row["MaxNs"]) / 1e3,
+                                    "total_ms": float(row["TotalDurationNs"]) / 1e6}
+    return out
+
+
+def isolated_run(dirpath: str, name_part: str) -> dict:
+    """The longest run of back-to-back dispatches of one kernel on one stream
+    with no other kernel of that stream in between (the stage-timing loop),
+    and their mean duration (first dispatch of the run excluded)."""
+    rows = []
+    for f in glob.glob(os.path.join(dirpath, "**", "*kernel_trace.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                rows.append((row.get("Stream_Id") or row.get("Queue_Id") or "0",
+                             float(_col(row, "Start_Timestamp", "BeginNs")), float(_col(row, "End_Timestamp", "EndNs")),
+                             _col(row, "Kernel_Name", "Kernel_name", "KernelName")))
+    rows.sort()
+    best, cur = [], []
+    prev_stream = None
+    for stream, a, b, name in rows:
+        if name_part in name and stream == prev_stream and cur:
+            cur.append((a, b))
+        elif name_part in name:
+            cur = [(a, b)]
+        else:
+            cur = []
+        prev_stream = stream
+        if len(cur) > len(best):
+            best = list(cur)
+    if len(best) < 2:
+        return {"dispatches": len(best)}
+    d = [b - a for a, b in best[1:]]
+    return {"dispatches": len(best) - 1, "avg_us": sum(d) / len(d) / 1e3,
+            "wall_per_dispatch_us": (best[-1][1] - best[1][0]) / (len(best) - 1) / 1e3}
+
+
+def summarize(dirpath: str, kernel: str = "", batch: int = 0) -> dict:
+    out = {"timeline": analyze_dir(dirpath, batch=batch), "kernel_stats": kernel_stats(dirpath)}
+    if kernel:
+        out["isolated"] = {kernel: isolated_run(dirpath, kernel)}
+    return out
+
+
 if __name__ == "__main__":
-    b = int(sys.argv[2]) if len(sys.argv) > 2 else 0
-    print(json.dumps(analyze_dir(sys.argv[1], batch=b), indent=1))
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize":
+        import argparse
+        ap = argparse.ArgumentParser()
+        ap.add_argument("cmd")
+        ap.add_argument("dir")
+        ap.add_argument("--kernel", default="")
+        ap.add_argument("--batch", type=int, default=0)
+        a = ap.parse_args()
+        print(json.dumps(summarize(a.dir, a.kernel, a.batch), indent=1))
+    else:
+        b = int(sys.argv[2]) if len(sys.argv) > 2 else 0
+        print(json.dumps(analyze_dir(sys.argv[1], batch=b), indent=1))

@@ -193,9 +193,9 @@ def vec_pools(torch_gpu):
 
 
 def _run_vec(mode, pools, ns, offs_x, offs_y, avals, workers=4, slots=8, policy=A.SET_SUBMIT_ROUND_ROBIN,
-             copy="kernels"):
+             copy="kernels", **kw):
     x, y, xd, yd = pools
-    ctx = Context(mode=mode, workers=workers, slots=slots, submit_policy=policy)
+    ctx = Context(mode=mode, workers=workers, slots=slots, submit_policy=policy, **kw)
     tid = ctx.define("saxpy_tanh_sum", max_n=int(max(ns)), x_pool=xd, y_pool=yd, copy=copy)
     k = len(ns)
     tout, nout = pinned(128 * k)
@@ -277,8 +277,8 @@ def _run_scan_flags(mode, inputs, max_n, flags, copy):
     return _run_scan(mode, inputs, max_n, copy=copy, extra_flags=flags)
 
 
-def _run_scan(mode, inputs, max_n, low32=False, workers=4, slots=4, copy="kernels", extra_flags=0):
-    ctx = Context(mode=mode, workers=workers, slots=slots)
+def _run_scan(mode, inputs, max_n, low32=False, workers=4, slots=4, copy="kernels", extra_flags=0, **kw):
+    ctx = Context(mode=mode, workers=workers, slots=slots, **kw)
     tid = ctx.define("scan", max_n=max_n, flags=(A.SET_TF_SCAN_LOW32 if low32 else 0) | extra_flags, copy=copy)
     k = len(inputs)
     ib = [4 * len(v) for v in inputs]
@@ -336,7 +336,7 @@ def test_scan_full_size_and_low32(torch_gpu):
 
 
 # ------------------------------------------------------------------ scheduling on the device
-@pytest.mark.parametrize("callback", ["event_chain", "same_stream", "event_poll"])
+@pytest.mark.parametrize("callback", ["event_chain", "same_stream", "event_poll", "host_flag"])
 def test_set_mode_callbacks_and_steals(torch_gpu, callback):
     """Skewed submission on the GPU: steals retarget jobs to thieves' slots; results stay exact."""
     _say("set callbacks", callback)
@@ -558,3 +558,40 @@ def test_captured_templates_match_explicit(torch_gpu, vec_pools, mode, copy):
         got = float(nout[128 * i + 64:128 * i + 68].view(np.float32)[0])
         assert abs(got - S) <= oracle.vec_tolerance(S, E)
     ctx.close()
+
+
+# ------------------------------------------------------------------ completion words in pinned host memory
+@pytest.mark.parametrize("capture", [False, True])
+def test_host_flag_completion_all_pipelines(torch_gpu, vec_pools, capture):
+    """SET mode with the completion thread watching per-slot host words (no HIP
+    call on the completion path): every pipeline, explicit and captured graphs."""
+    _say("host_flag", "capture" if capture else "explicit")
+    extra = A.SET_TF_CAPTURE if capture else 0
+    imgs = [synth.box_image(0, j) for j in range(64)]
+    outs, st = _run_images("set", "box_hist", imgs, np.uint8, flags=A.SET_TF_DEBUG | extra, callback="host_flag")
+    for img, o in zip(imgs, outs):
+        assert np.array_equal(o[64:64 + 1024].view(np.uint32), oracle.box_hist(img)[2])
+    assert st.completed == 64
+    g = [synth.normal_image(0, k) for k in range(4)]
+    outs, _ = _run_images("set", "gauss_sobel", g + g, np.float32, workers=8, slots=4, flags=extra,
+                          callback="host_flag")
+    for k, img in enumerate(g + g):
+        ref = oracle.gauss_sobel(img, want_images=False)
+        assert abs(int(outs[k][64:68].view(np.uint32)[0]) - ref["count"]) <= ref["band"]
+        assert abs(float(outs[k][68:72].view(np.float32)[0]) - ref["sum"]) <= 1e-5 * abs(ref["sum"])
+    x, y = vec_pools[0], vec_pools[1]
+    ns = np.array([1, 5, 1024, 4097, 65549, 1 << 20], np.int64)
+    rng = np.random.default_rng(9)
+    xo = 64 * rng.integers(0, (len(x) - ns) // 64)
+    yo = 64 * rng.integers(0, (len(y) - ns) // 64)
+    av = rng.uniform(0.5, 2, len(ns)).astype(np.float32)
+    got, _ = _run_vec("set", vec_pools, np.concatenate([ns] * 8), np.concatenate([xo] * 8),
+                      np.concatenate([yo] * 8), np.concatenate([av] * 8), callback="host_flag")
+    for i, n in enumerate(ns):
+        S, E = oracle.saxpy_tanh_sum(x[xo[i]:xo[i] + n], y[yo[i]:yo[i] + n], av[i])
+        for r in range(8):
+            assert abs(got[r * len(ns) + i] - S) <= oracle.vec_tolerance(S, E), (n, r)
+    inputs = [synth.scan_input(0, k, n) for k, n in enumerate([1, 2047, 2048, 100003, 1 << 20])]
+    res = _run_scan("set", inputs, max_n=1 << 20, extra_flags=extra, callback="host_flag")
+    for v, r in zip(inputs, res):
+        assert np.array_equal(r, oracle.scan(v))

@@ -39,3 +39,20 @@ def test_union_and_gap_invariants():
         assert u <= sum(b - a for a, b in iv) + 1e-9
         # the gaps plus the busy union tile the kernel span exactly
         assert sum(trace.kernel_gaps(iv)) + u == pytest.approx(span)
+
+
+def test_stream_gaps_hand_timeline():
+    # two streams, each running one job: copy, stage, stage, copy, then the next job's copy
+    ks = [(0, 10), (12, 20), (20, 25), (30, 40), (45, 55),      # stream A
+          (0, 5), (5, 6), (9, 10), (10, 20), (20, 21)]           # stream B
+    st = ["A"] * 5 + ["B"] * 5
+    nm = ["copy", "gauss", "sobel", "copy", "copy", "copy", "gauss", "sobel", "copy", "copy"]
+    g = trace.stream_gaps(ks, st, nm)
+    assert g["streams"] == 2
+    # A: 2, 0, 5, 5 ; B: 0, 3, 0, 0
+    assert g["mean_stream_gap"] == pytest.approx(15 / 8)
+    assert g["mean_job_boundary_gap"] == pytest.approx((5 + 0) / 2)
+    assert g["mean_intra_job_gap"] == pytest.approx((2 + 0 + 5 + 0 + 3 + 0) / 6)
+    # without names every pair counts as inside a job
+    g2 = trace.stream_gaps(ks, st)
+    assert g2["mean_job_boundary_gap"] is None and g2["mean_intra_job_gap"] == pytest.approx(15 / 8)
