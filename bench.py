@@ -125,6 +125,41 @@ def traffic_for(kernel_name):
         return None
 
 
+def timeline_from_profile():
+    """Kernel-gap and idle figures per mode from the committed rocprofv3
+    kernel-trace summaries, if they were taken on the current native sources."""
+    path = os.path.join(ROOT, "profiles", "timeline.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        from paper_2606_05495_amd.trace import csrc_digest
+        rec = json.load(open(path))
+        if rec.get("csrc_sha256") != csrc_digest():
+            return None
+        return {"source": "profiles/timeline.json", "command": rec.get("command"), "modes": rec["modes"]}
+    except Exception:
+        return None
+
+
+def copy_reference(torch, nbytes, reps):
+    """A plain device-to-device copy moving the same bytes (half read, half
+    written): the bandwidth HBM delivers at this transfer size."""
+    half = max(16, nbytes // 2)
+    a = torch.empty(half, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(10):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    return {"bytes": 2 * half, "avg_us": round(us, 3), "GBps": round(2 * half / us / 1e3, 1)}
+
+
 def bench_vectors(args, torch):
     """100,000 uneven vector jobs (n log-uniform in [4096, 4194304)) over two
     2^27-element device pools: bucketed persistent batches dispatched by SET vs
@@ -454,10 +489,12 @@ def main():
     dom_name, dom_bytes = stages[dom]
     achieved = dom_bytes / (stage_us[dom] * 1e-6) / 1e9
     ctx.close()
+    ref = copy_reference(torch, int(dom_bytes), args.stage_reps)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_for(dom_name),
                 "kernel": dom_name, "bytes_per_launch": int(dom_bytes), "avg_us": round(stage_us[dom], 3),
-                "stages_us": {n: round(u, 3) for (n, _), u in zip(stages, stage_us)}}
+                "stages_us": {n: round(u, 3) for (n, _), u in zip(stages, stage_us)},
+                "copy_same_bytes": ref, "frac_of_copy": round(achieved / ref["GBps"], 4)}
 
     extra = {}
     if not args.no_baselines and args.only is None:
@@ -477,6 +514,7 @@ def main():
         cpu = cpu_baseline(imgs, args.cpu_passes)
 
     h2d = ib * set_jps / 1e9
+    tl = timeline_from_profile()
     line = {
         "metric": METRIC,
         "value": round(set_jps, 1),
@@ -510,7 +548,8 @@ def main():
                   "host_us_per_job_bind": round(st.host_ns_bind / 1e3 / max(1, st.completed), 2),
                   "host_us_per_job_launch": round(st.host_ns_launch / 1e3 / max(1, st.completed), 2),
                   "host_us_per_job_callback": round(st.host_ns_callback / 1e3 / max(1, st.completed), 2)},
-        "mean_kernel_gap_us": None,
+        "mean_kernel_gap_us": (tl["modes"].get("set", {}).get("mean_kernel_gap") if tl else None),
+        "timeline": tl,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -220,6 +220,32 @@ def isolated_run(dirpath: str, name_part: str) -> dict:
             "wall_per_dispatch_us": (best[-1][1] - best[1][0]) / (len(best) - 1) / 1e3}
 
 
+def csrc_digest() -> str:
+    """sha256 over the native sources (names and bytes), so a stored profile
+    summary can tell whether it was taken on the current code."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def timeline_record(summaries: dict, command: str) -> dict:
+    """Assemble per-mode timeline metrics ({mode: summary-json path}) into
+    the stored record the benchmark reports."""
+    modes = {}
+    for mode, path in summaries.items():
+        with open(path) as fh:
+            t = json.load(fh)["timeline"]
+        modes[mode] = {k: t.get(k) for k in ("mean_kernel_gap", "mean_positive_kernel_gap", "gpu_idle_fraction",
+                                             "mean_stream_gap", "mean_intra_job_gap", "mean_job_boundary_gap",
+                                             "span", "kernels", "mean_inter_batch_us")}
+    return {"csrc_sha256": csrc_digest(), "command": command, "unit": "us", "modes": modes}
+
+
 def summarize(dirpath: str, kernel: str = "", batch: int = 0) -> dict:
     out = {"timeline": analyze_dir(dirpath, batch=batch), "kernel_stats": kernel_stats(dirpath)}
     if kernel:
@@ -228,7 +254,12 @@ def summarize(dirpath: str, kernel: str = "", batch: int = 0) -> dict:
 
 
 if __name__ == "__main__":
-    if len(sys.argv) > 1 and sys.argv[1] == "summarize":
+    if len(sys.argv) > 1 and sys.argv[1] == "timeline":
+        # python -m ...trace timeline OUT.json "COMMAND" mode=summary.json ...
+        rec = timeline_record(dict(a.split("=", 1) for a in sys.argv[4:]), sys.argv[3])
+        with open(sys.argv[2], "w") as fh:
+            json.dump(rec, fh, indent=1)
+    elif len(sys.argv) > 1 and sys.argv[1] == "summarize":
         import argparse
         ap = argparse.ArgumentParser()
         ap.add_argument("cmd")

@@ -253,6 +253,10 @@ def test_invalid_arguments_rejected():
         _fake(workers=0, slots=2)
     with pytest.raises(A.SetError):
         _fake(workers=2, slots=4, inflight=5)  # more permits than slots
+    with pytest.raises(A.SetError):
+        _fake(workers=2, slots=2, callback=A.SET_CB_HOST_FLAG + 1)  # no such completion mechanism
+    for cb in ("event_poll", "event_chain", "same_stream", "host_flag"):
+        _fake(workers=2, slots=2, callback=cb).close()
 
 
 def test_thread_sanitizer_stress():
