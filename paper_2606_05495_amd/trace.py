@@ -84,15 +84,16 @@ def timeline_metrics(kernels: Sequence[Interval], copies_h2d: Sequence[Interval]
 
 
 def stream_gaps(kernels: Sequence[Interval], streams: Sequence, names: Sequence[str] = (),
-                is_copy=lambda n: "copy" in n.lower()) -> dict:
+                is_copy=lambda n: "copy" in n.lower(), is_tail=lambda n: "done_flag" in n) -> dict:
     """Gaps between consecutive kernels of the same stream.
 
     On one stream a job's kernels run in order (host-to-device copy, stages,
-    device-to-host copy), so a gap there is dispatch latency: either between
-    two kernels of one job (dependency resolution inside a graph) or between
-    one job's last copy and the next job's first copy (the launch path).
-    A pair of two copies is counted as a job boundary; every other pair as a
-    gap inside a job."""
+    device-to-host copy, optionally a completion-word kernel), so a gap there
+    is dispatch latency: either between two kernels of one job (dependency
+    resolution inside a graph) or between one job's last kernel and the next
+    job's first copy (the launch path).  A copy that follows a copy or a
+    completion-word kernel starts a new job; every other pair is a gap inside
+    a job."""
     by = {}
     for i, (iv, s) in enumerate(zip(kernels, streams)):
         by.setdefault(s, []).append((iv[0], iv[1], names[i] if names else ""))
@@ -102,7 +103,7 @@ def stream_gaps(kernels: Sequence[Interval], streams: Sequence, names: Sequence[
         for (a0, a1, an), (b0, b1, bn) in zip(ks, ks[1:]):
             g = max(0.0, b0 - a1)
             allg.append(g)
-            if names and is_copy(an) and is_copy(bn):
+            if names and is_copy(bn) and (is_copy(an) or is_tail(an)):
                 inter.append(g)
             else:
                 intra.append(g)

@@ -56,3 +56,12 @@ def test_stream_gaps_hand_timeline():
     # without names every pair counts as inside a job
     g2 = trace.stream_gaps(ks, st)
     assert g2["mean_job_boundary_gap"] is None and g2["mean_intra_job_gap"] == pytest.approx(15 / 8)
+
+
+def test_stream_gaps_with_completion_word_kernel():
+    # copy, stage, copy, flag | copy ... : the flag -> copy pair is the job boundary
+    ks = [(0, 10), (11, 20), (22, 30), (30, 31), (40, 50), (50, 60)]
+    nm = ["copy", "stage", "copy", "k_done_flag", "copy", "stage"]
+    g = trace.stream_gaps(ks, ["A"] * 6, nm)
+    assert g["mean_job_boundary_gap"] == pytest.approx(9.0)
+    assert g["mean_intra_job_gap"] == pytest.approx((1 + 2 + 0 + 0) / 4)
