@@ -55,7 +55,7 @@ def run_mode(mode, args, jobs_per_step, steps, warmup, tin, tout, pool, torch, c
     workers = args.workers
     ctx = Context(mode=mode, workers=workers, slots=args.slots if mode == "set" else 1,
                   batch_size=args.batch if mode == "batch" else 0, callback=callback, inflight=args.inflight,
-                  spin_us=args.spin_us)
+                  spin_us=args.spin_us, dispatchers=args.dispatchers)
     tid = ctx.define("gauss_sobel", width=1024, height=1024, copy=args.copy)
     ib, ob = ctx.in_bytes(tid), ctx.out_bytes(tid)
     stride = 128
@@ -190,7 +190,7 @@ def bench_vectors(args, torch):
 
     out = {}
     # ---- bucketed persistent batches, dispatched by SET
-    ctx = Context(mode="set", workers=args.workers, slots=4, callback=args.callback)
+    ctx = Context(mode="set", workers=args.workers, slots=4, callback=args.callback, dispatchers=args.dispatchers)
     tid = ctx.define("saxpy_batch", max_n=int(js["n"].max()), x_pool=xd, y_pool=yd, batch_max=args.batch_max,
                      tiles_max=args.tiles_max, copy=args.copy)
     tuning = None if args.no_tune else autotune.load()
@@ -210,7 +210,7 @@ def bench_vectors(args, torch):
     # ---- per-job graphs / baselines on the per-job template
     for mode in ("set", "batch", "sync", "queue"):
         c = Context(mode=mode, workers=args.workers, slots=16 if mode == "set" else 1,
-                    batch_size=args.batch if mode == "batch" else 0, callback=args.callback)
+                    batch_size=args.batch if mode == "batch" else 0, callback=args.callback, dispatchers=args.dispatchers)
         t2 = c.define("saxpy_tanh_sum", max_n=int(js["n"].max()), x_pool=xd, y_pool=yd, copy=args.copy)
         tout, nout = pinned(128 * J)
         arr = c.job_array(J)
@@ -240,7 +240,7 @@ def bench_vectors(args, torch):
             "speedup_vs_per_job_set": round(p / out["per_job_set"]["jobs_per_s"], 2),
             "speedup_vs_queue": round(p / out["per_job_queue"]["jobs_per_s"], 2),
             "modes": out, "config": {"workers": args.workers, "batch_max": args.batch_max,
-                                     "tiles_max": args.tiles_max, "copy": args.copy, "callback": args.callback,
+                                     "tiles_max": args.tiles_max, "copy": args.copy, "callback": args.callback, "dispatchers": args.dispatchers,
                                      "tuned": tuning is not None}}
     print(json.dumps(line), flush=True)
 
@@ -285,7 +285,7 @@ def bench_scan(args, torch):
     configs = [("set", w, st) for w in (4, 8, 16) for st in (True, False)] + [("batch", 8, False), ("sync", 8, False)]
     for mode, workers, steal in configs:
         ctx = Context(mode=mode, workers=workers, slots=4 if mode == "set" else 1, stealing=steal,
-                      batch_size=min(args.batch, workers) if mode == "batch" else 0, callback=args.callback)
+                      batch_size=min(args.batch, workers) if mode == "batch" else 0, callback=args.callback, dispatchers=args.dispatchers)
         tid = ctx.define("scan", max_n=n, copy=args.copy)
         warm = job_array(ctx, tid, min(R, J))
         ctx.submit_many(tid, warm)
@@ -310,7 +310,7 @@ def bench_scan(args, torch):
     line = {"metric": METRIC, "workload": "scan jobs: %d x (8 MiB int32 H2D -> int64 inclusive scan -> 16 MiB D2H)" % J,
             "value": best["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1, "dtype": "int64", "data": "synthetic",
             "higher_is_better": True, "vs_baseline": None, "speedup_vs_batch_sync": round(best["jobs_per_s"] / bsync, 3),
-            "best": best, "runs": runs, "config": {"copy": args.copy, "callback": args.callback}}
+            "best": best, "runs": runs, "config": {"copy": args.copy, "callback": args.callback, "dispatchers": args.dispatchers}}
     print(json.dumps(line), flush=True)
 
 
@@ -339,7 +339,7 @@ def bench_serve(args, torch):
     results = []
     for rate in [float(r) for r in args.rates.split(",")]:
         ctx = Context(mode="set", workers=args.workers, slots=args.slots, mem_budget=int(args.mem_budget),
-                      callback=args.callback, inflight=args.inflight)
+                      callback=args.callback, inflight=args.inflight, dispatchers=args.dispatchers)
         timg = {s_: ctx.define("gauss_sobel", width=s_, height=s_, copy=args.copy) for s_ in sides}
         tvec = ctx.define("saxpy_batch", max_n=4194303, x_pool=xd, y_pool=yd, batch_max=args.batch_max,
                           tiles_max=args.tiles_max, copy=args.copy)
@@ -390,7 +390,7 @@ def bench_serve(args, torch):
             "vector jobs, %.0f GB admission cap, %.0f s window" % (args.mem_budget / 1e9, args.serve_seconds),
             "value": results[0]["throughput_jobs_per_s"], "unit": "jobs/s", "n_gpus": 1, "dtype": "f32",
             "data": "synthetic", "higher_is_better": True, "vs_baseline": None, "rates": results,
-            "config": {"workers": args.workers, "slots": args.slots, "copy": args.copy, "callback": args.callback,
+            "config": {"workers": args.workers, "slots": args.slots, "copy": args.copy, "callback": args.callback, "dispatchers": args.dispatchers,
                        "image_pool_per_size": P}}
     print(json.dumps(line), flush=True)
 
@@ -406,6 +406,7 @@ def main():
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--inflight", type=int, default=0)
     ap.add_argument("--spin-us", type=int, default=0)
+    ap.add_argument("--dispatchers", type=int, default=1, help="SET dispatcher threads")
     ap.add_argument("--callback", default="event_poll", choices=["event_chain", "same_stream", "event_poll", "host_flag"])
     ap.add_argument("--copy", default="kernels", choices=["nodes", "kernels"],
                     help="job copies as graph memcpy nodes or as small-grid copy kernels")
@@ -530,7 +531,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "gauss5-sobel-threshold-count/sum 1024x1024 f32 jobs, H2D 4 MiB + D2H 72 B each",
                    "jobs_per_step": args.jobs, "workers": args.workers, "slots_per_worker": args.slots,
-                   "callback": args.callback, "copy": args.copy, "image_pool": pool},
+                   "callback": args.callback, "dispatchers": args.dispatchers, "copy": args.copy, "image_pool": pool},
         "verified": bool(set_ok),
         "h2d_GBps": round(h2d, 2),
         "batch_sync_jobs_per_s": extra.get("batch", {}).get("jobs_per_s"),

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SET_ABI_VERSION 1u
+#define SET_ABI_VERSION 2u
 
 /* ---------------------------------------------------------------- status codes */
 enum set_status {
@@ -192,6 +192,13 @@ typedef struct set_config {
     /* CPU fake backend knobs (ignored by the HIP backend) */
     int32_t fake_fail_after;     /* >0: the N-th launch fails with SET_EDEVICE (error latching tests) */
     int32_t fake_reorder_callbacks; /* 1: completion callbacks may run out of launch order */
+    /* SET mode: dispatcher threads (Algorithm 2 loops); thread t owns the
+     * launch permits of workers w with w % dispatch_threads == t and steals
+     * from every queue.  0 or 1 = the single dispatcher of the paper; capped
+     * at num_workers.  ROCm's graph launch is host-bound (about 16 us per
+     * launch) but scales across threads. */
+    int32_t dispatch_threads;
+    int32_t reserved_cfg;
 } set_config;
 
 typedef struct set_job_template {

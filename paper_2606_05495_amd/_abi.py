@@ -20,7 +20,7 @@ except Exception:  # pragma: no cover - torch is part of the image
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libset.so")
 
-SET_ABI_VERSION = 1
+SET_ABI_VERSION = 2
 
 # status codes
 SET_OK, SET_EINVAL, SET_ENOMEM, SET_EDEVICE, SET_EAGAIN, SET_ETIMEOUT, SET_ECLOSED, SET_EUNSUPPORTED = (
@@ -66,6 +66,8 @@ class set_config(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("fake_fail_after", ctypes.c_int32),
         ("fake_reorder_callbacks", ctypes.c_int32),
+        ("dispatch_threads", ctypes.c_int32),
+        ("reserved_cfg", ctypes.c_int32),
     ]
 
 

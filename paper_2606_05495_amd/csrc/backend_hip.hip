@@ -317,7 +317,7 @@ class HipBackend : public Backend {
       HIPCK(hipLaunchKernel(sl.func[i], sl.grid[i], dim3(kBlock), sl.argv[i], 0, st));
     if (kcopy) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, sl.host_out, sl.out_bytes};
-      HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(kCopyBlocks), dim3(kBlock), sl.d2h_argv, 0, st));
+      HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(d2h_copy_blocks(p.L.out_cap)), dim3(kBlock), sl.d2h_argv, 0, st));
     } else {
       HIPCK(hipMemcpyAsync(sl.host_out, sl.base + p.L.out, sl.out_bytes, hipMemcpyDeviceToHost, st));
     }
@@ -562,8 +562,10 @@ class HipBackend : public Backend {
                              (float*)(b + L.scratch + q)};
         sl.sobelf = SobelFinalArgs{(const uint32_t*)(b + L.scratch), (const float*)(b + L.scratch + q), nb,
                                    (uint32_t*)(b + L.out + 64), (float*)(b + L.out + 68), sc};
-        stage((const void*)&k_gauss5_f32, to_dim3(gauss_grid(h, w)), &sl.gauss);
-        stage((const void*)&k_sobel_thresh_f32, to_dim3(sg), &sl.sobel);
+        const bool win = image_window_path(w);
+        stage(win ? (const void*)&k_gauss5_win_f32 : (const void*)&k_gauss5_f32, to_dim3(gauss_grid(h, w)),
+              &sl.gauss);
+        stage(win ? (const void*)&k_sobel_thresh_win_f32 : (const void*)&k_sobel_thresh_f32, to_dim3(sg), &sl.sobel);
         stage((const void*)&k_sobel_final, dim3(1), &sl.sobelf);
         break;
       }
@@ -653,10 +655,10 @@ class HipBackend : public Backend {
     return kp;
   }
 
-  hipKernelNodeParams copy_params(void** argv) {
+  hipKernelNodeParams copy_params(void** argv, unsigned blocks = kCopyBlocks) {
     hipKernelNodeParams kp{};
     kp.func = (void*)&k_copy_bytes;
-    kp.gridDim = dim3(kCopyBlocks);
+    kp.gridDim = dim3(blocks);
     kp.blockDim = dim3(kBlock);
     kp.sharedMemBytes = 0;
     kp.kernelParams = argv;
@@ -685,7 +687,7 @@ class HipBackend : public Backend {
     }
     if (kcopy) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, p.placeholder, p.L.out_cap};
-      hipKernelNodeParams kp = copy_params(sl.d2h_argv);
+      hipKernelNodeParams kp = copy_params(sl.d2h_argv, d2h_copy_blocks(p.L.out_cap));
       HIPCK(hipGraphAddKernelNode(&cn->d2h, g, &prev, 1, &kp));
     } else {
       HIPCK(hipGraphAddMemcpyNode1D(&cn->d2h, g, &prev, 1, p.placeholder, sl.base + p.L.out, p.L.out_cap,
@@ -727,7 +729,7 @@ class HipBackend : public Backend {
       HIPCK(hipLaunchKernel(sl.func[i], sl.grid[i], dim3(kBlock), sl.argv[i], 0, st));
     if (kcopy) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, p.placeholder, p.L.out_cap};
-      HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(kCopyBlocks), dim3(kBlock), sl.d2h_argv, 0, st));
+      HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(d2h_copy_blocks(p.L.out_cap)), dim3(kBlock), sl.d2h_argv, 0, st));
     } else {
       HIPCK(hipMemcpyAsync(p.placeholder, sl.base + p.L.out, p.L.out_cap, hipMemcpyDeviceToHost, st));
     }
@@ -799,7 +801,7 @@ class HipBackend : public Backend {
     HIPCK(hipGraphExecKernelNodeSetParams(ex, cn.k[0], &kp));
     if (kcopy) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, sl.host_out, sl.out_bytes};
-      hipKernelNodeParams kd = copy_params(sl.d2h_argv);
+      hipKernelNodeParams kd = copy_params(sl.d2h_argv, d2h_copy_blocks(p.L.out_cap));
       HIPCK(hipGraphExecKernelNodeSetParams(ex, cn.d2h, &kd));
     } else {
       HIPCK(hipGraphExecMemcpyNodeSetParams1D(ex, cn.d2h, sl.host_out, sl.base + p.L.out, sl.out_bytes,

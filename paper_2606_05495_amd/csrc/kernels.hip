@@ -269,6 +269,170 @@ __global__ __launch_bounds__(kBlock) void k_sobel_thresh_f32(SobelArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ register-window image kernels
+// Path for float images whose width is a multiple of 4.  A lane owns 4
+// adjacent columns (one 16-byte load or store per row), a wave 256 columns,
+// and slides down kWinRows output rows with the window of input rows in
+// registers: every input row of the wave is loaded before the first result
+// is formed, so each wave has all its loads in flight at once.  Neighbouring
+// columns come from the adjacent lanes by shuffles; lanes 0 and 63 take the
+// columns beyond the wave from two extra (clamped) loads.  A block is 4 waves
+// stacked vertically.
+//
+// Blocks are dealt to the 8 XCDs round-robin in launch order.  xcd_tile
+// renumbers them so each XCD owns a contiguous run of tiles in row-major
+// order: vertically adjacent tiles, which read each other's halo rows, then
+// share one L2.
+__device__ inline void xcd_tile(unsigned& bx, unsigned& by) {
+  const unsigned gx = gridDim.x, n = gx * gridDim.y;
+  const unsigned L = blockIdx.y * gx + blockIdx.x;
+  const unsigned q = n >> 3, rem = n & 7u, x = L & 7u, k = L >> 3;
+  const unsigned t = x * q + (x < rem ? x : rem) + k;  // XCD x owns tiles [x*q + min(x, rem), ...)
+  by = t / gx;
+  bx = t - by * gx;
+}
+
+__device__ inline float4 load_row4(const float* row, int x, bool in4, int wm) {
+  if (in4) return *reinterpret_cast<const float4*>(row + x);
+  const float e = row[wm];  // lanes past the right edge hold the replicated border
+  return make_float4(e, e, e, e);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gauss5_win_f32(GaussArgs a) {
+  constexpr int R = kWinRows;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  unsigned bx, by;
+  xcd_tile(bx, by);
+  if (bx == 0 && by == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
+  const int w = a.w, h = a.h, wm = w - 1, hm = h - 1;
+  const int xw = (int)bx * kWinCols;
+  const int x = xw + 4 * lane;
+  const int y0 = ((int)by * 4 + wave) * R;
+  const bool in4 = x + 3 <= wm;
+  // lane 0 needs columns xw-2, xw-1; lane 63 needs xw+256, xw+257
+  const int hx0 = clampi(lane == 0 ? xw - 2 : xw + kWinCols, 0, wm);
+  const int hx1 = clampi(lane == 0 ? xw - 1 : xw + kWinCols + 1, 0, wm);
+  float4 v[R + 4];
+  float e0[R + 4], e1[R + 4];
+#pragma unroll
+  for (int r = 0; r < R + 4; ++r) {
+    const float* row = a.in + (size_t)clampi(y0 + r - 2, 0, hm) * w;
+    v[r] = load_row4(row, x, in4, wm);
+    e0[r] = row[hx0];
+    e1[r] = row[hx1];
+  }
+  const float g0 = a.g0, g1 = a.g1, g2 = a.g2;
+  float hz[5][4];  // horizontal results of the last 5 input rows (ring)
+#pragma unroll
+  for (int r = 0; r < R + 4; ++r) {
+    float l2 = __shfl_up(v[r].z, 1, 64), l1 = __shfl_up(v[r].w, 1, 64);
+    float r1 = __shfl_down(v[r].x, 1, 64), r2 = __shfl_down(v[r].y, 1, 64);
+    if (lane == 0) {
+      l2 = e0[r];
+      l1 = e1[r];
+    }
+    if (lane == 63) {
+      r1 = e0[r];
+      r2 = e1[r];
+    }
+    const float c[8] = {l2, l1, v[r].x, v[r].y, v[r].z, v[r].w, r1, r2};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float acc = g0 * c[j];
+      acc = fmaf(g1, c[j + 1], acc);
+      acc = fmaf(g2, c[j + 2], acc);
+      acc = fmaf(g1, c[j + 3], acc);
+      acc = fmaf(g0, c[j + 4], acc);
+      hz[r % 5][j] = acc;
+    }
+    if (r >= 4) {
+      const int y = y0 + r - 4;
+      float o[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float acc = g0 * hz[(r - 4) % 5][j];
+        acc = fmaf(g1, hz[(r - 3) % 5][j], acc);
+        acc = fmaf(g2, hz[(r - 2) % 5][j], acc);
+        acc = fmaf(g1, hz[(r - 1) % 5][j], acc);
+        acc = fmaf(g0, hz[r % 5][j], acc);
+        o[j] = acc;
+      }
+      if (y < h && in4) *reinterpret_cast<float4*>(a.out + (size_t)y * w + x) = make_float4(o[0], o[1], o[2], o[3]);
+    }
+  }
+}
+
+// Sobel with the same window: per input row, the horizontal smoothing
+// (left + 2*centre + right) and difference (right - left); per output row,
+// gx = d[y-1] + 2*d[y] + d[y+1] and gy = s[y+1] - s[y-1] (the two 3x3
+// kernels factored).  Mask bytes of a lane go out as one 4-byte store.
+__global__ __launch_bounds__(kBlock) void k_sobel_thresh_win_f32(SobelArgs a) {
+  constexpr int R = kWinRows;
+  __shared__ float s4f[4];
+  __shared__ uint32_t s4u[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  unsigned bx, by;
+  xcd_tile(bx, by);
+  const int w = a.w, h = a.h, wm = w - 1, hm = h - 1;
+  const int xw = (int)bx * kWinCols;
+  const int x = xw + 4 * lane;
+  const int y0 = ((int)by * 4 + wave) * R;
+  const bool in4 = x + 3 <= wm;
+  const int hx = clampi(lane == 0 ? xw - 1 : xw + kWinCols, 0, wm);
+  float4 v[R + 2];
+  float e[R + 2];
+#pragma unroll
+  for (int r = 0; r < R + 2; ++r) {
+    const float* row = a.blur + (size_t)clampi(y0 + r - 1, 0, hm) * w;
+    v[r] = load_row4(row, x, in4, wm);
+    e[r] = row[hx];
+  }
+  const float thr = a.thr;
+  float sum = 0.f;
+  uint32_t cnt = 0;
+  float sm[3][4], df[3][4];
+#pragma unroll
+  for (int r = 0; r < R + 2; ++r) {
+    float left = __shfl_up(v[r].w, 1, 64), right = __shfl_down(v[r].x, 1, 64);
+    if (lane == 0) left = e[r];
+    if (lane == 63) right = e[r];
+    const float c[6] = {left, v[r].x, v[r].y, v[r].z, v[r].w, right};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      sm[r % 3][j] = (c[j] + 2.f * c[j + 1]) + c[j + 2];
+      df[r % 3][j] = c[j + 2] - c[j];
+    }
+    if (r >= 2) {
+      const int y = y0 + r - 2;
+      uint32_t packed = 0;
+      float rs = 0.f;
+      uint32_t rc = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float gx = (df[(r - 2) % 3][j] + 2.f * df[(r - 1) % 3][j]) + df[r % 3][j];
+        const float gy = sm[r % 3][j] - sm[(r - 2) % 3][j];
+        const float mag = sqrtf(gx * gx + gy * gy);
+        const uint32_t on = mag > thr ? 1u : 0u;
+        packed |= on << (8 * j);
+        rc += on;
+        rs += mag;
+      }
+      if (y < h && in4) {
+        *reinterpret_cast<uint32_t*>(a.mask + (size_t)y * w + x) = packed;
+        cnt += rc;
+        sum += rs;
+      }
+    }
+  }
+  const unsigned b = by * gridDim.x + bx;
+  const float bs = block_sum_f32(sum, s4f);
+  const uint32_t bc = block_sum_u32(cnt, s4u);
+  if (threadIdx.x == 0) {
+    a.psum[b] = bs;
+    a.pcount[b] = bc;
+  }
+}
+
 // One block: fixed-order combination of the per-block count and sum.
 __global__ __launch_bounds__(kBlock) void k_sobel_final(SobelFinalArgs a) {
   __shared__ float s4f[4];

@@ -141,7 +141,9 @@ __global__ void k_div9_u16_u8(Div9Args a);
 __global__ void k_hist256_u8(HistArgs a);
 __global__ void k_hist256_final(HistFinalArgs a);
 __global__ void k_gauss5_f32(GaussArgs a);
+__global__ void k_gauss5_win_f32(GaussArgs a);
 __global__ void k_sobel_thresh_f32(SobelArgs a);
+__global__ void k_sobel_thresh_win_f32(SobelArgs a);
 __global__ void k_sobel_final(SobelFinalArgs a);
 __global__ void k_saxpy_tanh_sum_f32(VecArgs a);
 __global__ void k_vec_final(VecFinalArgs a);

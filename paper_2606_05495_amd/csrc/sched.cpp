@@ -127,12 +127,19 @@ class Context {
 
   // ---- SET structures
   std::vector<std::unique_ptr<WorkerQueue>> queues;
-  std::mutex pool_mu;
-  std::condition_variable disp_cv;
-  std::deque<int> pool;            // W_pool: launch permits (worker ids)
+  // W_pool, split by dispatcher thread: dispatcher t holds the launch
+  // permits of workers w with w % ndisp == t, so each worker's launches come
+  // from one thread and keep their order on its stream.
+  struct DispState {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<int> pool;              // launch permits (worker ids)
+    std::atomic<uint64_t> pool_gen{0};
+  };
+  int ndisp = 1;
+  std::vector<std::unique_ptr<DispState>> disp;
   std::atomic<int64_t> queued{0};  // jobs sitting in any Q_i
   std::atomic<uint64_t> push_gen{0};
-  std::atomic<uint64_t> pool_gen{0};
   std::mutex sub_mu;
   std::condition_variable sub_cv;  // submitter waits for queue room / slots / budget
   std::atomic<uint64_t> room_gen{0};
@@ -143,7 +150,8 @@ class Context {
   std::mutex done_mu;
   std::condition_variable done_cv;
 
-  std::thread submitter, dispatcher;
+  std::thread submitter;
+  std::vector<std::thread> dispatchers;
   std::atomic<bool> stopping{false};
 
   // ---- queue model (SET_MODE_QUEUE)
@@ -306,11 +314,13 @@ class Context {
         queues[i].reset(new WorkerQueue());
         queues[i]->init(qcap);
       }
+      ndisp = std::max(1, std::min(cfg.dispatch_threads, b));
+      for (int t = 0; t < ndisp; ++t) disp.emplace_back(new DispState());
       // permits interleaved across workers so the first launches spread out
       for (int r = 0; r < kperm; ++r)
-        for (int w = 0; w < b; ++w) pool.push_back(w);
+        for (int w = 0; w < b; ++w) disp[w % ndisp]->pool.push_back(w);
       submitter = std::thread([this] { submitter_loop(); });
-      dispatcher = std::thread([this] { dispatcher_loop(); });
+      for (int t = 0; t < ndisp; ++t) dispatchers.emplace_back([this, t] { dispatcher_loop(t); });
     }
     if (cfg.mode == SET_MODE_QUEUE) issuer = std::thread([this] { issuer_loop(); });
     return SET_OK;
@@ -323,16 +333,17 @@ class Context {
         stage_cv.notify_all();
         stage_room_cv.notify_all();
       }
-      {
-        std::lock_guard<std::mutex> g(pool_mu);
-        disp_cv.notify_all();
+      for (auto& ds : disp) {
+        std::lock_guard<std::mutex> g(ds->mu);
+        ds->cv.notify_all();
       }
       {
         std::lock_guard<std::mutex> g(sub_mu);
         sub_cv.notify_all();
       }
       if (submitter.joinable()) submitter.join();
-      if (dispatcher.joinable()) dispatcher.join();
+      for (auto& th : dispatchers)
+        if (th.joinable()) th.join();
       if (issuer.joinable()) issuer.join();
       if (be) be->shutdown();
     }
@@ -428,11 +439,14 @@ class Context {
     --inflight;
     free_job(j);
     {
-      std::lock_guard<std::mutex> g(pool_mu);
-      pool.push_back(w);  // W_pool.push(w)
-      ++pool_gen;
+      DispState& ds = *disp[w % ndisp];
+      {
+        std::lock_guard<std::mutex> g(ds.mu);
+        ds.pool.push_back(w);  // W_pool.push(w)
+        ++ds.pool_gen;
+      }
+      ds.cv.notify_one();  // notify_one()
     }
-    disp_cv.notify_one();  // notify_one()
     {
       std::lock_guard<std::mutex> g(sub_mu);
       ++room_gen;
@@ -521,12 +535,9 @@ class Context {
       uint32_t sz = 0;
       queues[w]->try_push(j, &sz);  // cannot fail: only this thread pushes and pick_worker saw room
       update_max(st_q_hw, sz);
-      {
-        std::lock_guard<std::mutex> g(pool_mu);
-        ++queued;
-        ++push_gen;
-      }
-      disp_cv.notify_one();
+      ++queued;
+      ++push_gen;
+      wake_dispatchers(w);
       return 1;
     }
     return 0;
@@ -632,13 +643,25 @@ class Context {
     }
   }
 
-  void dispatcher_loop() {
+  // A job was pushed to Q_w: wake w's dispatcher, and with stealing the
+  // others too (a thief with a free permit may take it).
+  void wake_dispatchers(int w) {
+    for (int t = 0; t < ndisp; ++t) {
+      if (t != w % ndisp && !cfg.work_stealing) continue;
+      DispState& ds = *disp[t];
+      { std::lock_guard<std::mutex> g(ds.mu); }
+      ds.cv.notify_one();
+    }
+  }
+
+  void dispatcher_loop(int t) {
+    DispState& ds = *disp[t];
     std::vector<int> snapshot;
     while (true) {
       uint64_t gen_seen, pool_seen;
       {
-        std::unique_lock<std::mutex> lk(pool_mu);
-        auto ready = [&] { return (!pool.empty() && queued.load() > 0) || stopping.load(); };
+        std::unique_lock<std::mutex> lk(ds.mu);
+        auto ready = [&] { return (!ds.pool.empty() && queued.load() > 0) || stopping.load(); };
         if (!ready() && cfg.spin_us > 0) {
           lk.unlock();
           const uint64_t until = now_ns() + (uint64_t)cfg.spin_us * 1000ull;
@@ -648,13 +671,15 @@ class Context {
           }
           lk.lock();
         }
-        disp_cv.wait(lk, ready);
+        ds.cv.wait(lk, ready);
         if (stopping.load() && queued.load() == 0) return;
-        snapshot.assign(pool.begin(), pool.end());
+        snapshot.assign(ds.pool.begin(), ds.pool.end());
         gen_seen = push_gen.load();
-        pool_seen = pool_gen.load();
+        pool_seen = ds.pool_gen.load();
       }
-      // W_pool.pop(), FindJob; a permit that finds nothing goes back (reading 1)
+      // W_pool.pop(), FindJob; a permit that finds nothing goes back (reading 1).
+      // Only this thread removes permits from its pool, so each snapshot
+      // entry is still there when it is taken below.
       int chosen = -1;
       JobRec* job = nullptr;
       for (size_t i = 0; i < snapshot.size() && !job; ++i) {
@@ -666,19 +691,18 @@ class Context {
         if (job) chosen = w;
       }
       if (!job) {
-        std::unique_lock<std::mutex> lk(pool_mu);
-        timed_wait(disp_cv, lk, std::chrono::milliseconds(20), [&] {
-          return push_gen.load() != gen_seen || pool_gen.load() != pool_seen ||
+        std::unique_lock<std::mutex> lk(ds.mu);
+        timed_wait(ds.cv, lk, std::chrono::milliseconds(20), [&] {
+          return push_gen.load() != gen_seen || ds.pool_gen.load() != pool_seen ||
                  (stopping.load() && queued.load() == 0);
         });
         continue;
       }
       {
-        std::lock_guard<std::mutex> g(pool_mu);
-        auto it = std::find(pool.begin(), pool.end(), chosen);
-        pool.erase(it);
-        --queued;
+        std::lock_guard<std::mutex> g(ds.mu);
+        ds.pool.erase(std::find(ds.pool.begin(), ds.pool.end(), chosen));
       }
+      --queued;
       launch_job(job, chosen);  // LaunchJob
     }
   }
@@ -1255,6 +1279,7 @@ int set_ctx_create(const set_config* cfg, set_ctx** out) {
       cfg->batch_size < 0 || cfg->batch_size > cfg->num_workers || cfg->callback_mode < SET_CB_EVENT_POLL ||
       cfg->callback_mode > SET_CB_HOST_FLAG || cfg->submit_policy < 0 || cfg->submit_policy > SET_SUBMIT_SKEW0 ||
       cfg->inflight_per_worker < 0 || cfg->queue_capacity < 0 || cfg->spin_us < 0 || cfg->staging_capacity < 0 ||
+      cfg->dispatch_threads < 0 || cfg->dispatch_threads > setrt::kMaxWorkers ||
       (cfg->backend != SET_BACKEND_HIP && cfg->backend != SET_BACKEND_FAKE)) {
     setrt::g_create_error = "invalid configuration";
     return SET_EINVAL;

@@ -9,7 +9,8 @@
 
 #include "set.h"
 
-static int run(int mode, int b, int d, int policy, int stealing, int reorder, int producers, int per_producer) {
+static int run(int mode, int b, int d, int policy, int stealing, int reorder, int producers, int per_producer,
+               int dispatchers = 1) {
   set_config cfg;
   std::memset(&cfg, 0, sizeof(cfg));
   cfg.abi_version = SET_ABI_VERSION;
@@ -21,6 +22,7 @@ static int run(int mode, int b, int d, int policy, int stealing, int reorder, in
   cfg.submit_policy = policy;
   cfg.fake_reorder_callbacks = reorder;
   cfg.staging_capacity = 64;
+  cfg.dispatch_threads = dispatchers;
   set_ctx* c = nullptr;
   if (set_ctx_create(&cfg, &c) != SET_OK) {
     std::printf("create failed: %s\n", set_last_error(nullptr));
@@ -81,6 +83,8 @@ int main() {
   rc |= run(SET_MODE_SYNC, 4, 2, 0, 1, 0, 2, 100) << 4;
   rc |= run(SET_MODE_BATCH_SYNC, 4, 2, 0, 1, 0, 2, 100) << 5;
   rc |= run(SET_MODE_QUEUE, 4, 2, 0, 1, 0, 3, 200) << 6;
+  rc |= run(SET_MODE_SET, 6, 8, SET_SUBMIT_SKEW0, 1, 1, 3, 300, 3) << 7;
+  rc |= run(SET_MODE_SET, 4, 4, SET_SUBMIT_ROUND_ROBIN, 0, 1, 2, 200, 2) << 8;
   std::printf("tsan stress rc=%d\n", rc);
   return rc;
 }

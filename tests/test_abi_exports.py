@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(A.set_config) == 88
+    assert ctypes.sizeof(A.set_config) == 96
     assert ctypes.sizeof(A.set_job_args) == 80 == A.JOB_ARGS_DTYPE.itemsize
     assert ctypes.sizeof(A.set_out_header) == 64 == A.OUT_HEADER_DTYPE.itemsize
     assert ctypes.sizeof(A.set_job_template) == 88

@@ -127,7 +127,10 @@ def _check_gauss(img, o, exact_mask=True):
     return ref
 
 
-GAUSS_SHAPES = [(1, 1), (1, 9), (9, 1), (2, 3), (5, 5), (16, 64), (17, 65), (33, 17), (100, 130), (256, 256)]
+# widths that are multiples of 4 take the register-window kernels (ragged
+# against the 256-column / 16-row block), the others the LDS-tile kernels
+GAUSS_SHAPES = [(1, 1), (1, 9), (9, 1), (2, 3), (5, 5), (16, 64), (17, 65), (33, 17), (100, 130), (256, 256),
+                (1, 4), (3, 8), (70, 4), (17, 260), (35, 516), (2, 1028), (257, 264)]
 
 
 @pytest.mark.parametrize("mode", ["sync", "set"])
@@ -142,10 +145,12 @@ def test_gauss_sobel_parity(torch_gpu, mode, shape):
         _check_gauss(img, o)
 
 
-def test_gauss_sobel_pins_on_gpu(torch_gpu):
-    """Constant image: zero gradient everywhere; impulse: blur = g_i*g_j in float32."""
-    _say("gauss_sobel pins")
-    h, w = 24, 70
+@pytest.mark.parametrize("w", [70, 72])
+def test_gauss_sobel_pins_on_gpu(torch_gpu, w):
+    """Constant image: zero gradient everywhere; impulse: blur = g_i*g_j in float32
+    (width 70: LDS-tile kernels, 72: register-window kernels)."""
+    _say("gauss_sobel pins", w)
+    h = 24
     const = np.full((h, w), 3.25, np.float32)
     imp = np.zeros((h, w), np.float32)
     imp[10, 30] = 1.0

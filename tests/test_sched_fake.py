@@ -46,9 +46,9 @@ def _fake(**kw):
     return Context(**kw)
 
 
-@pytest.mark.parametrize("b,d", [(1, 2), (4, 8), (8, 16)])
-def test_every_job_completes_once(b, d):
-    with _fake(workers=b, slots=d) as ctx:
+@pytest.mark.parametrize("b,d,nd", [(1, 2, 1), (4, 8, 1), (8, 16, 1), (8, 16, 4), (5, 4, 3), (2, 2, 8)])
+def test_every_job_completes_once(b, d, nd):
+    with _fake(workers=b, slots=d, dispatchers=nd) as ctx:
         tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
         arr, outs = _vec_jobs(ctx, tid, 500, np.random.default_rng(0).integers(1, 60, 500))
         first = ctx.submit_many(tid, arr)
@@ -68,8 +68,9 @@ def test_every_job_completes_once(b, d):
         assert sum(st.launches_per_worker[:b]) == 500
 
 
-def test_skewed_submission_forces_steals_and_retargets():
-    with _fake(workers=4, slots=8, submit_policy=A.SET_SUBMIT_SKEW0) as ctx:
+@pytest.mark.parametrize("nd", [1, 2, 4])
+def test_skewed_submission_forces_steals_and_retargets(nd):
+    with _fake(workers=4, slots=8, submit_policy=A.SET_SUBMIT_SKEW0, dispatchers=nd) as ctx:
         tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
         arr, outs = _vec_jobs(ctx, tid, 400, 200)
         ctx.submit_many(tid, arr)
@@ -90,8 +91,9 @@ def test_skewed_submission_forces_steals_and_retargets():
         assert sum(st.launches_per_worker[1:4]) > 0
 
 
-def test_no_stealing_keeps_jobs_local():
-    with _fake(workers=4, slots=8, submit_policy=A.SET_SUBMIT_SKEW0, stealing=False) as ctx:
+@pytest.mark.parametrize("nd", [1, 3])
+def test_no_stealing_keeps_jobs_local(nd):
+    with _fake(workers=4, slots=8, submit_policy=A.SET_SUBMIT_SKEW0, stealing=False, dispatchers=nd) as ctx:
         tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
         arr, outs = _vec_jobs(ctx, tid, 100, 50)
         ctx.submit_many(tid, arr)
@@ -255,6 +257,8 @@ def test_invalid_arguments_rejected():
         _fake(workers=2, slots=4, inflight=5)  # more permits than slots
     with pytest.raises(A.SetError):
         _fake(workers=2, slots=2, callback=A.SET_CB_HOST_FLAG + 1)  # no such completion mechanism
+    with pytest.raises(A.SetError):
+        _fake(workers=2, slots=2, dispatchers=-1)
     for cb in ("event_poll", "event_chain", "same_stream", "host_flag"):
         _fake(workers=2, slots=2, callback=cb).close()
 
