@@ -153,12 +153,17 @@ enum set_pipeline {
     SET_PIPE_SAXPY_BATCH_F32 = 4
 };
 
-/* How a job's host<->device copies execute (both are part of the job's graph). */
+/* How a job's host<->device copies execute. */
 enum set_copy_mode {
-    SET_COPY_KERNELS = 0, /* small-grid copy kernels that pull the input from / push the output to pinned
-                             host memory; host buffers must be 16-byte aligned.  Default: ROCm runs graph
-                             memcpy nodes as large-grid blit kernels that crowd out the stage kernels */
-    SET_COPY_NODES = 1    /* graph memcpy nodes (hipMemcpyAsync in the synchronous model) */
+    SET_COPY_KERNELS = 0, /* small-grid copy kernels, nodes of the job's graph, that pull the input from /
+                             push the output to pinned host memory; host buffers must be 16-byte aligned.
+                             Default: ROCm runs graph memcpy nodes as large-grid blit kernels that crowd
+                             out the stage kernels */
+    SET_COPY_NODES = 1,   /* graph memcpy nodes (hipMemcpyAsync in the synchronous model) */
+    SET_COPY_ASYNC_IN = 2 /* for jobs that move much data both ways: the input goes by hipMemcpyAsync on
+                             the worker stream right before the graph launch (the graph holds the stages
+                             and a device-to-host copy kernel); that pair moved 77 GB/s in both directions
+                             together against 67 GB/s for two copy kernels.  Host buffers 16-byte aligned */
 };
 
 /* template flags */

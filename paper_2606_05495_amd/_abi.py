@@ -34,8 +34,8 @@ SET_SUBMIT_ROUND_ROBIN, SET_SUBMIT_SHORTEST, SET_SUBMIT_SKEW0 = 0, 1, 2
 SET_PIPE_BOX_HIST_U8, SET_PIPE_GAUSS_SOBEL_F32, SET_PIPE_SAXPY_TANH_SUM_F32, SET_PIPE_SCAN_I32_I64 = 0, 1, 2, 3
 SET_PIPE_SAXPY_BATCH_F32 = 4
 SET_TF_DEBUG, SET_TF_SCAN_LOW32, SET_TF_CAPTURE = 0x1, 0x2, 0x4
-SET_COPY_KERNELS, SET_COPY_NODES = 0, 1
-COPY_MODES = {"nodes": SET_COPY_NODES, "kernels": SET_COPY_KERNELS}
+SET_COPY_KERNELS, SET_COPY_NODES, SET_COPY_ASYNC_IN = 0, 1, 2
+COPY_MODES = {"nodes": SET_COPY_NODES, "kernels": SET_COPY_KERNELS, "async_in": SET_COPY_ASYNC_IN}
 SET_NONBLOCK = 0x1
 SET_OUT_MAGIC = 0x5E7D0A11
 

@@ -107,6 +107,13 @@ void gaussian_taps(float out[3]) {
 
 inline dim3 to_dim3(Grid3 g) { return dim3(g.x, g.y, g.z); }
 
+// Copy mechanisms of a template: the input by copy kernel, by a graph memcpy
+// node, or by hipMemcpyAsync ahead of the graph; the output by copy kernel or
+// graph memcpy node.
+inline bool in_by_kernel(const set_job_template& t) { return t.copy_mode == SET_COPY_KERNELS; }
+inline bool in_ahead(const set_job_template& t) { return t.copy_mode == SET_COPY_ASYNC_IN; }
+inline bool out_by_kernel(const set_job_template& t) { return t.copy_mode != SET_COPY_NODES; }
+
 thread_local int t_dev = -1;
 
 class HipBackend : public Backend {
@@ -245,6 +252,7 @@ class HipBackend : public Backend {
     hipStream_t st = streams_[w];
     sl.cb = CbCtx{j, done, ctx};
     sl.flag_seq = j->seq;
+    HIPCK(input_ahead(p, sl, st));
     HIPCK(hipGraphLaunch(sl.exec, st));
     switch (cfg_.callback_mode) {
       case SET_CB_EVENT_CHAIN:
@@ -277,6 +285,7 @@ class HipBackend : public Backend {
     Pipe& p = *pipes_[j->tmpl];
     Slot& sl = p.slots[(size_t)j->worker * d_ + j->slot];
     hipStream_t st = streams_[j->worker];
+    HIPCK(input_ahead(p, sl, st));
     HIPCK(hipGraphLaunch(sl.exec, st));
     HIPCK(hipEventRecord(sl.ev, st));
     return SET_OK;
@@ -304,9 +313,8 @@ class HipBackend : public Backend {
     Slot& sl = p.slots[(size_t)si * d_];
     set_scalars(p, sl, j);
     hipStream_t st = streams_[si];
-    const bool kcopy = p.t.copy_mode == SET_COPY_KERNELS;
     if (sl.in_bytes) {
-      if (kcopy) {
+      if (in_by_kernel(p.t)) {
         sl.h2d_copy = CopyArgs{sl.host_in, sl.base + p.L.in, sl.in_bytes};
         HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(kCopyBlocks), dim3(kBlock), sl.h2d_argv, 0, st));
       } else {
@@ -315,7 +323,7 @@ class HipBackend : public Backend {
     }
     for (int i = 0; i < sl.nstages; ++i)
       HIPCK(hipLaunchKernel(sl.func[i], sl.grid[i], dim3(kBlock), sl.argv[i], 0, st));
-    if (kcopy) {
+    if (out_by_kernel(p.t)) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, sl.host_out, sl.out_bytes};
       HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(d2h_copy_blocks(p.L.out_cap)), dim3(kBlock), sl.d2h_argv, 0, st));
     } else {
@@ -335,6 +343,7 @@ class HipBackend : public Backend {
     int rc = update_exec(p, sl, sl.exec, sl.nodes, err);
     if (rc != SET_OK) return rc;
     hipStream_t st = streams_[si];
+    HIPCK(input_ahead(p, sl, st));
     HIPCK(hipGraphLaunch(sl.exec, st));
     const uint64_t t0 = now_ns();
     HIPCK(hipStreamSynchronize(st));
@@ -368,6 +377,7 @@ class HipBackend : public Backend {
       set_scalars(p, sl, jobs[i]);
       int rc = update_exec(p, sl, bg.ex, bg.chains[i], err);
       if (rc != SET_OK) return rc;
+      HIPCK(input_ahead(p, sl, streams_[0]));
     }
     HIPCK(hipGraphLaunch(bg.ex, streams_[0]));
     const uint64_t t0 = now_ns();
@@ -666,10 +676,16 @@ class HipBackend : public Backend {
     return kp;
   }
 
+  // SET_COPY_ASYNC_IN: the job's input copy, stream-ordered ahead of its graph.
+  hipError_t input_ahead(Pipe& p, Slot& sl, hipStream_t st) {
+    if (!in_ahead(p.t) || sl.in_bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(sl.base + p.L.in, sl.host_in, sl.in_bytes, hipMemcpyHostToDevice, st);
+  }
+
   int add_chain(Pipe& p, Slot& sl, hipGraph_t g, ChainNodes* cn, std::string* err) {
-    const bool kcopy = p.t.copy_mode == SET_COPY_KERNELS;
+    const bool kcopy = in_by_kernel(p.t);
     hipGraphNode_t prev = nullptr;
-    if (p.L.in_cap > 0) {
+    if (p.L.in_cap > 0 && !in_ahead(p.t)) {
       if (kcopy) {
         sl.h2d_copy = CopyArgs{p.placeholder, sl.base + p.L.in, p.L.in_cap};
         hipKernelNodeParams kp = copy_params(sl.h2d_argv);
@@ -685,7 +701,7 @@ class HipBackend : public Backend {
       HIPCK(hipGraphAddKernelNode(&cn->k[i], g, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
       prev = cn->k[i];
     }
-    if (kcopy) {
+    if (out_by_kernel(p.t)) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, p.placeholder, p.L.out_cap};
       hipKernelNodeParams kp = copy_params(sl.d2h_argv, d2h_copy_blocks(p.L.out_cap));
       HIPCK(hipGraphAddKernelNode(&cn->d2h, g, &prev, 1, &kp));
@@ -715,9 +731,10 @@ class HipBackend : public Backend {
   // placeholder), then the captured chain is walked from its root to find
   // the nodes the binder updates.
   int capture_chain(Pipe& p, Slot& sl, hipStream_t st, hipGraph_t* out, ChainNodes* cn, std::string* err) {
-    const bool kcopy = p.t.copy_mode == SET_COPY_KERNELS;
+    const bool kcopy = in_by_kernel(p.t);
+    const bool in_node = p.L.in_cap > 0 && !in_ahead(p.t);
     HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    if (p.L.in_cap > 0) {
+    if (in_node) {
       if (kcopy) {
         sl.h2d_copy = CopyArgs{p.placeholder, sl.base + p.L.in, p.L.in_cap};
         HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(kCopyBlocks), dim3(kBlock), sl.h2d_argv, 0, st));
@@ -727,7 +744,7 @@ class HipBackend : public Backend {
     }
     for (int i = 0; i < sl.nstages; ++i)
       HIPCK(hipLaunchKernel(sl.func[i], sl.grid[i], dim3(kBlock), sl.argv[i], 0, st));
-    if (kcopy) {
+    if (out_by_kernel(p.t)) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, p.placeholder, p.L.out_cap};
       HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(d2h_copy_blocks(p.L.out_cap)), dim3(kBlock), sl.d2h_argv, 0, st));
     } else {
@@ -739,7 +756,7 @@ class HipBackend : public Backend {
     HIPCK(hipGraphGetNodes(*out, nullptr, &n));
     std::vector<hipGraphNode_t> nodes(n);
     HIPCK(hipGraphGetNodes(*out, nodes.data(), &n));
-    const size_t expect = (p.L.in_cap > 0 ? 1 : 0) + sl.nstages + 1 + (p.words ? 1 : 0);
+    const size_t expect = (in_node ? 1 : 0) + sl.nstages + 1 + (p.words ? 1 : 0);
     if (n != expect) {
       if (err) *err = "captured graph has an unexpected number of nodes";
       return SET_EDEVICE;
@@ -768,7 +785,7 @@ class HipBackend : public Backend {
       return SET_EDEVICE;
     }
     size_t k = 0;
-    if (p.L.in_cap > 0) cn->h2d = order[k++];
+    if (in_node) cn->h2d = order[k++];
     for (int i = 0; i < sl.nstages; ++i) {
       hipKernelNodeParams kp{};
       HIPCK(hipGraphKernelNodeGetParams(order[k], &kp));
@@ -786,8 +803,8 @@ class HipBackend : public Backend {
   // UpdateGraphParams: retarget an executable's chain to the slot's current
   // binding (H2D source, first kernel's argument block and grid, D2H target).
   int update_exec(Pipe& p, Slot& sl, hipGraphExec_t ex, const ChainNodes& cn, std::string* err) {
-    const bool kcopy = p.t.copy_mode == SET_COPY_KERNELS;
-    if (sl.in_bytes) {
+    const bool kcopy = in_by_kernel(p.t);
+    if (sl.in_bytes && cn.h2d) {
       if (kcopy) {
         sl.h2d_copy = CopyArgs{sl.host_in, sl.base + p.L.in, sl.in_bytes};
         hipKernelNodeParams kp = copy_params(sl.h2d_argv);
@@ -799,7 +816,7 @@ class HipBackend : public Backend {
     }
     hipKernelNodeParams kp = kparams(sl, 0);
     HIPCK(hipGraphExecKernelNodeSetParams(ex, cn.k[0], &kp));
-    if (kcopy) {
+    if (out_by_kernel(p.t)) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, sl.host_out, sl.out_bytes};
       hipKernelNodeParams kd = copy_params(sl.d2h_argv, d2h_copy_blocks(p.L.out_cap));
       HIPCK(hipGraphExecKernelNodeSetParams(ex, cn.d2h, &kd));

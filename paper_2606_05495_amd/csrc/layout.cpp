@@ -44,7 +44,8 @@ int pipeline_validate(const set_job_template& t, std::string* why) {
       return bad("unknown pipeline");
   }
   if (t.flags & ~(uint32_t)(SET_TF_DEBUG | SET_TF_SCAN_LOW32 | SET_TF_CAPTURE)) return bad("unknown template flags");
-  if (t.copy_mode != SET_COPY_KERNELS && t.copy_mode != SET_COPY_NODES) return bad("unknown copy mode");
+  if (t.copy_mode != SET_COPY_KERNELS && t.copy_mode != SET_COPY_NODES && t.copy_mode != SET_COPY_ASYNC_IN)
+    return bad("unknown copy mode");
   return SET_OK;
 }
 
@@ -210,7 +211,7 @@ int pipeline_validate_job(const set_job_template& t, const set_job_args& a, std:
   const uint64_t ib = pipeline_in_bytes(t, n), ob = pipeline_out_bytes(t, n);
   if (ib > 0 && (a.host_in == nullptr || a.in_bytes != ib)) return bad("host_in missing or in_bytes mismatch");
   if (a.host_out == nullptr || a.out_bytes < ob) return bad("host_out missing or out_bytes too small");
-  if (t.copy_mode == SET_COPY_KERNELS && ((((uintptr_t)a.host_in) | ((uintptr_t)a.host_out)) & 15u))
+  if (t.copy_mode != SET_COPY_NODES && ((((uintptr_t)a.host_in) | ((uintptr_t)a.host_out)) & 15u))
     return bad("copy kernels need 16-byte aligned host buffers");
   return SET_OK;
 }

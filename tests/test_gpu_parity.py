@@ -600,3 +600,44 @@ def test_host_flag_completion_all_pipelines(torch_gpu, vec_pools, capture):
     res = _run_scan("set", inputs, max_n=1 << 20, extra_flags=extra, callback="host_flag")
     for v, r in zip(inputs, res):
         assert np.array_equal(r, oracle.scan(v))
+
+
+# ------------------------------------------------------------------ input copied ahead of the graph
+@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "queue", "set"])
+def test_async_input_copy_all_modes(torch_gpu, vec_pools, mode):
+    """SET_COPY_ASYNC_IN: the input goes by hipMemcpyAsync before the job's graph, the output by copy
+    kernel inside it; results as with the other copy mechanisms."""
+    _say("async input", mode)
+    imgs = [synth.box_image(0, j, 37, 201) for j in range(6)]
+    outs, _ = _run_images(mode, "box_hist", imgs, np.uint8, copy="async_in")
+    for img, o in zip(imgs, outs):
+        assert np.array_equal(o[64:64 + 1024].view(np.uint32), oracle.box_hist(img)[2])
+    big = [synth.normal_image(0, k) for k in range(2)]
+    outs, _ = _run_images(mode, "gauss_sobel", big, np.float32, workers=4, slots=4, flags=0, copy="async_in")
+    for img, o in zip(big, outs):
+        ref = oracle.gauss_sobel(img, want_images=False)
+        assert abs(int(o[64:68].view(np.uint32)[0]) - ref["count"]) <= ref["band"]
+        assert abs(float(o[68:72].view(np.float32)[0]) - ref["sum"]) <= 1e-5 * abs(ref["sum"])
+    rng = np.random.default_rng(12)
+    ins = [rng.integers(-(1 << 20), (1 << 20) + 1, n).astype(np.int32) for n in (1, 5, 4097, 1 << 21)]
+    for v, r in zip(ins, _run_scan(mode, ins, max_n=1 << 21, copy="async_in")):
+        assert np.array_equal(r, oracle.scan(v))
+    if mode == "set":
+        for v, r in zip(ins, _run_scan(mode, ins, max_n=1 << 21, copy="async_in", extra_flags=A.SET_TF_CAPTURE,
+                                       callback="host_flag")):
+            assert np.array_equal(r, oracle.scan(v))
+        x, y, xd, yd = vec_pools
+        js = synth.vec_jobs(3, 64, pool_len=len(x))
+        jobs = np.zeros(64, dtype=A.VEC_JOB_DTYPE)
+        for f in ("n", "a", "x_off", "y_off"):
+            jobs[f] = js[f]
+        ctx = Context(mode="set", workers=4, slots=4)
+        tid = ctx.define("saxpy_batch", max_n=1 << 22, x_pool=xd, y_pool=yd, batch_max=16, tiles_max=512,
+                         copy="async_in")
+        res, nb = ctx.run_vector_jobs(tid, jobs)
+        ctx.close()
+        assert nb >= 4
+        for i in range(64):
+            n, xo, yo = int(jobs["n"][i]), int(jobs["x_off"][i]), int(jobs["y_off"][i])
+            S, E = oracle.saxpy_tanh_sum(x[xo:xo + n], y[yo:yo + n], jobs["a"][i])
+            assert abs(res[i] - S) <= oracle.vec_tolerance(S, E)
