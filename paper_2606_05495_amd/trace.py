@@ -112,6 +112,56 @@ def stream_gaps(kernels: Sequence[Interval], streams: Sequence, names: Sequence[
             "mean_job_boundary_gap": mean(inter) if names else None}
 
 
+def eq_terms(kernels: Sequence[Interval], streams: Sequence, names: Sequence[str],
+             is_copy=lambda n: "copy" in n.lower(), is_tail=lambda n: "done_flag" in n) -> dict:
+    """Per-job terms of the overhead model (Section 3.1, Eq. 1-2) from one
+    stream's kernel sequence [input copy, stages..., output copy (, completion
+    word)]: t_in, t_k (sum of stage durations), t_out, and the gaps t_in-k
+    (input copy end to first stage), Delta t_k (between stages) and t_k-out
+    (last stage to output copy).  Segments without that shape, or whose stage
+    count differs from the most common one (chains interleaved on one
+    stream), are skipped; `jobs` counts the ones used.  Means in the input's
+    time unit."""
+    by = {}
+    for iv, s, n in zip(kernels, streams, names):
+        by.setdefault(s, []).append((iv[0], iv[1], n))
+    cands = []
+    for ks in by.values():
+        ks.sort()
+        seg = []
+        for a, b, n in ks + [(None, None, "")]:
+            starts_job = n == "" or (is_copy(n) and (not seg or is_copy(seg[-1][2]) or is_tail(seg[-1][2])))
+            if starts_job and seg:
+                body = [x for x in seg if not is_tail(x[2])]
+                if len(body) >= 3 and is_copy(body[0][2]) and is_copy(body[-1][2]) and \
+                        not any(is_copy(x[2]) for x in body[1:-1]):
+                    cands.append(body)
+                seg = []
+            if n:
+                seg.append((a, b, n))
+    acc = {"t_in": 0.0, "t_k": 0.0, "t_out": 0.0, "t_in_k": 0.0, "delta_t_k": 0.0, "t_k_out": 0.0}
+    jobs = 0
+    if cands:
+        counts = {}
+        for body in cands:
+            counts[len(body)] = counts.get(len(body), 0) + 1
+        m = max(counts, key=lambda k: (counts[k], -k))
+        for body in cands:
+            if len(body) != m:
+                continue
+            st = body[1:-1]
+            acc["t_in"] += body[0][1] - body[0][0]
+            acc["t_out"] += body[-1][1] - body[-1][0]
+            acc["t_k"] += sum(b1 - a1 for a1, b1, _ in st)
+            acc["t_in_k"] += max(0.0, st[0][0] - body[0][1])
+            acc["t_k_out"] += max(0.0, body[-1][0] - st[-1][1])
+            acc["delta_t_k"] += sum(max(0.0, st[i + 1][0] - st[i][1]) for i in range(len(st) - 1))
+            jobs += 1
+    out = {k: (v / jobs if jobs else None) for k, v in acc.items()}
+    out["jobs"] = jobs
+    return out
+
+
 def inter_batch_gaps(h2d: Sequence[Interval], d2h: Sequence[Interval], batch: int) -> List[float]:
     """Eq. 3 for consecutive batches of `batch` jobs (copies in time order)."""
     hs = sorted(h2d)
@@ -164,6 +214,8 @@ def analyze_dir(dirpath: str, batch: int = 0) -> dict:
         dirpath, kernel_filter=lambda n: "setrt" in n or "copyBuffer" in n)
     m = timeline_metrics(kernels, h2d, d2h)
     m.update(stream_gaps(kernels, streams, names))
+    m["eq_terms"] = {k: (v / 1e3 if (v is not None and k != "jobs") else v)
+                     for k, v in eq_terms(kernels, streams, names).items()}
     us_keys = ("span", "busy", "t_schedule", "mean_kernel_gap", "mean_positive_kernel_gap", "mean_stream_gap",
                "mean_intra_job_gap", "mean_job_boundary_gap")
     m = {k: (v / 1e3 if k in us_keys and v is not None else v) for k, v in m.items()}  # ns -> us

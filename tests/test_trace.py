@@ -65,3 +65,22 @@ def test_stream_gaps_with_completion_word_kernel():
     g = trace.stream_gaps(ks, ["A"] * 6, nm)
     assert g["mean_job_boundary_gap"] == pytest.approx(9.0)
     assert g["mean_intra_job_gap"] == pytest.approx((1 + 2 + 0 + 0) / 4)
+
+
+def test_eq_terms_hand_timeline():
+    # stream A: job 1 = copy(0,10) g(12,20) s(21,25) copy(27,30) flag(30,31); job 2 = copy(40,50) g(50,55) s(55,56) copy(60,62)
+    # stream B: two chains interleaved on one stream (copy, copy, g, g, s, s, copy, copy) form a segment
+    # with 4 stages, not the usual 2, and are skipped
+    ks = [(0, 10), (12, 20), (21, 25), (27, 30), (30, 31), (40, 50), (50, 55), (55, 56), (60, 62),
+          (0, 1), (1, 2), (2, 3), (3, 4), (4, 5), (5, 6), (6, 7), (7, 8)]
+    st = ["A"] * 9 + ["B"] * 8
+    nm = ["copy", "g", "s", "copy", "k_done_flag", "copy", "g", "s", "copy",
+          "copy", "copy", "g", "g", "s", "s", "copy", "copy"]
+    t = trace.eq_terms(ks, st, nm)
+    assert t["jobs"] == 2
+    assert t["t_in"] == pytest.approx((10 + 10) / 2)
+    assert t["t_k"] == pytest.approx((8 + 4 + 5 + 1) / 2)
+    assert t["t_out"] == pytest.approx((3 + 2) / 2)
+    assert t["t_in_k"] == pytest.approx((2 + 0) / 2)
+    assert t["delta_t_k"] == pytest.approx((1 + 0) / 2)
+    assert t["t_k_out"] == pytest.approx((2 + 4) / 2)
