@@ -406,8 +406,8 @@ def main():
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--inflight", type=int, default=0)
     ap.add_argument("--spin-us", type=int, default=0)
-    ap.add_argument("--dispatchers", type=int, default=1, help="SET dispatcher threads")
-    ap.add_argument("--callback", default="event_poll", choices=["event_chain", "same_stream", "event_poll", "host_flag"])
+    ap.add_argument("--dispatchers", type=int, default=4, help="SET dispatcher threads")
+    ap.add_argument("--callback", default="host_flag", choices=["event_chain", "same_stream", "event_poll", "host_flag"])
     ap.add_argument("--copy", default="kernels", choices=["nodes", "kernels", "async_in"],
                     help="job copies as graph memcpy nodes or as small-grid copy kernels")
     ap.add_argument("--baseline-steps", type=int, default=1)

@@ -272,12 +272,12 @@ __global__ __launch_bounds__(kBlock) void k_sobel_thresh_f32(SobelArgs a) {
 // ------------------------------------------------------------------ register-window image kernels
 // Path for float images whose width is a multiple of 4.  A lane owns 4
 // adjacent columns (one 16-byte load or store per row), a wave 256 columns,
-// and slides down kWinRows output rows with the window of input rows in
+// and slides down R output rows with the window of input rows in
 // registers: every input row of the wave is loaded before the first result
 // is formed, so each wave has all its loads in flight at once.  Neighbouring
-// columns come from the adjacent lanes by shuffles; lanes 0 and 63 take the
-// columns beyond the wave from two extra (clamped) loads.  A block is 4 waves
-// stacked vertically.
+// columns come from the adjacent lanes by whole-wave lane shifts; lanes 0 and
+// 63 take the columns beyond the wave from extra (clamped) loads.  A block is
+// 4 waves stacked vertically.
 //
 // Blocks are dealt to the 8 XCDs round-robin in launch order.  xcd_tile
 // renumbers them so each XCD owns a contiguous run of tiles in row-major
@@ -292,6 +292,17 @@ __device__ inline void xcd_tile(unsigned& bx, unsigned& by) {
   bx = t - by * gx;
 }
 
+// Whole-wave shifts by one lane (DPP wave_shr:1 / wave_shl:1, a VALU move
+// instead of an LDS permute): up1 gives lane i the value of lane i-1, down1
+// the value of lane i+1.  Lanes 0 and 63 get 0 and are overwritten by the
+// caller.
+__device__ inline float up1(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ inline float down1(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
 __device__ inline float4 load_row4(const float* row, int x, bool in4, int wm) {
   if (in4) return *reinterpret_cast<const float4*>(row + x);
   const float e = row[wm];  // lanes past the right edge hold the replicated border
@@ -299,7 +310,7 @@ __device__ inline float4 load_row4(const float* row, int x, bool in4, int wm) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_gauss5_win_f32(GaussArgs a) {
-  constexpr int R = kWinRows;
+  constexpr int R = kGaussWinRows;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   unsigned bx, by;
   xcd_tile(bx, by);
@@ -325,8 +336,8 @@ __global__ __launch_bounds__(kBlock) void k_gauss5_win_f32(GaussArgs a) {
   float hz[5][4];  // horizontal results of the last 5 input rows (ring)
 #pragma unroll
   for (int r = 0; r < R + 4; ++r) {
-    float l2 = __shfl_up(v[r].z, 1, 64), l1 = __shfl_up(v[r].w, 1, 64);
-    float r1 = __shfl_down(v[r].x, 1, 64), r2 = __shfl_down(v[r].y, 1, 64);
+    float l2 = up1(v[r].z), l1 = up1(v[r].w);
+    float r1 = down1(v[r].x), r2 = down1(v[r].y);
     if (lane == 0) {
       l2 = e0[r];
       l1 = e1[r];
@@ -367,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_gauss5_win_f32(GaussArgs a) {
 // gx = d[y-1] + 2*d[y] + d[y+1] and gy = s[y+1] - s[y-1] (the two 3x3
 // kernels factored).  Mask bytes of a lane go out as one 4-byte store.
 __global__ __launch_bounds__(kBlock) void k_sobel_thresh_win_f32(SobelArgs a) {
-  constexpr int R = kWinRows;
+  constexpr int R = kSobelWinRows;
   __shared__ float s4f[4];
   __shared__ uint32_t s4u[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

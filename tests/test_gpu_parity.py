@@ -173,7 +173,8 @@ def test_gauss_sobel_full_size(torch_gpu, mode):
     """1024x1024 N(0,1) images from the 61-image pool, 8 workers x 16 slots."""
     _say("gauss_sobel 1024^2", mode)
     imgs = [synth.normal_image(0, k) for k in range(6)]
-    outs, st = _run_images(mode, "gauss_sobel", imgs + imgs, np.float32, workers=8, slots=16, flags=0)
+    outs, st = _run_images(mode, "gauss_sobel", imgs + imgs, np.float32, workers=8, slots=16, flags=0,
+                           callback="host_flag", dispatchers=4)
     for k, img in enumerate(imgs + imgs):
         ref = oracle.gauss_sobel(img, want_images=False)
         o = outs[k]
@@ -264,7 +265,7 @@ def test_vector_workload_sample(torch_gpu, vec_pools):
     x, y = vec_pools[0], vec_pools[1]
     jobs = synth.vec_jobs(0, 120, pool_len=len(x))
     got, st = _run_vec("set", vec_pools, jobs["n"], jobs["x_off"], jobs["y_off"], jobs["a"], workers=8, slots=16,
-                       policy=A.SET_SUBMIT_SKEW0)
+                       policy=A.SET_SUBMIT_SKEW0, callback="host_flag", dispatchers=4)
     assert st.stolen > 0
     for i in range(len(got)):
         n = int(jobs["n"][i])
@@ -341,12 +342,15 @@ def test_scan_full_size_and_low32(torch_gpu):
 
 
 # ------------------------------------------------------------------ scheduling on the device
-@pytest.mark.parametrize("callback", ["event_chain", "same_stream", "event_poll", "host_flag"])
-def test_set_mode_callbacks_and_steals(torch_gpu, callback):
-    """Skewed submission on the GPU: steals retarget jobs to thieves' slots; results stay exact."""
-    _say("set callbacks", callback)
+@pytest.mark.parametrize("callback,nd", [("event_chain", 1), ("same_stream", 1), ("event_poll", 1), ("host_flag", 1),
+                                         ("event_poll", 4), ("host_flag", 3)])
+def test_set_mode_callbacks_and_steals(torch_gpu, callback, nd):
+    """Skewed submission on the GPU: steals retarget jobs to thieves' slots; results stay exact
+    (one dispatcher thread, or several each owning a share of the workers)."""
+    _say("set callbacks", callback, nd)
     imgs = [synth.box_image(0, j) for j in range(96)]
-    ctx = Context(mode="set", workers=4, slots=4, callback=callback, submit_policy=A.SET_SUBMIT_SKEW0)
+    ctx = Context(mode="set", workers=4, slots=4, callback=callback, submit_policy=A.SET_SUBMIT_SKEW0,
+                  dispatchers=nd)
     tid = ctx.define("box_hist", width=256, height=256)
     ib, ob = ctx.in_bytes(tid), ctx.out_bytes(tid)
     tin, nin = pinned(ib * 96)
