@@ -12,6 +12,23 @@ import json
 import numpy as np
 
 
+def _copy_us(torch, nbytes, reps):
+    """A plain device copy moving the same bytes (half read, half written)."""
+    half = max(16, nbytes // 2)
+    a = torch.empty(half, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(10):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    return round(e0.elapsed_time(e1) * 1e3 / reps, 3)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--pipeline", default="gauss_sobel", choices=["gauss_sobel", "box_hist", "scan"])
@@ -43,7 +60,9 @@ def main():
     ctx.drain()
     out = {}
     for i, (name, nbytes) in enumerate(ctx.stage_info(tid)):
-        out[name] = {"avg_us": round(ctx.time_stage(tid, i, 0, args.reps), 3), "bytes": int(nbytes)}
+        us = ctx.time_stage(tid, i, 0, args.reps)
+        out[name] = {"avg_us": round(us, 3), "bytes": int(nbytes), "GBps": round(nbytes / us / 1e3, 1),
+                     "copy_same_bytes_us": _copy_us(torch, int(nbytes), args.reps)}
     # calibration: a plain device-to-device copy of known size
     n = args.copy_mib << 20
     a = torch.empty(n, dtype=torch.uint8, device="cuda")
