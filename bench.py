@@ -408,15 +408,16 @@ def main():
     ap.add_argument("--spin-us", type=int, default=0)
     ap.add_argument("--dispatchers", type=int, default=4, help="SET dispatcher threads")
     ap.add_argument("--callback", default="host_flag", choices=["event_chain", "same_stream", "event_poll", "host_flag"])
-    ap.add_argument("--copy", default="kernels", choices=["nodes", "kernels", "async_in"],
-                    help="job copies as graph memcpy nodes or as small-grid copy kernels")
+    ap.add_argument("--copy", default=None, choices=["nodes", "kernels", "async_in"],
+                    help="job copies: graph memcpy nodes, small-grid copy kernels, or the input by hipMemcpyAsync "
+                         "ahead of the graph (default: async_in for the scan workload, kernels otherwise)")
     ap.add_argument("--baseline-steps", type=int, default=1)
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-passes", type=int, default=5)
     ap.add_argument("--stage-reps", type=int, default=200)
     ap.add_argument("--workload", choices=["images", "vectors", "serve", "scan"], default="images")
-    ap.add_argument("--scan-jobs", type=int, default=4000)
+    ap.add_argument("--scan-jobs", type=int, default=20000)
     ap.add_argument("--scan-ring", type=int, default=48)
     ap.add_argument("--rates", default="2000,10000,40000")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
@@ -430,6 +431,8 @@ def main():
     ap.add_argument("--only", choices=["set", "batch", "sync", "queue"], default=None,
                     help="run one mode only (for traced runs); prints its line")
     args = ap.parse_args()
+    if args.copy is None:
+        args.copy = "async_in" if args.workload == "scan" else "kernels"
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the job path shards by running one independent scheduler per GPU, "
