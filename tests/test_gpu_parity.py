@@ -187,6 +187,18 @@ def test_gauss_sobel_full_size(torch_gpu, mode):
         assert np.array_equal(outs[k][64:72], outs[k + 6][64:72])
 
 
+def test_gauss_sobel_largest_serving_size(torch_gpu):
+    """2048x2048, the largest image of the serving mix (16 MiB input), through SET."""
+    _say("gauss_sobel 2048^2")
+    imgs = [synth.normal_image(3, k, 2048, 2048) for k in range(2)]
+    outs, _ = _run_images("set", "gauss_sobel", imgs + imgs[:1], np.float32, workers=2, slots=2, flags=0)
+    for k, img in enumerate(imgs + imgs[:1]):
+        ref = oracle.gauss_sobel(img, want_images=False)
+        assert abs(int(outs[k][64:68].view(np.uint32)[0]) - ref["count"]) <= ref["band"]
+        assert abs(float(outs[k][68:72].view(np.float32)[0]) - ref["sum"]) <= 1e-5 * abs(ref["sum"])
+    assert np.array_equal(outs[0][64:72], outs[2][64:72])
+
+
 # ------------------------------------------------------------------ vector jobs
 @pytest.fixture(scope="module")
 def vec_pools(torch_gpu):
