@@ -670,8 +670,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_spine_i64(ScanSpineArgs a) {
   if (threadIdx.x == 0) publish_out(a.sc, true);
 }
 
+// Results are computed in the blocked order the loads use (8 consecutive
+// elements per thread), then pass through LDS so that each store instruction
+// of a wave writes one contiguous 1 KiB run: a thread's own 64-byte run would
+// make every store instruction touch 32 lines a quarter each.
 __global__ __launch_bounds__(kBlock) void k_scan_down_i32_i64(ScanDownArgs a) {
+  constexpr int kPitch = kScanItems + 2;  // LDS row of a thread (padding spreads the banks, keeps 16-byte alignment)
   __shared__ int64_t s_wave[4];
+  __shared__ __align__(16) int64_t s_out[kBlock * kPitch];
   const uint64_t n = a.hdr->n;
   const unsigned t = blockIdx.x;
   if ((uint64_t)t * kScanTile >= n) return;
@@ -681,28 +687,35 @@ __global__ __launch_bounds__(kBlock) void k_scan_down_i32_i64(ScanDownArgs a) {
   for (int k = 1; k < kScanItems; ++k) v[k] += v[k - 1];
   int64_t total;
   const int64_t off0 = a.tile_excl[t] + block_exclusive_i64(v[kScanItems - 1], s_wave, &total);
-  const uint64_t base = (uint64_t)t * kScanTile + (uint64_t)threadIdx.x * kScanItems;
-  if (!a.low32) {
-    int64_t* o = reinterpret_cast<int64_t*>(a.out);
-    if (base + kScanItems <= n) {
-      longlong2* o2 = reinterpret_cast<longlong2*>(o + base);
 #pragma unroll
-      for (int k = 0; k < kScanItems / 2; ++k) o2[k] = make_longlong2(off0 + v[2 * k], off0 + v[2 * k + 1]);
+  for (int k = 0; k < kScanItems; ++k) s_out[threadIdx.x * kPitch + k] = off0 + v[k];
+  __syncthreads();
+  const uint64_t tile0 = (uint64_t)t * kScanTile;
+  auto at = [&](int e) { return s_out[(e / kScanItems) * kPitch + (e % kScanItems)]; };
+  if (!a.low32) {
+    int64_t* o = reinterpret_cast<int64_t*>(a.out) + tile0;
+    if (tile0 + kScanTile <= n) {
+#pragma unroll
+      for (int k = 0; k < kScanItems / 2; ++k) {
+        const int e = 2 * (k * kBlock + (int)threadIdx.x);  // element pairs in striped order
+        reinterpret_cast<longlong2*>(o)[e / 2] = make_longlong2(at(e), at(e + 1));
+      }
     } else {
-      for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) o[base + k] = off0 + v[k];
+      for (int e = threadIdx.x; e < kScanTile; e += kBlock)
+        if (tile0 + e < n) o[e] = at(e);
     }
   } else {
-    uint32_t* o = reinterpret_cast<uint32_t*>(a.out);
-    if (base + kScanItems <= n) {
-      uint4* o4 = reinterpret_cast<uint4*>(o + base);
-      o4[0] = make_uint4((uint32_t)(off0 + v[0]), (uint32_t)(off0 + v[1]), (uint32_t)(off0 + v[2]),
-                         (uint32_t)(off0 + v[3]));
-      o4[1] = make_uint4((uint32_t)(off0 + v[4]), (uint32_t)(off0 + v[5]), (uint32_t)(off0 + v[6]),
-                         (uint32_t)(off0 + v[7]));
+    uint32_t* o = reinterpret_cast<uint32_t*>(a.out) + tile0;
+    if (tile0 + kScanTile <= n) {
+#pragma unroll
+      for (int k = 0; k < kScanItems / 4; ++k) {
+        const int e = 4 * (k * kBlock + (int)threadIdx.x);  // element quads in striped order
+        reinterpret_cast<uint4*>(o)[e / 4] =
+            make_uint4((uint32_t)at(e), (uint32_t)at(e + 1), (uint32_t)at(e + 2), (uint32_t)at(e + 3));
+      }
     } else {
-      for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) o[base + k] = (uint32_t)(off0 + v[k]);
+      for (int e = threadIdx.x; e < kScanTile; e += kBlock)
+        if (tile0 + e < n) o[e] = (uint32_t)at(e);
     }
   }
 }
