@@ -74,6 +74,29 @@ __device__ inline uint32_t block_sum_u32(uint32_t v, uint32_t* s4) {
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Fill an LDS tile of N elements (row-major, LW per row, stored with pitch
+// P) from global memory: every thread issues all of its loads before its
+// first LDS write, so one memory latency covers the whole tile.  get(r, c)
+// returns the element for tile row r, column c.
+template <typename T, int LW, int LH, int P, class Get>
+__device__ inline void stage_tile(T (*tile)[P], Get get) {
+  constexpr int N = LW * LH;
+  constexpr int PER = (N + kBlock - 1) / kBlock;
+  T vals[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    const int r = i / LW, c = i - r * LW;
+    vals[k] = (i < N) ? get(r, c) : T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    const int r = i / LW, c = i - r * LW;
+    if (i < N) tile[r][c] = vals[k];
+  }
+}
+
 // ------------------------------------------------------------------ copy kernel (H2D pull / D2H push)
 // Grid-stride over 16-byte words with four independent loads in flight per
 // thread, then a byte tail.  Source and destination are 16-byte aligned (slot
@@ -111,11 +134,10 @@ __global__ __launch_bounds__(kBlock) void k_box3_u8_u16(BoxArgs a) {
   __shared__ uint8_t tile[LH][LW + 2];
   const int x0 = blockIdx.x * kBoxTW, y0 = blockIdx.y * kBoxTH;
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
-  for (int i = threadIdx.x; i < LH * LW; i += kBlock) {
-    const int r = i / LW, c = i - r * LW;
+  stage_tile<uint8_t, LW, LH, LW + 2>(tile, [&](int r, int c) {
     const int gy = y0 + r - 1, gx = x0 + c - 1;
-    tile[r][c] = (gy >= 0 && gy < a.h && gx >= 0 && gx < a.w) ? a.in[(size_t)gy * a.w + gx] : (uint8_t)0;
-  }
+    return (gy >= 0 && gy < a.h && gx >= 0 && gx < a.w) ? a.in[(size_t)gy * a.w + gx] : (uint8_t)0;
+  });
   __syncthreads();
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int y = y0 + ty;
@@ -194,11 +216,9 @@ __global__ __launch_bounds__(kBlock) void k_gauss5_f32(GaussArgs a) {
   const int x0 = blockIdx.x * kGaussTW, y0 = blockIdx.y * kGaussTH;
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
   const int wm = a.w - 1, hm = a.h - 1;
-  for (int i = threadIdx.x; i < IH * IW; i += kBlock) {
-    const int r = i / IW, c = i - r * IW;
-    const int gy = clampi(y0 + r - 2, 0, hm), gx = clampi(x0 + c - 2, 0, wm);
-    tin[r][c] = a.in[(size_t)gy * a.w + gx];
-  }
+  stage_tile<float, IW, IH, IW + 1>(tin, [&](int r, int c) {
+    return a.in[(size_t)clampi(y0 + r - 2, 0, hm) * a.w + clampi(x0 + c - 2, 0, wm)];
+  });
   __syncthreads();
   const float g0 = a.g0, g1 = a.g1, g2 = a.g2;
   for (int i = threadIdx.x; i < IH * kGaussTW; i += kBlock) {
@@ -236,11 +256,9 @@ __global__ __launch_bounds__(kBlock) void k_sobel_thresh_f32(SobelArgs a) {
   __shared__ uint32_t s4u[4];
   const int x0 = blockIdx.x * kSobelTW, y0 = blockIdx.y * kSobelTH;
   const int wm = a.w - 1, hm = a.h - 1;
-  for (int i = threadIdx.x; i < IH * IW; i += kBlock) {
-    const int r = i / IW, c = i - r * IW;
-    const int gy = clampi(y0 + r - 1, 0, hm), gx = clampi(x0 + c - 1, 0, wm);
-    t[r][c] = a.blur[(size_t)gy * a.w + gx];
-  }
+  stage_tile<float, IW, IH, IW + 1>(t, [&](int r, int c) {
+    return a.blur[(size_t)clampi(y0 + r - 1, 0, hm) * a.w + clampi(x0 + c - 1, 0, wm)];
+  });
   __syncthreads();
   float sum = 0.f;
   uint32_t cnt = 0;
