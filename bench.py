@@ -414,7 +414,7 @@ def main():
     ap.add_argument("--baseline-steps", type=int, default=1)
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-passes", type=int, default=5)
+    ap.add_argument("--cpu-passes", type=int, default=15)
     ap.add_argument("--stage-reps", type=int, default=200)
     ap.add_argument("--workload", choices=["images", "vectors", "serve", "scan"], default="images")
     ap.add_argument("--scan-jobs", type=int, default=20000)
