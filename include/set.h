@@ -107,7 +107,8 @@ enum set_callback_mode {
      * array (system-scope release store, after the device-to-host copy node
      * has finished).  The completion thread watches each worker's oldest
      * word with plain host loads and calls no HIP function, so it never
-     * contends with the dispatcher inside the HIP runtime.  SET mode only. */
+     * contends with the dispatcher inside the HIP runtime.  SET mode only;
+     * the configuration the benchmark runs. */
     SET_CB_HOST_FLAG = 3
 };
 
@@ -296,7 +297,8 @@ typedef struct set_ctx set_ctx;
 
 /* Create a context: b workers with their streams (borrowed or created),
  * per-worker queues and callback streams, the free pool, and (SET mode) the
- * submitter and dispatcher threads ("Initialization", Section 4.2).
+ * submitter thread, the dispatcher thread(s) and the completion thread
+ * ("Initialization", Section 4.2).
  * cfg is copied.  *out receives the handle.  Errors: SET_EINVAL (bad sizes,
  * abi_version mismatch), SET_ENOMEM, SET_EDEVICE (no device / HIP failure). */
 int set_ctx_create(const set_config *cfg, set_ctx **out);
