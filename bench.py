@@ -160,6 +160,29 @@ def copy_reference(torch, nbytes, reps):
     return {"bytes": 2 * half, "avg_us": round(us, 3), "GBps": round(2 * half / us / 1e3, 1)}
 
 
+def _vec_persistent(args, torch, A, autotune, Context, js, vj, xd, yd, J, total_bytes, check):
+    out = {}
+    # ---- bucketed persistent batches, dispatched by SET
+    ctx = Context(mode="set", workers=args.workers, slots=4, callback=args.callback, dispatchers=args.dispatchers)
+    tid = ctx.define("saxpy_batch", max_n=int(js["n"].max()), x_pool=xd, y_pool=yd, batch_max=args.batch_max,
+                     tiles_max=args.tiles_max, copy=args.copy)
+    tuning = None if args.no_tune else autotune.load()
+    if tuning is None and not args.no_tune:
+        log("autotuning buckets")
+        tuning = autotune.tune(ctx, tid, vj, calib=512, log=log)
+    res = np.zeros(J, np.float32)
+    ctx.run_vector_jobs(tid, vj, res, tuning)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, nb = ctx.run_vector_jobs(tid, vj, res, tuning)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["persistent"] = {"jobs_per_s": round(J / dt, 1), "batches": int(nb), "verified": check(res),
+                         "effective_GBps": round(total_bytes / dt / 1e9, 1), "tuned": tuning is not None}
+    ctx.close()
+    return out
+
+
 def bench_vectors(args, torch):
     """100,000 uneven vector jobs (n log-uniform in [4096, 4194304)) over two
     2^27-element device pools: bucketed persistent batches dispatched by SET vs
@@ -189,26 +212,13 @@ def bench_vectors(args, torch):
         return all(abs(float(res[i]) - S) <= oracle.vec_tolerance(S, E) for i, (S, E) in refs.items())
 
     out = {}
-    # ---- bucketed persistent batches, dispatched by SET
-    ctx = Context(mode="set", workers=args.workers, slots=4, callback=args.callback, dispatchers=args.dispatchers)
-    tid = ctx.define("saxpy_batch", max_n=int(js["n"].max()), x_pool=xd, y_pool=yd, batch_max=args.batch_max,
-                     tiles_max=args.tiles_max, copy=args.copy)
-    tuning = None if args.no_tune else autotune.load()
-    if tuning is None and not args.no_tune:
-        log("autotuning buckets")
-        tuning = autotune.tune(ctx, tid, vj, calib=512, log=log)
-    res = np.zeros(J, np.float32)
-    ctx.run_vector_jobs(tid, vj, res, tuning)  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, nb = ctx.run_vector_jobs(tid, vj, res, tuning)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out["persistent"] = {"jobs_per_s": round(J / dt, 1), "batches": int(nb), "verified": check(res),
-                         "effective_GBps": round(total_bytes / dt / 1e9, 1)}
-    ctx.close()
-    # ---- per-job graphs / baselines on the per-job template
-    for mode in ("set", "batch", "sync", "queue"):
+    modes = ("set", "batch", "sync", "queue")
+    if args.only:
+        # traced runs: one per-job mode only
+        modes = (args.only,)
+    else:
+        out.update(_vec_persistent(args, torch, A, autotune, Context, js, vj, xd, yd, J, total_bytes, check))
+    for mode in modes:
         c = Context(mode=mode, workers=args.workers, slots=16 if mode == "set" else 1,
                     batch_size=args.batch if mode == "batch" else 0, callback=args.callback, dispatchers=args.dispatchers)
         t2 = c.define("saxpy_tanh_sum", max_n=int(js["n"].max()), x_pool=xd, y_pool=yd, copy=args.copy)
@@ -231,6 +241,10 @@ def bench_vectors(args, torch):
         r2 = nout.reshape(J, 128)[:, 64:68].copy().view(np.float32).ravel()
         out["per_job_" + mode] = {"jobs_per_s": round(J / dt2, 1), "verified": check(r2)}
         c.close()
+    if args.only:
+        print(json.dumps({"mode": args.only, "workload": "vectors", "jobs_per_s": out["per_job_" + args.only]["jobs_per_s"],
+                          "verified": out["per_job_" + args.only]["verified"]}), flush=True)
+        return
     p = out["persistent"]["jobs_per_s"]
     line = {"metric": METRIC, "workload": "vector jobs: %d uneven (n log-uniform [4096, 4194304)) SAXPY->tanh->sum"
             % J, "value": p, "unit": "jobs/s", "n_gpus": 1, "dtype": "f32", "data": "synthetic",
@@ -241,7 +255,7 @@ def bench_vectors(args, torch):
             "speedup_vs_queue": round(p / out["per_job_queue"]["jobs_per_s"], 2),
             "modes": out, "config": {"workers": args.workers, "batch_max": args.batch_max,
                                      "tiles_max": args.tiles_max, "copy": args.copy, "callback": args.callback, "dispatchers": args.dispatchers,
-                                     "tuned": tuning is not None}}
+                                     "tuned": out["persistent"]["tuned"]}}
     print(json.dumps(line), flush=True)
 
 
