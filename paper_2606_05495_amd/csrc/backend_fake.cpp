@@ -35,6 +35,8 @@ class FakeBackend : public Backend {
     cfg_ = cfg;
     b_ = cfg.num_workers;
     d_ = cfg.slots_per_worker;
+    templates_.reserve(kMaxTemplates);  // entries never move while jobs read them
+    inuse_.reserve(kMaxTemplates);
     workers_.resize(b_);
     for (int w = 0; w < b_; ++w) {
       workers_[w].reset(new Worker());

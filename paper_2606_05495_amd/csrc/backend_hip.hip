@@ -131,6 +131,7 @@ class HipBackend : public Backend {
       return SET_EDEVICE;
     }
     dev_ = cfg.device;
+    pipes_.reserve(kMaxTemplates);  // entries never move while jobs of other templates run
     HIPCK(hipSetDevice(dev_));
     t_dev = dev_;
     streams_.resize(b_);

@@ -107,11 +107,17 @@ class Context {
   std::atomic<int> sticky{SET_OK};
 
   // ---- templates
+  // Capacity kMaxTemplates is reserved up front, so a template defined while
+  // jobs of others run never moves the entries those jobs read; ntmpl
+  // publishes a new entry once it is complete.
   std::vector<set_job_template> templates;
   std::vector<TemplateSizes> tsizes;
   // free-slot bitmask per (template, worker): bit s set = slot FREE
   std::vector<std::unique_ptr<std::atomic<uint64_t>[]>> free_mask;
-  std::vector<std::vector<uint64_t>> slot_seq;  // [tmpl][w*d+s], touched by the binder only
+  // [tmpl][w*d+s]: touched only by the thread that holds the slot (binder, or a thief retargeting to its own slot)
+  std::vector<std::vector<uint64_t>> slot_seq;
+  std::atomic<int> ntmpl{0};
+  bool valid_template(int id) const { return id >= 0 && id < ntmpl.load(std::memory_order_acquire); }
 
   // ---- job records
   std::mutex job_mu;
@@ -297,6 +303,10 @@ class Context {
     kperm = c.inflight_per_worker > 0 ? c.inflight_per_worker : std::min(2, d);
     qcap = c.queue_capacity > 0 ? c.queue_capacity : std::max(1, d - kperm);
     staging_cap = c.staging_capacity > 0 ? c.staging_capacity : 4096;
+    templates.reserve(kMaxTemplates);
+    tsizes.reserve(kMaxTemplates);
+    free_mask.reserve(kMaxTemplates);
+    slot_seq.reserve(kMaxTemplates);
     for (int i = 0; i < kMaxWorkers; ++i) st_launch[i] = 0;
     // A thief steals only into a FREE slot of its own; with an empty queue and a
     // permit in hand it has at most kperm - 1 slots in flight, so kperm <= d
@@ -350,7 +360,7 @@ class Context {
   }
 
   int define_template(const set_job_template& t, int* id) {
-    if (templates.size() >= (size_t)kMaxTemplates) return fail(SET_EINVAL, "too many templates");
+    if (ntmpl.load() >= kMaxTemplates) return fail(SET_EINVAL, "too many templates");
     std::string why;
     if (pipeline_validate(t, &why) != SET_OK) return fail(SET_EINVAL, why);
     TemplateSizes sz;
@@ -366,6 +376,7 @@ class Context {
     slot_seq.emplace_back((size_t)b * d, 0);
     tsizes.push_back(sz);
     templates.push_back(t);
+    ntmpl.store(tid + 1, std::memory_order_release);
     *id = tid;
     return SET_OK;
   }
@@ -781,7 +792,7 @@ class Context {
     int st = check_sticky();
     if (st != SET_OK) return st;
     if (stopping.load()) return SET_ECLOSED;
-    if (tmpl < 0 || tmpl >= (int)templates.size()) return fail(SET_EINVAL, "unknown template id");
+    if (!valid_template(tmpl)) return fail(SET_EINVAL, "unknown template id");
     if (!a) return fail(SET_EINVAL, "null job args");
     std::string why;
     if (pipeline_validate_job(templates[tmpl], *a, &why) != SET_OK) return fail(SET_EINVAL, why);
@@ -897,7 +908,7 @@ class Context {
                       uint64_t* nbatches_out) {
     int st = check_sticky();
     if (st != SET_OK) return st;
-    if (tmpl < 0 || tmpl >= (int)templates.size()) return fail(SET_EINVAL, "unknown template id");
+    if (!valid_template(tmpl)) return fail(SET_EINVAL, "unknown template id");
     const set_job_template& t = templates[tmpl];
     if (t.pipeline != SET_PIPE_SAXPY_BATCH_F32) return fail(SET_EINVAL, "template is not a vector batch template");
     if (count && (!jobs || !results)) return fail(SET_EINVAL, "null jobs or results");
@@ -1092,7 +1103,7 @@ class Context {
     uint64_t nvec = 0;
     for (uint64_t i = 0; i < count; ++i) {
       const set_request& q = reqs[i];
-      if (q.template_id < 0 || q.template_id >= (int)templates.size()) return fail(SET_EINVAL, "unknown template id");
+      if (!valid_template(q.template_id)) return fail(SET_EINVAL, "unknown template id");
       if (i && q.t_arrival_ns < reqs[i - 1].t_arrival_ns) return fail(SET_EINVAL, "arrivals must be non-decreasing");
       const set_job_template& t = templates[q.template_id];
       std::string why;
@@ -1378,7 +1389,7 @@ int set_time_stage(set_ctx* c, int template_id, int stage, int worker, int reps,
   if (!c || !avg_us || reps < 1) return SET_EINVAL;
   int st = c->impl.check_sticky();
   if (st != SET_OK) return st;
-  if (template_id < 0 || template_id >= (int)c->impl.templates.size()) return SET_EINVAL;
+  if (!c->impl.valid_template(template_id)) return SET_EINVAL;
   if (stage < 0 || stage >= c->impl.tsizes[template_id].num_stages) return SET_EINVAL;
   if (worker < 0 || worker >= c->impl.b) return SET_EINVAL;
   std::string err;
@@ -1390,7 +1401,7 @@ int set_time_stage(set_ctx* c, int template_id, int stage, int worker, int reps,
 int set_stage_info(set_ctx* c, int template_id, int* num_stages, uint64_t* bytes_per_stage, int max_stages,
                    char* names, int names_len) {
   if (!c || !num_stages) return SET_EINVAL;
-  if (template_id < 0 || template_id >= (int)c->impl.templates.size()) return SET_EINVAL;
+  if (!c->impl.valid_template(template_id)) return SET_EINVAL;
   const setrt::TemplateSizes& sz = c->impl.tsizes[template_id];
   *num_stages = sz.num_stages;
   for (int i = 0; i < sz.num_stages && i < max_stages; ++i)

@@ -10,7 +10,7 @@
 #include "set.h"
 
 static int run(int mode, int b, int d, int policy, int stealing, int reorder, int producers, int per_producer,
-               int dispatchers = 1) {
+               int dispatchers = 1, int extra_templates = 0) {
   set_config cfg;
   std::memset(&cfg, 0, sizeof(cfg));
   cfg.abi_version = SET_ABI_VERSION;
@@ -57,7 +57,15 @@ static int run(int mode, int b, int d, int policy, int stealing, int reorder, in
       }
     });
   }
+  // templates defined while the producers' jobs are in flight
+  std::thread definer([&] {
+    for (int k = 0; k < extra_templates; ++k) {
+      int id = -1;
+      set_template_define(c, &t, &id);
+    }
+  });
   for (auto& x : th) x.join();
+  definer.join();
   if (set_drain(c, -1) != SET_OK) return 3;
   set_stats st;
   set_get_stats(c, &st);
@@ -85,6 +93,7 @@ int main() {
   rc |= run(SET_MODE_QUEUE, 4, 2, 0, 1, 0, 3, 200) << 6;
   rc |= run(SET_MODE_SET, 6, 8, SET_SUBMIT_SKEW0, 1, 1, 3, 300, 3) << 7;
   rc |= run(SET_MODE_SET, 4, 4, SET_SUBMIT_ROUND_ROBIN, 0, 1, 2, 200, 2) << 8;
+  rc |= run(SET_MODE_SET, 4, 4, SET_SUBMIT_SKEW0, 1, 1, 2, 300, 2, 5) << 9;
   std::printf("tsan stress rc=%d\n", rc);
   return rc;
 }

@@ -393,3 +393,24 @@ def test_queue_model_completes_and_spreads_work():
         assert np.array_equal(np.sort(h["job_id"]), np.arange(300))
         assert all(st.launches_per_worker[w] > 0 for w in range(4))
         assert np.all(h["slot"] == 0)
+
+
+def test_define_template_while_other_jobs_run():
+    """A template defined while jobs of another template are in flight (storage never moves under them)."""
+    import threading
+    with _fake(workers=4, slots=4, dispatchers=2) as ctx:
+        t0 = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        arr0, outs0 = _vec_jobs(ctx, t0, 600, 20)
+        th = threading.Thread(target=lambda: ctx.submit_many(t0, arr0))
+        th.start()
+        tids = [ctx.define("saxpy_tanh_sum", max_n=1 << 18, pool_ptrs=DUMMY_POOL) for _ in range(6)]
+        th.join()
+        arrs = [_vec_jobs(ctx, t, 50, 10) for t in tids]
+        for t, (arr, _) in zip(tids, arrs):
+            ctx.submit_many(t, arr)
+        ctx.drain()
+        st = ctx.stats()
+        assert st.completed == 600 + 6 * 50 and st.failed == 0
+        assert np.all(_headers(outs0)["magic"] == A.SET_OUT_MAGIC)
+        for _, outs in arrs:
+            assert np.all(_headers(outs)["canary_ok"] == 1)
