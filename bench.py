@@ -328,6 +328,65 @@ def bench_scan(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def bench_sweep(args, torch):
+    """Worker-count sweep (the batch size b of Section 5.2): per-job vector jobs
+    (the configs[2] length distribution, device-resident inputs, two kernels and
+    a 68-byte D2H each) through SET (b workers, 16 slots each, min(4, b)
+    dispatcher threads), batch-sync (one graph of b chains per batch) and the
+    queue model (b workers), at b = 1 .. 64.  Prints one JSON line."""
+    from paper_2606_05495_amd import synth
+    from paper_2606_05495_amd.runtime import Context, pinned
+    import oracle
+    L = synth.VEC_POOL_LEN
+    x = synth.vec_pool(0, "x", L)
+    y = synth.vec_pool(0, "y", L)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.from_numpy(y).cuda()
+    J = args.sweep_jobs
+    js = synth.vec_jobs(0, J, pool_len=L)
+    refs = {int(i): oracle.saxpy_tanh_sum(x[js["x_off"][i]:js["x_off"][i] + js["n"][i]],
+                                          y[js["y_off"][i]:js["y_off"][i] + js["n"][i]], js["a"][i])
+            for i in range(0, J, max(1, J // 20))}
+    tout, nout = pinned(128 * J)
+    rows = []
+    for b in [int(v) for v in args.sweep_b.split(",")]:
+        for mode in ("set", "batch", "queue"):
+            c = Context(mode=mode, workers=b, slots=16 if mode == "set" else 1,
+                        batch_size=b if mode == "batch" else 0, callback=args.callback,
+                        dispatchers=min(args.dispatchers, b))
+            tid = c.define("saxpy_tanh_sum", max_n=int(js["n"].max()), x_pool=xd, y_pool=yd, copy=args.copy)
+            arr = c.job_array(J)
+            arr["host_out"] = tout.data_ptr() + np.arange(J, dtype=np.uint64) * 128
+            arr["out_bytes"] = 68
+            for f in ("n", "a", "x_off", "y_off"):
+                arr[f] = js[f]
+            c.submit_many(tid, arr[:min(J, 1000)])
+            c.drain()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.submit_many(tid, arr)
+            c.drain()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = c.stats()
+            c.close()
+            res = nout.reshape(J, 128)[:, 64:68].copy().view(np.float32).ravel()
+            ok = all(abs(float(res[i]) - S) <= oracle.vec_tolerance(S, E) for i, (S, E) in refs.items())
+            rows.append({"b": b, "mode": mode, "jobs_per_s": round(J / dt, 1), "verified": ok,
+                         "host_sync_ms": round(st.host_ns_sync / 1e6, 2), "stolen": int(st.stolen)})
+            log("b=%d %s %.0f jobs/s" % (b, mode, J / dt))
+    table = {}
+    for r in rows:
+        table.setdefault(r["b"], {})[r["mode"]] = r["jobs_per_s"]
+    line = {"metric": METRIC, "workload": "worker-count sweep, %d per-job vector jobs per point" % J,
+            "unit": "jobs/s", "n_gpus": 1, "dtype": "f32", "data": "synthetic", "higher_is_better": True,
+            "vs_baseline": None, "table": table,
+            "set_over_batch": {b: round(t["set"] / t["batch"], 3) for b, t in table.items()},
+            "set_over_queue": {b: round(t["set"] / t["queue"], 3) for b, t in table.items()},
+            "runs": rows, "config": {"callback": args.callback, "dispatchers": args.dispatchers, "copy": args.copy}}
+    print(json.dumps(line), flush=True)
+
+
 def bench_serve(args, torch):
     """Open-loop serving: Poisson arrivals at each rate for a fixed window; half
     image jobs (Gaussian/Sobel at 256^2, 512^2, 1024^2, 2048^2, uniform) and
@@ -430,7 +489,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-passes", type=int, default=15)
     ap.add_argument("--stage-reps", type=int, default=200)
-    ap.add_argument("--workload", choices=["images", "vectors", "serve", "scan"], default="images")
+    ap.add_argument("--workload", choices=["images", "vectors", "serve", "scan", "sweep"], default="images")
+    ap.add_argument("--sweep-b", default="1,2,4,8,16,32,64", help="worker counts of the sweep workload")
+    ap.add_argument("--sweep-jobs", type=int, default=20000)
     ap.add_argument("--scan-jobs", type=int, default=20000)
     ap.add_argument("--scan-ring", type=int, default=48)
     ap.add_argument("--rates", default="2000,10000,40000")
@@ -465,6 +526,9 @@ def main():
         return
     if args.workload == "scan":
         bench_scan(args, torch)
+        return
+    if args.workload == "sweep":
+        bench_sweep(args, torch)
         return
     from paper_2606_05495_amd import synth
     from paper_2606_05495_amd.runtime import pinned
