@@ -151,7 +151,17 @@ enum set_pipeline {
      * set_out_header + one float32 S per job, in descriptor order.  Jobs are
      * normally submitted through set_run_vector_jobs, which builds the
      * tables; per-job S depends only on (n, tile size). */
-    SET_PIPE_SAXPY_BATCH_F32 = 4
+    SET_PIPE_SAXPY_BATCH_F32 = 4,
+    /* The inclusive int32 -> int64 scan of SET_PIPE_SCAN_I32_I64 done by a
+     * library call (rocPRIM's device scan) instead of this library's kernels:
+     * the job graph is built by stream capture of [H2D] -> a kernel writing
+     * the job's scalars into the slot -> the library's kernels -> a kernel
+     * publishing the output header -> [D2H] (Section 4.1: templates mixing
+     * explicit nodes and captured library code, with placeholders only for
+     * the job's own parameters).  The captured call has a fixed length, so
+     * every job has n = max_n (n = 0 in the job means max_n).  Not available
+     * in SET_MODE_BATCH_SYNC, and SET_TF_SCAN_LOW32 does not apply. */
+    SET_PIPE_SCAN_LIB_I32_I64 = 5
 };
 
 /* How a job's host<->device copies execute. */
@@ -413,6 +423,12 @@ typedef struct set_serve_stats {
  * requests' host buffers follow set_submit's rules. */
 int set_serve(set_ctx *c, const set_request *reqs, uint64_t count, const set_serve_config *cfg,
               uint64_t *done_ns, float *vec_results, set_serve_stats *stats);
+
+/* Bytes a job of length n (the vector, scan and batch pipelines; ignored by
+ * the image pipelines; 0 = the template's max_n where that applies) copies in
+ * (set_job_args.in_bytes must equal *in_bytes) and out (set_job_args.out_bytes
+ * must be at least *out_bytes).  Either output may be NULL. */
+int set_job_io_bytes(set_ctx *c, int template_id, uint64_t n, uint64_t *in_bytes, uint64_t *out_bytes);
 
 /* Number of kernels in the template's chain and the algorithmic HBM bytes one
  * launch of each moves (reads + writes of its operands, counted once). */

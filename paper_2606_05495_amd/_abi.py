@@ -33,6 +33,7 @@ SET_SUBMIT_ROUND_ROBIN, SET_SUBMIT_SHORTEST, SET_SUBMIT_SKEW0 = 0, 1, 2
 # pipelines
 SET_PIPE_BOX_HIST_U8, SET_PIPE_GAUSS_SOBEL_F32, SET_PIPE_SAXPY_TANH_SUM_F32, SET_PIPE_SCAN_I32_I64 = 0, 1, 2, 3
 SET_PIPE_SAXPY_BATCH_F32 = 4
+SET_PIPE_SCAN_LIB_I32_I64 = 5
 SET_TF_DEBUG, SET_TF_SCAN_LOW32, SET_TF_CAPTURE = 0x1, 0x2, 0x4
 SET_COPY_KERNELS, SET_COPY_NODES, SET_COPY_ASYNC_IN = 0, 1, 2
 COPY_MODES = {"nodes": SET_COPY_NODES, "kernels": SET_COPY_KERNELS, "async_in": SET_COPY_ASYNC_IN}
@@ -204,7 +205,7 @@ EXPORTS = [
     "set_ctx_create", "set_ctx_destroy", "set_template_footprint", "set_template_define", "set_submit",
     "set_submit_many", "set_set_completion_cb", "set_drain", "set_get_stats", "set_reset_stats",
     "set_get_job_times", "set_time_stage", "set_stage_info", "set_last_error", "set_strerror",
-    "set_run_vector_jobs", "set_serve",
+    "set_run_vector_jobs", "set_serve", "set_job_io_bytes",
 ]
 
 _lib = None
@@ -237,6 +238,7 @@ def load():
         "set_get_job_times": (I, [P, P, U64, ctypes.POINTER(U64)]),
         "set_time_stage": (I, [P, I, I, I, I, ctypes.POINTER(ctypes.c_double)]),
         "set_stage_info": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(U64), I, ctypes.c_char_p, I]),
+        "set_job_io_bytes": (I, [P, I, U64, ctypes.POINTER(U64), ctypes.POINTER(U64)]),
         "set_run_vector_jobs": (I, [P, I, P, U64, P, ctypes.POINTER(set_vec_tuning), ctypes.POINTER(U64)]),
         "set_serve": (I, [P, P, U64, ctypes.POINTER(set_serve_config), P, P, ctypes.POINTER(set_serve_stats)]),
         "set_last_error": (ctypes.c_char_p, [P]),
@@ -332,6 +334,12 @@ def set_time_stage(ctx, template_id: int, stage: int, worker: int, reps: int) ->
     us = ctypes.c_double()
     check(load().set_time_stage(ctx, template_id, stage, worker, reps, ctypes.byref(us)), ctx)
     return us.value
+
+
+def set_job_io_bytes(ctx, template_id: int, n: int = 0):
+    i, o = ctypes.c_uint64(), ctypes.c_uint64()
+    check(load().set_job_io_bytes(ctx, template_id, n, ctypes.byref(i), ctypes.byref(o)), ctx)
+    return i.value, o.value
 
 
 def set_stage_info(ctx, template_id: int):

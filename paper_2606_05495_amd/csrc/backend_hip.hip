@@ -7,6 +7,10 @@
 // (direct launches, per-job graph relaunch, one batch graph of b chains).
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+#include <rocprim/device/device_scan.hpp>
+#include <rocprim/iterator/transform_iterator.hpp>
+
 #include <algorithm>
 #include <cmath>
 #include <condition_variable>
@@ -62,6 +66,10 @@ struct Slot {
   void* d2h_argv[1] = {&d2h_copy};
   DoneFlagArgs flag{};
   void* flag_argv[1] = {&flag};
+  JobBeginArgs jb{};
+  JobEndArgs je{};
+  void* lib_ws = nullptr;  // library-call templates: this slot's share of the library workspace
+  size_t lib_ws_bytes = 0;
   uint64_t flag_seq = 0;  // sequence number the completion word will hold when the launched job is done
   int nstages = 0;
   const void* func[kMaxStages] = {};
@@ -91,6 +99,7 @@ struct Pipe {
   bool own_arena = false;
   void* placeholder = nullptr;  // pinned host buffer the memcpy nodes point at before the first bind
   uint64_t* words = nullptr;    // completion words, one 64-byte line per slot (SET_CB_HOST_FLAG)
+  void* lib_ws = nullptr;       // library-call templates: temporary storage of every slot
   std::vector<Slot> slots;      // [w * d + s]
   std::vector<BatchGraph> batch;  // [count - 1]
 };
@@ -113,6 +122,22 @@ inline dim3 to_dim3(Grid3 g) { return dim3(g.x, g.y, g.z); }
 inline bool in_by_kernel(const set_job_template& t) { return t.copy_mode == SET_COPY_KERNELS; }
 inline bool in_ahead(const set_job_template& t) { return t.copy_mode == SET_COPY_ASYNC_IN; }
 inline bool out_by_kernel(const set_job_template& t) { return t.copy_mode != SET_COPY_NODES; }
+
+// Templates whose middle stage is a library call captured into the job
+// graph (between stage kernel 0 and stage kernel 1).
+inline bool lib_template(const set_job_template& t) { return t.pipeline == SET_PIPE_SCAN_LIB_I32_I64; }
+
+struct WidenI32 {
+  __host__ __device__ int64_t operator()(int32_t v) const { return (int64_t)v; }
+};
+
+// The library stage: rocPRIM's device-wide inclusive scan of the slot's
+// int32 input into its int64 output, widening on load.  With ws == nullptr
+// only the workspace size is computed.
+hipError_t lib_scan(void* ws, size_t& ws_bytes, const int32_t* in, int64_t* out, size_t n, hipStream_t st) {
+  auto it = rocprim::make_transform_iterator(in, WidenI32{});
+  return rocprim::inclusive_scan(ws, ws_bytes, it, out, n, rocprim::plus<int64_t>(), st, false);
+}
 
 thread_local int t_dev = -1;
 
@@ -196,6 +221,12 @@ class HipBackend : public Backend {
     }
     float taps[3];
     gaussian_taps(taps);
+    size_t lib_ws_bytes = 0;
+    if (lib_template(t)) {
+      HIPCK(lib_scan(nullptr, lib_ws_bytes, nullptr, nullptr, (size_t)t.max_n, nullptr));
+      lib_ws_bytes = (std::max<size_t>(lib_ws_bytes, 256) + 255) / 256 * 256;
+      HIPCK(hipMalloc(&p.lib_ws, lib_ws_bytes * (size_t)b_ * d_));
+    }
     p.slots.resize((size_t)b_ * d_);
     for (int w = 0; w < b_; ++w) {
       for (int s = 0; s < d_; ++s) {
@@ -205,6 +236,10 @@ class HipBackend : public Backend {
         sl.s = s;
         sl.base = p.arena + p.L.total * ((uint64_t)w * d_ + s);
         setup_slot(p, sl, taps);
+        if (p.lib_ws) {
+          sl.lib_ws = (char*)p.lib_ws + lib_ws_bytes * ((size_t)w * d_ + s);
+          sl.lib_ws_bytes = lib_ws_bytes;
+        }
         if (p.words) sl.flag = DoneFlagArgs{reinterpret_cast<const DevSlotHdr*>(sl.base + p.L.hdr),
                                             p.words + ((size_t)w * d_ + s) * 8};
         const uint64_t ch = canary_value(id, w, s, 0), ct = canary_value(id, w, s, 1);
@@ -218,7 +253,7 @@ class HipBackend : public Backend {
         for (int s = 0; s < ds; ++s) {
           Slot& sl = p.slots[(size_t)w * d_ + s];
           int rc;
-          if (t.flags & SET_TF_CAPTURE) {
+          if ((t.flags & SET_TF_CAPTURE) || lib_template(t)) {
             rc = capture_chain(p, sl, streams_[w], &sl.graph, &sl.nodes, err);
           } else {
             HIPCK(hipGraphCreate(&sl.graph, 0));
@@ -322,8 +357,10 @@ class HipBackend : public Backend {
         HIPCK(hipMemcpyAsync(sl.base + p.L.in, sl.host_in, sl.in_bytes, hipMemcpyHostToDevice, st));
       }
     }
-    for (int i = 0; i < sl.nstages; ++i)
+    for (int i = 0; i < sl.nstages; ++i) {
+      if (i == 1) HIPCK(library_stage(p, sl, st));
       HIPCK(hipLaunchKernel(sl.func[i], sl.grid[i], dim3(kBlock), sl.argv[i], 0, st));
+    }
     if (out_by_kernel(p.t)) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, sl.host_out, sl.out_bytes};
       HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(d2h_copy_blocks(p.L.out_cap)), dim3(kBlock), sl.d2h_argv, 0, st));
@@ -391,18 +428,26 @@ class HipBackend : public Backend {
     ensure_dev();
     Pipe& p = *pipes_[tmpl];
     Slot& sl = p.slots[(size_t)worker * d_];
-    if (stage < 0 || stage >= sl.nstages) {
+    // library-call templates list [stage 0, library call, stage 1]
+    const bool lib = lib_template(p.t);
+    const int nlisted = sl.nstages + (lib ? 1 : 0);
+    if (stage < 0 || stage >= nlisted) {
       if (err) *err = "no such stage";
       return SET_EINVAL;
     }
+    const bool lib_call = lib && stage == 1;
+    const int ks = (lib && stage == 2) ? 1 : stage;
     hipStream_t st = streams_[worker];
+    auto once = [&]() -> hipError_t {
+      if (lib_call) return library_stage(p, sl, st);
+      return hipLaunchKernel(sl.func[ks], sl.grid[ks], dim3(kBlock), sl.argv[ks], 0, st);
+    };
     hipEvent_t e0, e1;
     HIPCK(hipEventCreate(&e0));
     HIPCK(hipEventCreate(&e1));
-    HIPCK(hipLaunchKernel(sl.func[stage], sl.grid[stage], dim3(kBlock), sl.argv[stage], 0, st));
+    HIPCK(once());
     HIPCK(hipEventRecord(e0, st));
-    for (int r = 0; r < reps; ++r)
-      HIPCK(hipLaunchKernel(sl.func[stage], sl.grid[stage], dim3(kBlock), sl.argv[stage], 0, st));
+    for (int r = 0; r < reps; ++r) HIPCK(once());
     HIPCK(hipEventRecord(e1, st));
     HIPCK(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -452,6 +497,7 @@ class HipBackend : public Backend {
       if (p.own_arena && p.arena) (void)hipFree(p.arena);
       if (p.placeholder) (void)hipHostFree(p.placeholder);
       if (p.words) (void)hipHostFree(p.words);
+      if (p.lib_ws) (void)hipFree(p.lib_ws);
     }
     pipes_.clear();
     for (hipStream_t s : cb_streams_) (void)hipStreamDestroy(s);
@@ -599,6 +645,12 @@ class HipBackend : public Backend {
         stage((const void*)&k_vec_batch_final, dim3((t.batch_max + kBlock - 1) / kBlock), &sl.vbf);
         break;
       }
+      case SET_PIPE_SCAN_LIB_I32_I64:
+        sl.jb = JobBeginArgs{sc.hdr, JobScalars{}};
+        sl.je = JobEndArgs{sc};
+        stage((const void*)&k_job_begin, dim3(1), &sl.jb);
+        stage((const void*)&k_job_end, dim3(1), &sl.je);
+        break;
       case SET_PIPE_SCAN_I32_I64: {
         const unsigned T = scan_tiles(t.max_n);
         const uint64_t q8 = ((uint64_t)T * 8 + 255) / 256 * 256;
@@ -644,6 +696,10 @@ class HipBackend : public Backend {
         if (js.n == 0) js.n = p.t.max_n;
         sl.scan_r.js = js;
         break;
+      case SET_PIPE_SCAN_LIB_I32_I64:
+        js.n = p.t.max_n;
+        sl.jb.js = js;
+        break;
       case SET_PIPE_SAXPY_BATCH_F32:
         sl.vb.js = js;
         sl.grid[0] = dim3(j->args.grid ? j->args.grid : (p.t.grid > 0 ? (unsigned)p.t.grid : (unsigned)kVecBatchGrid));
@@ -677,6 +733,14 @@ class HipBackend : public Backend {
     return kp;
   }
 
+  // The library stage of a library-call template (no-op for the others).
+  hipError_t library_stage(Pipe& p, Slot& sl, hipStream_t st) {
+    if (!lib_template(p.t)) return hipSuccess;
+    size_t bytes = sl.lib_ws_bytes;
+    return lib_scan(sl.lib_ws, bytes, reinterpret_cast<const int32_t*>(sl.base + p.L.in),
+                    reinterpret_cast<int64_t*>(sl.base + p.L.out + 64), (size_t)p.t.max_n, st);
+  }
+
   // SET_COPY_ASYNC_IN: the job's input copy, stream-ordered ahead of its graph.
   hipError_t input_ahead(Pipe& p, Slot& sl, hipStream_t st) {
     if (!in_ahead(p.t) || sl.in_bytes == 0) return hipSuccess;
@@ -684,6 +748,10 @@ class HipBackend : public Backend {
   }
 
   int add_chain(Pipe& p, Slot& sl, hipGraph_t g, ChainNodes* cn, std::string* err) {
+    if (lib_template(p.t)) {
+      if (err) *err = "library-call templates are built by stream capture only";
+      return SET_EUNSUPPORTED;
+    }
     const bool kcopy = in_by_kernel(p.t);
     hipGraphNode_t prev = nullptr;
     if (p.L.in_cap > 0 && !in_ahead(p.t)) {
@@ -743,8 +811,10 @@ class HipBackend : public Backend {
         HIPCK(hipMemcpyAsync(sl.base + p.L.in, p.placeholder, p.L.in_cap, hipMemcpyHostToDevice, st));
       }
     }
-    for (int i = 0; i < sl.nstages; ++i)
+    for (int i = 0; i < sl.nstages; ++i) {
+      if (i == 1) HIPCK(library_stage(p, sl, st));
       HIPCK(hipLaunchKernel(sl.func[i], sl.grid[i], dim3(kBlock), sl.argv[i], 0, st));
+    }
     if (out_by_kernel(p.t)) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, p.placeholder, p.L.out_cap};
       HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(d2h_copy_blocks(p.L.out_cap)), dim3(kBlock), sl.d2h_argv, 0, st));
@@ -757,8 +827,9 @@ class HipBackend : public Backend {
     HIPCK(hipGraphGetNodes(*out, nullptr, &n));
     std::vector<hipGraphNode_t> nodes(n);
     HIPCK(hipGraphGetNodes(*out, nodes.data(), &n));
-    const size_t expect = (in_node ? 1 : 0) + sl.nstages + 1 + (p.words ? 1 : 0);
-    if (n != expect) {
+    const size_t fixed = (in_node ? 1 : 0) + sl.nstages + 1 + (p.words ? 1 : 0);
+    const size_t lib_nodes = n - std::min(n, fixed);  // captured library kernels between stages 0 and 1
+    if (n < fixed || (lib_template(p.t) ? lib_nodes < 1 : lib_nodes != 0)) {
       if (err) *err = "captured graph has an unexpected number of nodes";
       return SET_EDEVICE;
     }
@@ -788,6 +859,18 @@ class HipBackend : public Backend {
     size_t k = 0;
     if (in_node) cn->h2d = order[k++];
     for (int i = 0; i < sl.nstages; ++i) {
+      if (i == 1) {
+        // the library's nodes: kernels only (no memset or memcpy nodes in a replayed graph)
+        for (size_t m = 0; m < lib_nodes; ++m) {
+          hipGraphNodeType ty;
+          HIPCK(hipGraphNodeGetType(order[k + m], &ty));
+          if (ty != hipGraphNodeTypeKernel) {
+            if (err) *err = "captured library call recorded a node that is not a kernel";
+            return SET_EUNSUPPORTED;
+          }
+        }
+        k += lib_nodes;
+      }
       hipKernelNodeParams kp{};
       HIPCK(hipGraphKernelNodeGetParams(order[k], &kp));
       if (kp.func != sl.func[i]) {

@@ -127,6 +127,14 @@ __global__ __launch_bounds__(64) void k_done_flag(DoneFlagArgs a) {
   if (threadIdx.x == 0) __hip_atomic_store(a.word, a.hdr->seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// ------------------------------------------------------------------ bracket kernels of library-call jobs
+__global__ __launch_bounds__(kBlock) void k_job_begin(JobBeginArgs a) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
+}
+__global__ __launch_bounds__(kBlock) void k_job_end(JobEndArgs a) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) publish_out(a.sc, true);
+}
+
 // ------------------------------------------------------------------ 3x3 box sum (zero padded), uint8 -> uint16
 // Output tile kBoxTW x kBoxTH, input tile + 1-pixel halo staged in LDS.
 __global__ __launch_bounds__(kBlock) void k_box3_u8_u16(BoxArgs a) {

@@ -136,6 +136,19 @@ struct DoneFlagArgs {
 };
 __global__ void k_done_flag(DoneFlagArgs a);
 
+// Bracket kernels of a job whose middle stages are library code captured
+// into the job graph: the first writes the job's scalars into the slot
+// header, the last checks the canaries and publishes the output header.
+struct JobBeginArgs {
+  DevSlotHdr* hdr;
+  JobScalars js;
+};
+struct JobEndArgs {
+  SlotConst sc;
+};
+__global__ void k_job_begin(JobBeginArgs a);
+__global__ void k_job_end(JobEndArgs a);
+
 __global__ void k_box3_u8_u16(BoxArgs a);
 __global__ void k_div9_u16_u8(Div9Args a);
 __global__ void k_hist256_u8(HistArgs a);

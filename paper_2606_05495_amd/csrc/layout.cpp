@@ -33,6 +33,10 @@ int pipeline_validate(const set_job_template& t, std::string* why) {
     case SET_PIPE_SCAN_I32_I64:
       if (t.max_n < 1 || t.max_n > (1ull << 31)) return bad("scan template needs 1 <= max_n <= 2^31");
       break;
+    case SET_PIPE_SCAN_LIB_I32_I64:
+      if (t.max_n < 1 || t.max_n > (1ull << 31)) return bad("scan template needs 1 <= max_n <= 2^31");
+      if (t.flags & SET_TF_SCAN_LOW32) return bad("the library scan template writes the full int64 output");
+      break;
     case SET_PIPE_SAXPY_BATCH_F32:
       if (t.max_n < 1 || t.max_n > (1ull << 32) - 1) return bad("vector batch template needs 1 <= max_n < 2^32");
       if (t.dev_x_pool == nullptr || t.dev_y_pool == nullptr || t.pool_len < 1)
@@ -135,6 +139,19 @@ static SlotLayout layout_of(const set_job_template& t) {
       off = up(off + L.scratch_bytes);
       break;
     }
+    case SET_PIPE_SCAN_LIB_I32_I64: {
+      // the library's temporary storage is a separate per-slot workspace
+      const uint64_t n = t.max_n;
+      L.in = off;
+      L.in_cap = 4 * n;
+      off = up(off + 4 * n);
+      L.out = off;
+      L.out_cap = 64 + 8 * n;
+      off = up(off + L.out_cap);
+      L.scratch = off;
+      L.scratch_bytes = 0;
+      break;
+    }
     case SET_PIPE_SCAN_I32_I64: {
       const uint64_t n = t.max_n;
       const uint64_t tiles = scan_tiles(n);
@@ -169,6 +186,7 @@ uint64_t pipeline_in_bytes(const set_job_template& t, uint64_t n) {
     case SET_PIPE_SAXPY_TANH_SUM_F32:
       return 0;
     case SET_PIPE_SCAN_I32_I64:
+    case SET_PIPE_SCAN_LIB_I32_I64:
       return 4ull * (n ? n : t.max_n);
     case SET_PIPE_SAXPY_BATCH_F32:
       return 64 + 48ull * n;
@@ -185,6 +203,8 @@ uint64_t pipeline_out_bytes(const set_job_template& t, uint64_t n) {
       return 64 + 4;
     case SET_PIPE_SCAN_I32_I64:
       return 64 + ((t.flags & SET_TF_SCAN_LOW32) ? 4ull : 8ull) * (n ? n : t.max_n);
+    case SET_PIPE_SCAN_LIB_I32_I64:
+      return 64 + 8ull * t.max_n;
     case SET_PIPE_SAXPY_BATCH_F32:
       return 64 + 4ull * n;
   }
@@ -205,6 +225,10 @@ int pipeline_validate_job(const set_job_template& t, const set_job_args& a, std:
   if (t.pipeline == SET_PIPE_SCAN_I32_I64) {
     if (n == 0) n = t.max_n;
     if (n > t.max_n) return bad("scan job n exceeds template max_n");
+  }
+  if (t.pipeline == SET_PIPE_SCAN_LIB_I32_I64) {
+    if (n == 0) n = t.max_n;
+    if (n != t.max_n) return bad("library scan jobs have n = template max_n (the captured call has a fixed length)");
   }
   if (t.pipeline == SET_PIPE_SAXPY_BATCH_F32 && (n < 1 || n > t.batch_max))
     return bad("vector batch job needs 1 <= n (jobs in the batch) <= batch_max");
@@ -254,6 +278,11 @@ int pipeline_sizes(const set_job_template& t, TemplateSizes* out) {
       // the streamed bytes depend on the batch (8 bytes per element of every job)
       stage("vec_batch_tiles", 64 + 48ull * t.batch_max + 4ull * t.tiles_max);
       stage("vec_batch_final", 64 + 48ull * t.batch_max + 4ull * t.tiles_max + 4ull * t.batch_max);
+      break;
+    case SET_PIPE_SCAN_LIB_I32_I64:
+      stage("job_begin", 64);
+      stage("scan_lib_rocprim", 4 * t.max_n + 8 * t.max_n);  // the library's own traffic is its business
+      stage("job_end", 64 + 64);
       break;
     case SET_PIPE_SCAN_I32_I64: {
       const uint64_t T = scan_tiles(t.max_n);

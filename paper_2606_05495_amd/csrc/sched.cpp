@@ -363,6 +363,8 @@ class Context {
     if (ntmpl.load() >= kMaxTemplates) return fail(SET_EINVAL, "too many templates");
     std::string why;
     if (pipeline_validate(t, &why) != SET_OK) return fail(SET_EINVAL, why);
+    if (t.pipeline == SET_PIPE_SCAN_LIB_I32_I64 && cfg.mode == SET_MODE_BATCH_SYNC)
+      return fail(SET_EUNSUPPORTED, "library-call templates are captured per slot; no batch graph is built for them");
     TemplateSizes sz;
     pipeline_sizes(t, &sz);
     const int tid = (int)templates.size();
@@ -802,7 +804,9 @@ class Context {
     j->tmpl = tmpl;
     j->args = *a;
     j->serve_ref = serve_ref;
-    if (templates[tmpl].pipeline == SET_PIPE_SCAN_I32_I64 && j->args.n == 0) j->args.n = templates[tmpl].max_n;
+    if ((templates[tmpl].pipeline == SET_PIPE_SCAN_I32_I64 || templates[tmpl].pipeline == SET_PIPE_SCAN_LIB_I32_I64) &&
+        j->args.n == 0)
+      j->args.n = templates[tmpl].max_n;
     j->footprint = tsizes[tmpl].slot_bytes;
     if (cfg.mode == SET_MODE_SET) {
       std::unique_lock<std::mutex> lk(stage_mu);
@@ -1395,6 +1399,15 @@ int set_time_stage(set_ctx* c, int template_id, int stage, int worker, int reps,
   std::string err;
   int rc = c->impl.be->time_stage(template_id, stage, worker, reps, avg_us, &err);
   if (rc != SET_OK) return c->impl.fail(rc, "time_stage: " + err);
+  return SET_OK;
+}
+
+int set_job_io_bytes(set_ctx* c, int template_id, uint64_t n, uint64_t* in_bytes, uint64_t* out_bytes) {
+  if (!c) return SET_EINVAL;
+  if (!c->impl.valid_template(template_id)) return SET_EINVAL;
+  const set_job_template& t = c->impl.templates[template_id];
+  if (in_bytes) *in_bytes = setrt::pipeline_in_bytes(t, n);
+  if (out_bytes) *out_bytes = setrt::pipeline_out_bytes(t, n);
   return SET_OK;
 }
 

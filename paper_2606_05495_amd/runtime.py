@@ -18,6 +18,7 @@ PIPELINES = {
     "saxpy_tanh_sum": A.SET_PIPE_SAXPY_TANH_SUM_F32,
     "scan": A.SET_PIPE_SCAN_I32_I64,
     "saxpy_batch": A.SET_PIPE_SAXPY_BATCH_F32,
+    "scan_lib": A.SET_PIPE_SCAN_LIB_I32_I64,
 }
 
 
@@ -117,36 +118,12 @@ class Context:
         return tid
 
     def in_bytes(self, tid, n=0):
-        t = self.templates[tid]
-        if t.pipeline == A.SET_PIPE_BOX_HIST_U8:
-            return t.width * t.height
-        if t.pipeline == A.SET_PIPE_GAUSS_SOBEL_F32:
-            return 4 * t.width * t.height
-        if t.pipeline == A.SET_PIPE_SCAN_I32_I64:
-            return 4 * (n or t.max_n)
-        return 0
+        """Input bytes of a job of length n (0 = the template's max_n where that applies)."""
+        return A.set_job_io_bytes(self.h, tid, n)[0]
 
     def out_bytes(self, tid, n=0):
-        t = self.templates[tid]
-        dbg = bool(t.flags & A.SET_TF_DEBUG)
-        npix = t.width * t.height
-        up64 = lambda v: (v + 63) // 64 * 64
-        if t.pipeline == A.SET_PIPE_BOX_HIST_U8:
-            if dbg:
-                s_off = up64(64 + 1024)
-                q_off = up64(s_off + 2 * npix)
-                return q_off + npix
-            return 64 + 1024
-        if t.pipeline == A.SET_PIPE_GAUSS_SOBEL_F32:
-            if dbg:
-                return up64(128 + npix) + 4 * npix
-            return 64 + 8
-        if t.pipeline == A.SET_PIPE_SAXPY_TANH_SUM_F32:
-            return 64 + 4
-        if t.pipeline == A.SET_PIPE_SAXPY_BATCH_F32:
-            return 64 + 4 * n
-        lo = bool(t.flags & A.SET_TF_SCAN_LOW32)
-        return 64 + (4 if lo else 8) * (n or t.max_n)
+        """Output bytes (header + payload) of a job of length n."""
+        return A.set_job_io_bytes(self.h, tid, n)[1]
 
     # ------------------------------------------------------------ jobs
     @staticmethod

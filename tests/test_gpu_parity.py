@@ -295,9 +295,10 @@ def _run_scan_flags(mode, inputs, max_n, flags, copy):
     return _run_scan(mode, inputs, max_n, copy=copy, extra_flags=flags)
 
 
-def _run_scan(mode, inputs, max_n, low32=False, workers=4, slots=4, copy="kernels", extra_flags=0, **kw):
+def _run_scan(mode, inputs, max_n, low32=False, workers=4, slots=4, copy="kernels", extra_flags=0, pipeline="scan",
+              **kw):
     ctx = Context(mode=mode, workers=workers, slots=slots, **kw)
-    tid = ctx.define("scan", max_n=max_n, flags=(A.SET_TF_SCAN_LOW32 if low32 else 0) | extra_flags, copy=copy)
+    tid = ctx.define(pipeline, max_n=max_n, flags=(A.SET_TF_SCAN_LOW32 if low32 else 0) | extra_flags, copy=copy)
     k = len(inputs)
     ib = [4 * len(v) for v in inputs]
     ob = [ctx.out_bytes(tid, len(v)) for v in inputs]
@@ -657,3 +658,36 @@ def test_async_input_copy_all_modes(torch_gpu, vec_pools, mode):
             n, xo, yo = int(jobs["n"][i]), int(jobs["x_off"][i]), int(jobs["y_off"][i])
             S, E = oracle.saxpy_tanh_sum(x[xo:xo + n], y[yo:yo + n], jobs["a"][i])
             assert abs(res[i] - S) <= oracle.vec_tolerance(S, E)
+
+
+# ------------------------------------------------------------------ library call captured into the job graph
+@pytest.mark.parametrize("mode,copy,callback", [("set", "kernels", "host_flag"), ("set", "async_in", "event_poll"),
+                                                ("set", "nodes", "host_flag"), ("graph", "kernels", "host_flag"),
+                                                ("queue", "kernels", "host_flag"), ("sync", "kernels", "host_flag")])
+def test_library_scan_template(torch_gpu, mode, copy, callback):
+    """rocPRIM's device scan captured between the job's begin/end kernels: exact int64 prefix sums,
+    headers published, any slot, repeated replays of every slot's graph."""
+    _say("library scan", mode, copy, callback)
+    for n in (1, 1000, 1 << 21):
+        inputs = [synth.scan_input(1, k, n) for k in range(3)]
+        res = _run_scan(mode, inputs * 4, max_n=n, copy=copy, callback=callback, pipeline="scan_lib")
+        for k, r in enumerate(res):
+            assert np.array_equal(r, oracle.scan(inputs[k % 3])), (n, k)
+
+
+def test_library_scan_stage_timing(torch_gpu):
+    """The library stage is timed like the kernel stages."""
+    ctx = Context(mode="set", workers=1, slots=2)
+    tid = ctx.define("scan_lib", max_n=1 << 21)
+    ib, ob = ctx.in_bytes(tid), ctx.out_bytes(tid)
+    tin, nin = pinned(ib)
+    nin.view(np.int32)[:] = synth.scan_input(1, 0, 1 << 21)
+    tout, nout = pinned(ob)
+    ctx.submit(tid, host_in=tin.data_ptr(), in_bytes=ib, host_out=tout.data_ptr(), out_bytes=ob)
+    ctx.drain()
+    names = [nm for nm, _ in ctx.stage_info(tid)]
+    us = [ctx.time_stage(tid, i, 0, 5) for i in range(len(names))]
+    ctx.close()
+    assert names == ["job_begin", "scan_lib_rocprim", "job_end"]
+    assert all(u > 0 for u in us)
+    assert np.array_equal(nout[64:].view(np.int64), oracle.scan(synth.scan_input(1, 0, 1 << 21)))

@@ -414,3 +414,24 @@ def test_define_template_while_other_jobs_run():
         assert np.all(_headers(outs0)["magic"] == A.SET_OUT_MAGIC)
         for _, outs in arrs:
             assert np.all(_headers(outs)["canary_ok"] == 1)
+
+
+def test_library_scan_template_rules():
+    """Library-call templates: fixed length (n = max_n), no low-word output, no batch graph."""
+    with _fake(workers=2, slots=2) as ctx:
+        tid = ctx.define("scan_lib", max_n=1000)
+        assert ctx.out_bytes(tid) == 64 + 8 * 1000 and ctx.in_bytes(tid) == 4 * 1000
+        names = [n for n, _ in ctx.stage_info(tid)]
+        assert names == ["job_begin", "scan_lib_rocprim", "job_end"]
+        inp = np.zeros(1000, np.int32)
+        out = np.zeros(64 + 8 * 1000, np.uint8)
+        with pytest.raises(A.SetError) as e:
+            ctx.submit(tid, host_in=inp.ctypes.data, in_bytes=4 * 500, host_out=out.ctypes.data,
+                       out_bytes=out.size, n=500)
+        assert e.value.code == A.SET_EINVAL
+        with pytest.raises(A.SetError):
+            ctx.define("scan_lib", max_n=1000, flags=A.SET_TF_SCAN_LOW32)
+    with _fake(mode="batch", workers=2, slots=1, batch_size=2) as ctx:
+        with pytest.raises(A.SetError) as e:
+            ctx.define("scan_lib", max_n=1000)
+        assert e.value.code == A.SET_EUNSUPPORTED
