@@ -46,7 +46,9 @@ def lib():
         _lib.oracle_gauss_sobel_f32.argtypes = [P, I64, I64, ctypes.c_double, P, P, P, P, P, P]
         _lib.oracle_saxpy_tanh_sum_f32.argtypes = [P, P, I64, ctypes.c_float, P, P]
         _lib.oracle_scan_i32_i64.argtypes = [P, I64, P]
-        for f in ("oracle_box_hist_u8", "oracle_gauss_sobel_f32", "oracle_saxpy_tanh_sum_f32", "oracle_scan_i32_i64"):
+        _lib.oracle_hotspot_f32.argtypes = [P, P, I64, I64, ctypes.c_int, P]
+        for f in ("oracle_box_hist_u8", "oracle_gauss_sobel_f32", "oracle_saxpy_tanh_sum_f32", "oracle_scan_i32_i64",
+                  "oracle_hotspot_f32"):
             getattr(_lib, f).restype = ctypes.c_int
     return _lib
 
@@ -110,6 +112,27 @@ def scan(x: np.ndarray) -> np.ndarray:
     out = np.empty(x.size, np.int64)
     _check(lib().oracle_scan_i32_i64(_ptr(x), x.size, _ptr(out)), "scan")
     return out
+
+
+HOTSPOT = {"cx": 0.1, "cy": 0.1, "cz": 1.0 / 640.0, "cp": 0.5, "t_amb": 300.0}
+
+
+def hotspot(T0: np.ndarray, P: np.ndarray, iters: int) -> np.ndarray:
+    """Temperature grid after `iters` explicit heat steps (float64)."""
+    T0 = np.ascontiguousarray(T0, dtype=np.float32)
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    assert T0.shape == P.shape and T0.ndim == 2
+    out = np.empty(T0.shape, np.float64)
+    _check(lib().oracle_hotspot_f32(_ptr(T0), _ptr(P), T0.shape[0], T0.shape[1], int(iters), _ptr(out)), "hotspot")
+    return out
+
+
+def hotspot_tolerance(ref: np.ndarray, iters: int) -> float:
+    """Allowed max |T_gpu - T_ref| for float32 evaluation: each step rounds a
+    handful of operations on values of magnitude <= max|T| (the coefficients
+    sum below 1), and the monotone step does not amplify earlier errors, so
+    the error grows at most linearly: (iters + 1) * 8 * 2^-24 * max|T|."""
+    return (iters + 1) * 8.0 * 2.0 ** -24 * float(np.max(np.abs(ref)))
 
 
 def vec_tolerance(S_ref: float, E: float) -> float:

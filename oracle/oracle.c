@@ -22,7 +22,9 @@
  *                   borders, horizontal then vertical, unnormalised Sobel,
  *                   L2 magnitude, strict mag > 1 threshold, sum over all pixels;
  *   vector job    : z = a*x + y, t = tanh(z), S = sum t;
- *   scan          : inclusive prefix sum of int32 into int64.
+ *   scan          : inclusive prefix sum of int32 into int64;
+ *   thermal grid  : explicit five-point heat update with power input and an
+ *                   ambient loss term, zero-flux borders (see below).
  *
  * parity pinned: every function here is pinned by tests against brute force,
  * closed forms and invariants (see the oracle tests).
@@ -204,5 +206,63 @@ int oracle_scan_i32_i64(const int32_t *in, int64_t n, int64_t *out)
         acc += (int64_t)in[i];
         out[i] = acc;
     }
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------ thermal grid (iterative stencil) */
+/*
+ * The memory-bound iterative workload standing in for the paper's Hotspot
+ * (Section 5.1): a chip's temperature grid T advanced by explicit steps of
+ * the two-dimensional heat equation with a power-density source and a
+ * leakage to ambient.  One step, for every cell, with N, S, W, E its four
+ * neighbours (a neighbour outside the grid is the cell itself: no heat
+ * crosses the border):
+ *
+ *   T' = T + CP*P + CY*(N + S - 2T) + CX*(W + E - 2T) + CZ*(T_AMB - T)
+ *
+ * iterated `iters` times from T0.  The coefficients are the workload's
+ * (CX = CY = 0.1, CZ = 1/640, CP = 0.5, T_AMB = 300); 1 - 2CX - 2CY - CZ > 0,
+ * so every step is a convex combination plus source and the scheme is
+ * monotone.  Evaluated in double from the float32 inputs.
+ */
+#define HS_CX 0.1
+#define HS_CY 0.1
+#define HS_CZ (1.0 / 640.0)
+#define HS_CP 0.5
+#define HS_TAMB 300.0
+
+int oracle_hotspot_f32(const float *T0, const float *P, int64_t h, int64_t w, int iters, double *out)
+{
+    if (h < 1 || w < 1 || iters < 0 || T0 == NULL || P == NULL || out == NULL)
+        return ORACLE_EINVAL;
+    const int64_t n = h * w;
+    double *a = (double *)malloc((size_t)n * sizeof(double));
+    double *b = (double *)malloc((size_t)n * sizeof(double));
+    if (!a || !b) {
+        free(a);
+        free(b);
+        return ORACLE_ENOMEM;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        a[i] = (double)T0[i];
+    for (int k = 0; k < iters; ++k) {
+        for (int64_t y = 0; y < h; ++y) {
+            for (int64_t x = 0; x < w; ++x) {
+                const double t = a[y * w + x];
+                const double nn = a[clampi(y - 1, 0, h - 1) * w + x];
+                const double ss = a[clampi(y + 1, 0, h - 1) * w + x];
+                const double ww = a[y * w + clampi(x - 1, 0, w - 1)];
+                const double ee = a[y * w + clampi(x + 1, 0, w - 1)];
+                b[y * w + x] = t + HS_CP * (double)P[y * w + x] + HS_CY * (nn + ss - 2.0 * t) +
+                               HS_CX * (ww + ee - 2.0 * t) + HS_CZ * (HS_TAMB - t);
+            }
+        }
+        double *tmp = a;
+        a = b;
+        b = tmp;
+    }
+    memcpy(out, a, (size_t)n * sizeof(double));
+    free(a);
+    free(b);
     return ORACLE_OK;
 }

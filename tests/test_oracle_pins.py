@@ -250,3 +250,60 @@ def test_scan_brute_force(rng):
             acc += v
             ref.append(acc)
         assert out.tolist() == ref
+
+
+# ------------------------------------------------------------------ thermal grid
+HS = oracle.HOTSPOT
+
+
+def test_hotspot_ambient_is_a_fixed_point():
+    T0 = np.full((7, 9), HS["t_amb"], np.float32)
+    P = np.zeros((7, 9), np.float32)
+    assert np.array_equal(oracle.hotspot(T0, P, 12), T0.astype(np.float64))
+
+
+@pytest.mark.parametrize("t0,p,k", [(320.0, 0.0, 5), (300.0, 0.25, 9), (280.0, 1.0, 1), (350.0, 0.5, 0)])
+def test_hotspot_uniform_closed_form(t0, p, k):
+    # a uniform grid stays uniform (zero-flux borders, zero Laplacian); the
+    # scalar recurrence T <- T + cp*p + cz*(Tamb - T) sums to a geometric series
+    T0 = np.full((5, 6), t0, np.float32)
+    P = np.full((5, 6), p, np.float32)
+    fix = HS["t_amb"] + HS["cp"] * np.float64(np.float32(p)) / HS["cz"]
+    want = fix + (np.float64(np.float32(t0)) - fix) * (1.0 - HS["cz"]) ** k
+    got = oracle.hotspot(T0, P, k)
+    assert np.allclose(got, want, rtol=0, atol=1e-9)
+
+
+def _hotspot_brute(T0, P, k):
+    # independent restatement: padded arrays instead of clamped indices
+    T = T0.astype(np.float64)
+    for _ in range(k):
+        E = np.pad(T, 1, mode="edge")
+        lap_y = E[:-2, 1:-1] + E[2:, 1:-1] - 2 * T
+        lap_x = E[1:-1, :-2] + E[1:-1, 2:] - 2 * T
+        T = T + HS["cp"] * P.astype(np.float64) + HS["cy"] * lap_y + HS["cx"] * lap_x + HS["cz"] * (HS["t_amb"] - T)
+    return T
+
+
+@pytest.mark.parametrize("shape,k", [((1, 1), 3), ((1, 5), 4), ((4, 1), 2), ((3, 4), 3), ((6, 7), 6)])
+def test_hotspot_brute_force(shape, k, rng):
+    T0 = (300 + 40 * rng.random(shape)).astype(np.float32)
+    P = rng.random(shape).astype(np.float32)
+    assert np.allclose(oracle.hotspot(T0, P, k), _hotspot_brute(T0, P, k), rtol=0, atol=1e-9)
+
+
+def test_hotspot_symmetries_and_maximum_principle(rng):
+    T0 = (300 + 50 * rng.random((8, 8))).astype(np.float32)
+    P = np.zeros((8, 8), np.float32)
+    out = oracle.hotspot(T0, P, 10)
+    # cx == cy: transposing and flipping the input does the same to the output
+    assert np.allclose(oracle.hotspot(T0.T.copy(), P, 10), out.T, rtol=0, atol=1e-9)
+    assert np.allclose(oracle.hotspot(T0[::-1, ::-1].copy(), P, 10), out[::-1, ::-1], rtol=0, atol=1e-9)
+    # no source: a monotone step keeps every cell within [min(T0, Tamb), max(T0, Tamb)]
+    assert out.min() >= min(T0.min(), HS["t_amb"]) - 1e-9 and out.max() <= max(T0.max(), HS["t_amb"]) + 1e-9
+    # a single hot cell spreads symmetrically and the heat above ambient decays by (1 - cz) per step
+    T1 = np.full((9, 9), HS["t_amb"], np.float32)
+    T1[4, 4] = 400.0
+    o1 = oracle.hotspot(T1, P[:1, :1].repeat(9, 0).repeat(9, 1), 3)
+    assert np.allclose(o1, o1.T, rtol=0, atol=1e-12) and np.allclose(o1, o1[::-1, :], rtol=0, atol=1e-12)
+    assert (o1 - HS["t_amb"]).sum() == pytest.approx(100.0 * (1 - HS["cz"]) ** 3, rel=1e-12)
