@@ -387,6 +387,67 @@ def bench_sweep(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def bench_hotspot(args, torch):
+    """Thermal-grid jobs (a memory-bound iterative workload): H2D of a
+    temperature and a power grid -> K explicit heat steps, one kernel each ->
+    D2H of the final grid.  SET against batch-sync, synchronous and the queue
+    model on the same jobs.  Prints one JSON line."""
+    from paper_2606_05495_amd import synth
+    from paper_2606_05495_amd.runtime import Context, pinned
+    import oracle
+    h = w = args.hot_side
+    K, J, P = args.hot_steps, args.hot_jobs, 16
+    grids = [synth.hotspot_input(0, k, h, w) for k in range(P)]
+    refs = [oracle.hotspot(t0, p, K) for t0, p in grids]
+    ib, ob = 8 * h * w, 64 + 4 * h * w
+    istride, ostride = (ib + 255) // 256 * 256, (ob + 255) // 256 * 256
+    tin, nin = pinned(istride * P)
+    for i, (t0, p) in enumerate(grids):
+        nin[i * istride:i * istride + ib].view(np.float32)[:] = np.concatenate([t0.ravel(), p.ravel()])
+    R = 256  # output ring
+    tout, nout = pinned(ostride * R)
+    out = {}
+    for mode in ("set", "batch", "sync", "queue"):
+        c = Context(mode=mode, workers=args.workers, slots=args.slots if mode == "set" else 1,
+                    batch_size=args.batch if mode == "batch" else 0, callback=args.callback,
+                    dispatchers=args.dispatchers)
+        tid = c.define("hotspot", width=w, height=h, max_n=K, copy=args.copy)
+        j = np.arange(J, dtype=np.uint64)
+        arr = c.job_array(J)
+        arr["host_in"] = tin.data_ptr() + (j % np.uint64(P)) * np.uint64(istride)
+        arr["in_bytes"] = ib
+        arr["host_out"] = tout.data_ptr() + (j % np.uint64(R)) * np.uint64(ostride)
+        arr["out_bytes"] = ob
+        c.submit_many(tid, arr[:min(J, 2 * R)])
+        c.drain()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.submit_many(tid, arr)
+        c.drain()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        c.close()
+        # the ring holds the last R jobs: job J - R + i sits in ring entry (J - R + i) % R
+        ok = True
+        for i in range(min(R, J)):
+            jj = J - min(R, J) + i
+            o = nout[(jj % R) * ostride + 64:(jj % R) * ostride + ob].view(np.float32).reshape(h, w)
+            ref = refs[jj % P]
+            ok &= bool(np.max(np.abs(o - ref)) <= oracle.hotspot_tolerance(ref, K))
+        out[mode] = {"jobs_per_s": round(J / dt, 1), "verified": ok}
+        log("hotspot %s %.0f jobs/s" % (mode, J / dt))
+    v = out["set"]["jobs_per_s"]
+    line = {"metric": METRIC, "workload": "thermal grid: %d jobs, %dx%d float32, %d steps per job" % (J, h, w, K),
+            "value": v, "unit": "jobs/s", "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+            "higher_is_better": True, "vs_baseline": None,
+            "speedup_vs_batch_sync": round(v / out["batch"]["jobs_per_s"], 3),
+            "speedup_vs_sync": round(v / out["sync"]["jobs_per_s"], 3),
+            "speedup_vs_queue": round(v / out["queue"]["jobs_per_s"], 3),
+            "modes": out, "config": {"workers": args.workers, "slots": args.slots, "batch": args.batch,
+                                     "callback": args.callback, "dispatchers": args.dispatchers, "copy": args.copy}}
+    print(json.dumps(line), flush=True)
+
+
 def bench_serve(args, torch):
     """Open-loop serving: Poisson arrivals at each rate for a fixed window; half
     image jobs (Gaussian/Sobel at 256^2, 512^2, 1024^2, 2048^2, uniform) and
@@ -489,7 +550,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-passes", type=int, default=15)
     ap.add_argument("--stage-reps", type=int, default=200)
-    ap.add_argument("--workload", choices=["images", "vectors", "serve", "scan", "sweep"], default="images")
+    ap.add_argument("--workload", choices=["images", "vectors", "serve", "scan", "sweep", "hotspot"], default="images")
+    ap.add_argument("--hot-side", type=int, default=256)
+    ap.add_argument("--hot-steps", type=int, default=16)
+    ap.add_argument("--hot-jobs", type=int, default=10000)
     ap.add_argument("--sweep-b", default="1,2,4,8,16,32,64", help="worker counts of the sweep workload")
     ap.add_argument("--sweep-jobs", type=int, default=20000)
     ap.add_argument("--scan-jobs", type=int, default=20000)
@@ -529,6 +593,9 @@ def main():
         return
     if args.workload == "sweep":
         bench_sweep(args, torch)
+        return
+    if args.workload == "hotspot":
+        bench_hotspot(args, torch)
         return
     from paper_2606_05495_amd import synth
     from paper_2606_05495_amd.runtime import pinned

@@ -161,7 +161,16 @@ enum set_pipeline {
      * the job's own parameters).  The captured call has a fixed length, so
      * every job has n = max_n (n = 0 in the job means max_n).  Not available
      * in SET_MODE_BATCH_SYNC, and SET_TF_SCAN_LOW32 does not apply. */
-    SET_PIPE_SCAN_LIB_I32_I64 = 5
+    SET_PIPE_SCAN_LIB_I32_I64 = 5,
+    /* Iterative thermal grid (a memory-bound iterative workload like the
+     * paper's Hotspot, Section 5.1): in = temperature grid T0 followed by
+     * the power grid P (each height x width float32, row-major); max_n = the
+     * number of explicit steps K (1..32), each one kernel of the chain:
+     *   T' = T + 0.5*P + 0.1*(N + S - 2T) + 0.1*(W + E - 2T) + (300 - T)/640
+     * with N, S, W, E the four neighbours and a neighbour outside the grid
+     * taken as the cell itself (no heat crosses the border); then a kernel
+     * publishing the header.  out: set_out_header + T_K (float32, row-major). */
+    SET_PIPE_HOTSPOT_F32 = 6
 };
 
 /* How a job's host<->device copies execute. */

@@ -34,6 +34,7 @@ SET_SUBMIT_ROUND_ROBIN, SET_SUBMIT_SHORTEST, SET_SUBMIT_SKEW0 = 0, 1, 2
 SET_PIPE_BOX_HIST_U8, SET_PIPE_GAUSS_SOBEL_F32, SET_PIPE_SAXPY_TANH_SUM_F32, SET_PIPE_SCAN_I32_I64 = 0, 1, 2, 3
 SET_PIPE_SAXPY_BATCH_F32 = 4
 SET_PIPE_SCAN_LIB_I32_I64 = 5
+SET_PIPE_HOTSPOT_F32 = 6
 SET_TF_DEBUG, SET_TF_SCAN_LOW32, SET_TF_CAPTURE = 0x1, 0x2, 0x4
 SET_COPY_KERNELS, SET_COPY_NODES, SET_COPY_ASYNC_IN = 0, 1, 2
 COPY_MODES = {"nodes": SET_COPY_NODES, "kernels": SET_COPY_KERNELS, "async_in": SET_COPY_ASYNC_IN}
@@ -344,9 +345,9 @@ def set_job_io_bytes(ctx, template_id: int, n: int = 0):
 
 def set_stage_info(ctx, template_id: int):
     n = ctypes.c_int()
-    b = (ctypes.c_uint64 * 8)()
-    names = ctypes.create_string_buffer(512)
-    check(load().set_stage_info(ctx, template_id, ctypes.byref(n), b, 8, names, 512), ctx)
+    b = (ctypes.c_uint64 * 64)()
+    names = ctypes.create_string_buffer(64 * 32)
+    check(load().set_stage_info(ctx, template_id, ctypes.byref(n), b, 64, names, 64 * 32), ctx)
     return list(zip(names.value.decode().split(","), list(b)[:n.value]))
 
 

@@ -68,6 +68,7 @@ struct Slot {
   void* flag_argv[1] = {&flag};
   JobBeginArgs jb{};
   JobEndArgs je{};
+  HotspotArgs hot[kMaxHotspotSteps] = {};
   void* lib_ws = nullptr;  // library-call templates: this slot's share of the library workspace
   size_t lib_ws_bytes = 0;
   uint64_t flag_seq = 0;  // sequence number the completion word will hold when the launched job is done
@@ -645,6 +646,23 @@ class HipBackend : public Backend {
         stage((const void*)&k_vec_batch_final, dim3((t.batch_max + kBlock - 1) / kBlock), &sl.vbf);
         break;
       }
+      case SET_PIPE_HOTSPOT_F32: {
+        // step k reads T_k and writes T_{k+1}: T_0 is the input, the last
+        // step writes the output payload, the others alternate b1 / b2
+        const int K = (int)t.max_n;
+        const float* P = (const float*)(b + L.in) + (size_t)h * w;
+        const bool win = image_window_path(w);
+        for (int k = 0; k < K; ++k) {
+          const float* src = (k == 0) ? (const float*)(b + L.in) : sl.hot[k - 1].tout;
+          float* dst = (k == K - 1) ? (float*)(b + L.out + 64) : (float*)(b + ((k % 2 == 0) ? L.b1 : L.b2));
+          sl.hot[k] = HotspotArgs{src, P, dst, h, w, k == 0 ? 1 : 0, sc.hdr, JobScalars{}};
+          stage(win ? (const void*)&k_hotspot_win_f32 : (const void*)&k_hotspot_f32, to_dim3(hotspot_grid(h, w)),
+                &sl.hot[k]);
+        }
+        sl.je = JobEndArgs{sc};
+        stage((const void*)&k_job_end, dim3(1), &sl.je);
+        break;
+      }
       case SET_PIPE_SCAN_LIB_I32_I64:
         sl.jb = JobBeginArgs{sc.hdr, JobScalars{}};
         sl.je = JobEndArgs{sc};
@@ -699,6 +717,9 @@ class HipBackend : public Backend {
       case SET_PIPE_SCAN_LIB_I32_I64:
         js.n = p.t.max_n;
         sl.jb.js = js;
+        break;
+      case SET_PIPE_HOTSPOT_F32:
+        sl.hot[0].js = js;
         break;
       case SET_PIPE_SAXPY_BATCH_F32:
         sl.vb.js = js;

@@ -23,7 +23,8 @@ inline uint64_t now_ns() {
 constexpr int kMaxWorkers = 64;
 constexpr int kMaxSlots = 64;
 constexpr int kMaxTemplates = 16;
-constexpr int kMaxStages = 8;
+constexpr int kMaxStages = 40;
+constexpr int kMaxHotspotSteps = 32;  // thermal-grid template: steps per job (one kernel each)
 
 // Per-job scalar arguments.  Passed by value to the first kernel of a chain
 // (a kernel-node placeholder, Section 4.1) and written by it into the slot's

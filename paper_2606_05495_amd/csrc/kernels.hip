@@ -470,6 +470,74 @@ __global__ __launch_bounds__(kBlock) void k_sobel_thresh_win_f32(SobelArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ thermal grid step
+// T' = T + CP*P + CY*(N + S - 2T) + CX*(W + E - 2T) + CZ*(T_AMB - T), a
+// neighbour outside the grid being the cell itself.
+namespace hotspot {
+constexpr float CX = 0.1f, CY = 0.1f, CZ = 1.0f / 640.0f, CP = 0.5f, T_AMB = 300.0f;
+__device__ inline float step(float t, float p, float n, float s, float w, float e) {
+  const float lap_y = (n + s) - 2.f * t;
+  const float lap_x = (w + e) - 2.f * t;
+  return t + CP * p + CY * lap_y + CX * lap_x + CZ * (T_AMB - t);
+}
+}  // namespace hotspot
+
+// Register window as for the image stages: a lane owns 4 columns, a wave 256
+// columns x kHotWinRows rows with its rows of T (plus one above and below)
+// and of P loaded before the first result.
+__global__ __launch_bounds__(kBlock) void k_hotspot_win_f32(HotspotArgs a) {
+  constexpr int R = kHotWinRows;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  unsigned bx, by;
+  xcd_tile(bx, by);
+  if (a.first && bx == 0 && by == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
+  const int w = a.w, h = a.h, wm = w - 1, hm = h - 1;
+  const int xw = (int)bx * kWinCols;
+  const int x = xw + 4 * lane;
+  const int y0 = ((int)by * 4 + wave) * R;
+  const bool in4 = x + 3 <= wm;
+  const int hx = clampi(lane == 0 ? xw - 1 : xw + kWinCols, 0, wm);
+  float4 v[R + 2], pv[R];
+  float e[R + 2];
+#pragma unroll
+  for (int r = 0; r < R + 2; ++r) {
+    const float* row = a.tin + (size_t)clampi(y0 + r - 1, 0, hm) * w;
+    v[r] = load_row4(row, x, in4, wm);
+    e[r] = row[hx];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) pv[r] = load_row4(a.p + (size_t)clampi(y0 + r, 0, hm) * w, x, in4, wm);
+#pragma unroll
+  for (int r = 1; r <= R; ++r) {
+    const int y = y0 + r - 1;
+    float left = up1(v[r].w), right = down1(v[r].x);
+    if (lane == 0) left = e[r];
+    if (lane == 63) right = e[r];
+    const float c[6] = {left, v[r].x, v[r].y, v[r].z, v[r].w, right};
+    const float n4[4] = {v[r - 1].x, v[r - 1].y, v[r - 1].z, v[r - 1].w};
+    const float s4[4] = {v[r + 1].x, v[r + 1].y, v[r + 1].z, v[r + 1].w};
+    const float p4[4] = {pv[r - 1].x, pv[r - 1].y, pv[r - 1].z, pv[r - 1].w};
+    float o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = hotspot::step(c[j + 1], p4[j], n4[j], s4[j], c[j], c[j + 2]);
+    if (y < h && in4) *reinterpret_cast<float4*>(a.tout + (size_t)y * w + x) = make_float4(o[0], o[1], o[2], o[3]);
+  }
+}
+
+// Widths that are not a multiple of 4: one cell per thread.
+__global__ __launch_bounds__(kBlock) void k_hotspot_f32(HotspotArgs a) {
+  if (a.first && blockIdx.x == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= (int64_t)a.h * a.w) return;
+  const int y = (int)(i / a.w), x = (int)(i - (int64_t)y * a.w);
+  const int wm = a.w - 1, hm = a.h - 1;
+  const float* T = a.tin;
+  const float t = T[i];
+  const float n = T[(size_t)clampi(y - 1, 0, hm) * a.w + x], s = T[(size_t)clampi(y + 1, 0, hm) * a.w + x];
+  const float wv = T[(size_t)y * a.w + clampi(x - 1, 0, wm)], ev = T[(size_t)y * a.w + clampi(x + 1, 0, wm)];
+  a.tout[i] = hotspot::step(t, a.p[i], n, s, wv, ev);
+}
+
 // One block: fixed-order combination of the per-block count and sum.
 __global__ __launch_bounds__(kBlock) void k_sobel_final(SobelFinalArgs a) {
   __shared__ float s4f[4];

@@ -149,6 +149,21 @@ struct JobEndArgs {
 __global__ void k_job_begin(JobBeginArgs a);
 __global__ void k_job_end(JobEndArgs a);
 
+// One explicit step of the thermal grid: tout = step(tin, p).  The first
+// step of a job (first != 0) also writes the job's scalars into the slot
+// header.
+struct HotspotArgs {
+  const float* tin;
+  const float* p;
+  float* tout;
+  int h, w;
+  int first;
+  DevSlotHdr* hdr;
+  JobScalars js;
+};
+__global__ void k_hotspot_win_f32(HotspotArgs a);
+__global__ void k_hotspot_f32(HotspotArgs a);
+
 __global__ void k_box3_u8_u16(BoxArgs a);
 __global__ void k_div9_u16_u8(Div9Args a);
 __global__ void k_hist256_u8(HistArgs a);

@@ -33,6 +33,12 @@ int pipeline_validate(const set_job_template& t, std::string* why) {
     case SET_PIPE_SCAN_I32_I64:
       if (t.max_n < 1 || t.max_n > (1ull << 31)) return bad("scan template needs 1 <= max_n <= 2^31");
       break;
+    case SET_PIPE_HOTSPOT_F32:
+      if (t.width < 1 || t.height < 1) return bad("thermal-grid templates need width >= 1 and height >= 1");
+      if ((uint64_t)t.width * t.height > (1ull << 28)) return bad("grid larger than 2^28 cells");
+      if (t.width > (1u << 20) || t.height > (1u << 20)) return bad("grid side larger than 2^20");
+      if (t.max_n < 1 || t.max_n > (uint64_t)kMaxHotspotSteps) return bad("thermal-grid template needs 1 <= max_n (steps) <= 32");
+      break;
     case SET_PIPE_SCAN_LIB_I32_I64:
       if (t.max_n < 1 || t.max_n > (1ull << 31)) return bad("scan template needs 1 <= max_n <= 2^31");
       if (t.flags & SET_TF_SCAN_LOW32) return bad("the library scan template writes the full int64 output");
@@ -139,6 +145,22 @@ static SlotLayout layout_of(const set_job_template& t) {
       off = up(off + L.scratch_bytes);
       break;
     }
+    case SET_PIPE_HOTSPOT_F32: {
+      const uint64_t npix = (uint64_t)t.width * t.height;
+      L.in = off;  // T0 then P
+      L.in_cap = 8 * npix;
+      off = up(off + 8 * npix);
+      L.out = off;  // header + T_K
+      L.out_cap = 64 + 4 * npix;
+      off = up(off + L.out_cap);
+      L.b1 = off;  // ping-pong buffers of the intermediate steps
+      off = up(off + 4 * npix);
+      L.b2 = off;
+      off = up(off + 4 * npix);
+      L.scratch = off;
+      L.scratch_bytes = 0;
+      break;
+    }
     case SET_PIPE_SCAN_LIB_I32_I64: {
       // the library's temporary storage is a separate per-slot workspace
       const uint64_t n = t.max_n;
@@ -183,6 +205,8 @@ uint64_t pipeline_in_bytes(const set_job_template& t, uint64_t n) {
       return (uint64_t)t.width * t.height;
     case SET_PIPE_GAUSS_SOBEL_F32:
       return 4ull * t.width * t.height;
+    case SET_PIPE_HOTSPOT_F32:
+      return 8ull * t.width * t.height;
     case SET_PIPE_SAXPY_TANH_SUM_F32:
       return 0;
     case SET_PIPE_SCAN_I32_I64:
@@ -205,6 +229,8 @@ uint64_t pipeline_out_bytes(const set_job_template& t, uint64_t n) {
       return 64 + ((t.flags & SET_TF_SCAN_LOW32) ? 4ull : 8ull) * (n ? n : t.max_n);
     case SET_PIPE_SCAN_LIB_I32_I64:
       return 64 + 8ull * t.max_n;
+    case SET_PIPE_HOTSPOT_F32:
+      return 64 + 4ull * t.width * t.height;
     case SET_PIPE_SAXPY_BATCH_F32:
       return 64 + 4ull * n;
   }
@@ -278,6 +304,11 @@ int pipeline_sizes(const set_job_template& t, TemplateSizes* out) {
       // the streamed bytes depend on the batch (8 bytes per element of every job)
       stage("vec_batch_tiles", 64 + 48ull * t.batch_max + 4ull * t.tiles_max);
       stage("vec_batch_final", 64 + 48ull * t.batch_max + 4ull * t.tiles_max + 4ull * t.batch_max);
+      break;
+    case SET_PIPE_HOTSPOT_F32:
+      // each step reads T and P and writes T'
+      for (uint64_t k = 0; k < t.max_n; ++k) stage("hotspot_step_f32", 12 * npix);
+      stage("job_end", 64 + 64);
       break;
     case SET_PIPE_SCAN_LIB_I32_I64:
       stage("job_begin", 64);

@@ -73,6 +73,14 @@ inline Grid3 sobel_grid(int h, int w) {
   if (image_window_path(w)) return window_grid(h, w, kSobelWinRows);
   return {(unsigned)((w + kSobelTW - 1) / kSobelTW), (unsigned)((h + kSobelTH - 1) / kSobelTH), 1u};
 }
+// Thermal-grid step: the register window (4 columns x kHotWinRows rows per
+// lane) for widths that are multiples of 4, one pixel per thread otherwise.
+constexpr int kHotWinRows = 2;
+inline Grid3 hotspot_grid(int h, int w) {
+  if (image_window_path(w)) return window_grid(h, w, kHotWinRows);
+  const uint64_t n = (uint64_t)h * w;
+  return {(unsigned)((n + kBlock - 1) / kBlock), 1u, 1u};
+}
 // Vector job: blocks for length n.  Deterministic in n, so the reduction
 // order of a job depends only on its length.
 SETRT_HD inline unsigned vec_blocks(uint64_t n) {

@@ -19,6 +19,7 @@ PIPELINES = {
     "scan": A.SET_PIPE_SCAN_I32_I64,
     "saxpy_batch": A.SET_PIPE_SAXPY_BATCH_F32,
     "scan_lib": A.SET_PIPE_SCAN_LIB_I32_I64,
+    "hotspot": A.SET_PIPE_HOTSPOT_F32,
 }
 
 

@@ -37,6 +37,7 @@ CFG_IMAGE = 1
 CFG_VECTOR = 2
 CFG_SCAN = 3
 CFG_SERVE = 4
+CFG_HOTSPOT = 5
 
 IMAGE_POOL = 61
 SCAN_POOL = 31
@@ -144,6 +145,17 @@ def serve_image_pool(seed: int, side: int, count: int = IMAGE_POOL, out=None) ->
 def scan_input(seed: int, k: int, n: int = 1 << 21) -> np.ndarray:
     """cfg-3 input k: int32 uniform on [-2**20, 2**20]."""
     return as_i32_range(draws(stream_key(seed, CFG_SCAN, k), n), -(1 << 20), 1 << 20)
+
+
+def hotspot_input(seed: int, k: int, h: int = 256, w: int = 256):
+    """Thermal-grid input k: temperatures T0 uniform on [310, 340) K and a
+    skewed power map P = 2 u^4 (u uniform on [0, 1)): a few hot cells on a cool
+    background.  Returns (T0, P), float32 h x w each."""
+    z = draws(stream_key(seed, CFG_HOTSPOT, k), 2 * h * w)
+    t0 = (310.0 + 30.0 * as_unit24(z[: h * w])).astype(np.float32).reshape(h, w)
+    u = as_unit24(z[h * w:]).astype(np.float64)
+    p = (2.0 * u ** 4).astype(np.float32).reshape(h, w)
+    return t0, p
 
 
 def scan_pool(seed: int, count: int = SCAN_POOL, n: int = 1 << 21, out=None) -> np.ndarray:

@@ -691,3 +691,69 @@ def test_library_scan_stage_timing(torch_gpu):
     assert names == ["job_begin", "scan_lib_rocprim", "job_end"]
     assert all(u > 0 for u in us)
     assert np.array_equal(nout[64:].view(np.int64), oracle.scan(synth.scan_input(1, 0, 1 << 21)))
+
+
+# ------------------------------------------------------------------ thermal grid (iterative stencil)
+def _run_hotspot(mode, grids, steps, workers=4, slots=4, **kw):
+    h, w = grids[0][0].shape
+    ctx = Context(mode=mode, workers=workers, slots=slots, **kw)
+    tid = ctx.define("hotspot", width=w, height=h, max_n=steps)
+    ib, ob = ctx.in_bytes(tid), ctx.out_bytes(tid)
+    assert ib == 8 * h * w and ob == 64 + 4 * h * w
+    istride, ostride = _up64(ib), _up64(ob)
+    tin, nin = pinned(istride * len(grids))
+    tout, nout = pinned(ostride * len(grids))
+    for i, (t0, p) in enumerate(grids):
+        nin[i * istride:i * istride + ib].view(np.float32)[:] = np.concatenate([t0.ravel(), p.ravel()])
+    arr = ctx.job_array(len(grids))
+    arr["host_in"] = tin.data_ptr() + np.arange(len(grids), dtype=np.uint64) * istride
+    arr["in_bytes"] = ib
+    arr["host_out"] = tout.data_ptr() + np.arange(len(grids), dtype=np.uint64) * ostride
+    arr["out_bytes"] = ob
+    first = ctx.submit_many(tid, arr)
+    ctx.drain()
+    ctx.close()
+    outs = []
+    for i in range(len(grids)):
+        o = nout[i * ostride:(i + 1) * ostride]
+        _check_header(o, first + i)
+        outs.append(o[64:64 + 4 * h * w].view(np.float32).reshape(h, w).copy())
+    return outs
+
+
+HOT_SHAPES = [(1, 1), (1, 4), (3, 8), (5, 5), (33, 17), (17, 260), (64, 64), (70, 516), (256, 256)]
+
+
+@pytest.mark.parametrize("mode", ["sync", "set"])
+@pytest.mark.parametrize("shape", HOT_SHAPES)
+def test_hotspot_parity(torch_gpu, mode, shape):
+    _say("hotspot", mode, shape)
+    h, w = shape
+    grids = [synth.hotspot_input(0, k, h, w) for k in range(3)]
+    for steps in (1, 7):
+        outs = _run_hotspot(mode, grids, steps)
+        for (t0, p), o in zip(grids, outs):
+            ref = oracle.hotspot(t0, p, steps)
+            assert np.max(np.abs(o - ref)) <= oracle.hotspot_tolerance(ref, steps), (shape, steps)
+
+
+@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "queue", "set"])
+def test_hotspot_workload(torch_gpu, mode):
+    """256x256 grids, 16 steps per job, 8 workers: every mode, identical results for identical inputs."""
+    _say("hotspot workload", mode)
+    grids = [synth.hotspot_input(0, k) for k in range(5)]
+    outs = _run_hotspot(mode, grids * 4, 16, workers=8, slots=8, callback="host_flag", dispatchers=4)
+    for i, o in enumerate(outs):
+        t0, p = grids[i % 5]
+        if i < 5:
+            ref = oracle.hotspot(t0, p, 16)
+            assert np.max(np.abs(o - ref)) <= oracle.hotspot_tolerance(ref, 16)
+        assert np.array_equal(o, outs[i % 5])
+
+
+def test_hotspot_pins_on_gpu(torch_gpu):
+    """Ambient grid without power stays exactly ambient; 32 steps (the most a template allows)."""
+    h, w = 40, 72
+    amb = (np.full((h, w), 300.0, np.float32), np.zeros((h, w), np.float32))
+    o = _run_hotspot("set", [amb], 32)[0]
+    assert np.all(o == np.float32(300.0))
