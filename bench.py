@@ -407,7 +407,7 @@ def bench_hotspot(args, torch):
     R = 256  # output ring
     tout, nout = pinned(ostride * R)
     out = {}
-    for mode in ("set", "batch", "sync", "queue"):
+    for mode in ((args.only,) if args.only else ("set", "batch", "sync", "queue")):
         c = Context(mode=mode, workers=args.workers, slots=args.slots if mode == "set" else 1,
                     batch_size=args.batch if mode == "batch" else 0, callback=args.callback,
                     dispatchers=args.dispatchers)
@@ -436,6 +436,9 @@ def bench_hotspot(args, torch):
             ok &= bool(np.max(np.abs(o - ref)) <= oracle.hotspot_tolerance(ref, K))
         out[mode] = {"jobs_per_s": round(J / dt, 1), "verified": ok}
         log("hotspot %s %.0f jobs/s" % (mode, J / dt))
+    if args.only:
+        print(json.dumps({"mode": args.only, "workload": "hotspot", **out[args.only]}), flush=True)
+        return
     v = out["set"]["jobs_per_s"]
     line = {"metric": METRIC, "workload": "thermal grid: %d jobs, %dx%d float32, %d steps per job" % (J, h, w, K),
             "value": v, "unit": "jobs/s", "n_gpus": 1, "dtype": "f32", "data": "synthetic",

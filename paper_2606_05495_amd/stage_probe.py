@@ -31,7 +31,8 @@ def _copy_us(torch, nbytes, reps):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--pipeline", default="gauss_sobel", choices=["gauss_sobel", "box_hist", "scan"])
+    ap.add_argument("--pipeline", default="gauss_sobel", choices=["gauss_sobel", "box_hist", "scan", "hotspot"])
+    ap.add_argument("--steps", type=int, default=4, help="hotspot: steps per job")
     ap.add_argument("--side", type=int, default=1024)
     ap.add_argument("--n", type=int, default=1 << 21)
     ap.add_argument("--reps", type=int, default=50)
@@ -45,6 +46,10 @@ def main():
     if args.pipeline == "scan":
         tid = ctx.define("scan", max_n=args.n)
         data = synth.scan_input(0, 0, args.n).view(np.uint8)
+    elif args.pipeline == "hotspot":
+        tid = ctx.define("hotspot", width=args.side, height=args.side, max_n=args.steps)
+        t0, p = synth.hotspot_input(0, 0, args.side, args.side)
+        data = np.concatenate([t0.ravel(), p.ravel()]).view(np.uint8)
     elif args.pipeline == "box_hist":
         tid = ctx.define("box_hist", width=args.side, height=args.side)
         data = synth.box_image(0, 0, args.side, args.side).ravel()
