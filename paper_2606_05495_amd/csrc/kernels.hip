@@ -74,6 +74,12 @@ __device__ inline uint32_t block_sum_u32(uint32_t v, uint32_t* s4) {
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// The hardware square root (v_sqrt_f32, within 1 ulp for normal inputs)
+// instead of the correctly rounded library sequence, which costs about 15
+// instructions per call; the Sobel magnitudes here are normal numbers and
+// their parity bound is 1e-5 relative.
+__device__ inline float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // Fill an LDS tile of N elements (row-major, LW per row, stored with pitch
 // P) from global memory: every thread issues all of its loads before its
 // first LDS write, so one memory latency covers the whole tile.  get(r, c)
@@ -279,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_sobel_thresh_f32(SobelArgs a) {
       const float p20 = t[r + 2][c], p21 = t[r + 2][c + 1], p22 = t[r + 2][c + 2];
       const float gx = (p02 + 2.f * p12 + p22) - (p00 + 2.f * p10 + p20);
       const float gy = (p20 + 2.f * p21 + p22) - (p00 + 2.f * p01 + p02);
-      const float mag = sqrtf(gx * gx + gy * gy);
+      const float mag = sqrt_hw(gx * gx + gy * gy);
       const uint32_t on = mag > a.thr ? 1u : 0u;
       a.mask[(size_t)y * a.w + x] = (uint8_t)on;
       cnt += on;
@@ -359,7 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_gauss5_win_f32(GaussArgs a) {
     e1[r] = row[hx1];
   }
   const float g0 = a.g0, g1 = a.g1, g2 = a.g2;
-  float hz[5][4];  // horizontal results of the last 5 input rows (ring)
+  float hz[R + 4][4];  // horizontal pass of every input row of the window
 #pragma unroll
   for (int r = 0; r < R + 4; ++r) {
     float l2 = up1(v[r].z), l1 = up1(v[r].w);
@@ -380,22 +386,23 @@ __global__ __launch_bounds__(kBlock) void k_gauss5_win_f32(GaussArgs a) {
       acc = fmaf(g2, c[j + 2], acc);
       acc = fmaf(g1, c[j + 3], acc);
       acc = fmaf(g0, c[j + 4], acc);
-      hz[r % 5][j] = acc;
+      hz[r][j] = acc;
     }
-    if (r >= 4) {
-      const int y = y0 + r - 4;
-      float o[4];
+  }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        float acc = g0 * hz[(r - 4) % 5][j];
-        acc = fmaf(g1, hz[(r - 3) % 5][j], acc);
-        acc = fmaf(g2, hz[(r - 2) % 5][j], acc);
-        acc = fmaf(g1, hz[(r - 1) % 5][j], acc);
-        acc = fmaf(g0, hz[r % 5][j], acc);
-        o[j] = acc;
-      }
-      if (y < h && in4) *reinterpret_cast<float4*>(a.out + (size_t)y * w + x) = make_float4(o[0], o[1], o[2], o[3]);
+  for (int r = 0; r < R; ++r) {
+    const int y = y0 + r;
+    float o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float acc = g0 * hz[r][j];
+      acc = fmaf(g1, hz[r + 1][j], acc);
+      acc = fmaf(g2, hz[r + 2][j], acc);
+      acc = fmaf(g1, hz[r + 3][j], acc);
+      acc = fmaf(g0, hz[r + 4][j], acc);
+      o[j] = acc;
     }
+    if (y < h && in4) *reinterpret_cast<float4*>(a.out + (size_t)y * w + x) = make_float4(o[0], o[1], o[2], o[3]);
   }
 }
 
@@ -427,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_sobel_thresh_win_f32(SobelArgs a) {
   const float thr = a.thr;
   float sum = 0.f;
   uint32_t cnt = 0;
-  float sm[3][4], df[3][4];
+  float sm[R + 2][4], df[R + 2][4];  // per input row: smoothing and difference along x
 #pragma unroll
   for (int r = 0; r < R + 2; ++r) {
     float left = __shfl_up(v[r].w, 1, 64), right = __shfl_down(v[r].x, 1, 64);
@@ -436,29 +443,30 @@ __global__ __launch_bounds__(kBlock) void k_sobel_thresh_win_f32(SobelArgs a) {
     const float c[6] = {left, v[r].x, v[r].y, v[r].z, v[r].w, right};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      sm[r % 3][j] = (c[j] + 2.f * c[j + 1]) + c[j + 2];
-      df[r % 3][j] = c[j + 2] - c[j];
+      sm[r][j] = (c[j] + 2.f * c[j + 1]) + c[j + 2];
+      df[r][j] = c[j + 2] - c[j];
     }
-    if (r >= 2) {
-      const int y = y0 + r - 2;
-      uint32_t packed = 0;
-      float rs = 0.f;
-      uint32_t rc = 0;
+  }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float gx = (df[(r - 2) % 3][j] + 2.f * df[(r - 1) % 3][j]) + df[r % 3][j];
-        const float gy = sm[r % 3][j] - sm[(r - 2) % 3][j];
-        const float mag = sqrtf(gx * gx + gy * gy);
-        const uint32_t on = mag > thr ? 1u : 0u;
-        packed |= on << (8 * j);
-        rc += on;
-        rs += mag;
-      }
-      if (y < h && in4) {
-        *reinterpret_cast<uint32_t*>(a.mask + (size_t)y * w + x) = packed;
-        cnt += rc;
-        sum += rs;
-      }
+  for (int r = 0; r < R; ++r) {
+    const int y = y0 + r;
+    uint32_t packed = 0;
+    float rs = 0.f;
+    uint32_t rc = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float gx = (df[r][j] + 2.f * df[r + 1][j]) + df[r + 2][j];
+      const float gy = sm[r + 2][j] - sm[r][j];
+      const float mag = sqrt_hw(gx * gx + gy * gy);
+      const uint32_t on = mag > thr ? 1u : 0u;
+      packed |= on << (8 * j);
+      rc += on;
+      rs += mag;
+    }
+    if (y < h && in4) {
+      *reinterpret_cast<uint32_t*>(a.mask + (size_t)y * w + x) = packed;
+      cnt += rc;
+      sum += rs;
     }
   }
   const unsigned b = by * gridDim.x + bx;
