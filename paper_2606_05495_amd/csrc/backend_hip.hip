@@ -621,8 +621,10 @@ class HipBackend : public Backend {
         sl.sobelf = SobelFinalArgs{(const uint32_t*)(b + L.scratch), (const float*)(b + L.scratch + q), nb,
                                    (uint32_t*)(b + L.out + 64), (float*)(b + L.out + 68), sc};
         const bool win = image_window_path(w);
-        stage(win ? (const void*)&k_gauss5_win_f32 : (const void*)&k_gauss5_f32, to_dim3(gauss_grid(h, w)),
-              &sl.gauss);
+        const void* gk = !win                       ? (const void*)&k_gauss5_f32
+                         : gauss_win_rows(h, w) == 2 ? (const void*)&k_gauss5_win_f32<2>
+                                                     : (const void*)&k_gauss5_win_f32<4>;
+        stage(gk, to_dim3(gauss_grid(h, w)), &sl.gauss);
         stage(win ? (const void*)&k_sobel_thresh_win_f32 : (const void*)&k_sobel_thresh_f32, to_dim3(sg), &sl.sobel);
         stage((const void*)&k_sobel_final, dim3(1), &sl.sobelf);
         break;

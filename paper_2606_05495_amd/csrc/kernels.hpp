@@ -169,6 +169,7 @@ __global__ void k_div9_u16_u8(Div9Args a);
 __global__ void k_hist256_u8(HistArgs a);
 __global__ void k_hist256_final(HistFinalArgs a);
 __global__ void k_gauss5_f32(GaussArgs a);
+template <int R>
 __global__ void k_gauss5_win_f32(GaussArgs a);
 __global__ void k_sobel_thresh_f32(SobelArgs a);
 __global__ void k_sobel_thresh_win_f32(SobelArgs a);

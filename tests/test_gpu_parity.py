@@ -199,6 +199,15 @@ def test_gauss_sobel_largest_serving_size(torch_gpu):
     assert np.array_equal(outs[0][64:72], outs[2][64:72])
 
 
+def test_gauss_sobel_above_2048sq_per_pixel(torch_gpu):
+    """2056x2052 (more than 2048^2 pixels: the Gaussian's 4-row window; ragged
+    against the 256-column and 16-row blocks), every pixel of blur and mask."""
+    _say("gauss_sobel 2056x2052 per pixel")
+    imgs = [synth.normal_image(4, 0, 2056, 2052)]
+    outs, _ = _run_images("set", "gauss_sobel", imgs, np.float32, workers=1, slots=1)
+    _check_gauss(imgs[0], outs[0])
+
+
 # ------------------------------------------------------------------ vector jobs
 @pytest.fixture(scope="module")
 def vec_pools(torch_gpu):
