@@ -223,7 +223,13 @@ typedef struct set_config {
      * at num_workers.  ROCm's graph launch is host-bound (about 16 us per
      * launch) but scales across threads. */
     int32_t dispatch_threads;
-    int32_t reserved_cfg;
+    /* SET_COPY_ASYNC_IN templates, every mode: the number C of library-owned
+     * streams that carry the input copies (worker w's on stream w % C; the
+     * worker's stream waits on that copy's event before the graph).  At most
+     * C DMA copies are then in flight whatever the worker count; on a PCIe
+     * Gen5 link 4 MiB copies are fastest with 2 to 4 in flight.  0 = each
+     * input copy on its worker's own stream.  0..64, capped at num_workers. */
+    int32_t input_copy_streams;
 } set_config;
 
 typedef struct set_job_template {

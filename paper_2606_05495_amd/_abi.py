@@ -69,7 +69,7 @@ class set_config(ctypes.Structure):
         ("fake_fail_after", ctypes.c_int32),
         ("fake_reorder_callbacks", ctypes.c_int32),
         ("dispatch_threads", ctypes.c_int32),
-        ("reserved_cfg", ctypes.c_int32),
+        ("input_copy_streams", ctypes.c_int32),
     ]
 
 

@@ -80,6 +80,7 @@ struct Slot {
   hipGraphExec_t exec = nullptr;
   ChainNodes nodes;
   hipEvent_t ev = nullptr;
+  hipEvent_t in_ev = nullptr;  // end of the input copy on an input-copy stream
   CbCtx cb{};
   const void* host_in = nullptr;
   uint64_t in_bytes = 0;
@@ -173,6 +174,8 @@ class HipBackend : public Backend {
       own_streams_ = true;
       for (int i = 0; i < b_; ++i) HIPCK(hipStreamCreateWithFlags(&streams_[i], hipStreamNonBlocking));
     }
+    copy_streams_.resize(std::min(cfg.input_copy_streams, b_));
+    for (hipStream_t& cs : copy_streams_) HIPCK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     if (cfg.mode == SET_MODE_SET && cfg.callback_mode == SET_CB_EVENT_CHAIN) {
       cb_streams_.resize(b_);
       for (int i = 0; i < b_; ++i) HIPCK(hipStreamCreateWithFlags(&cb_streams_[i], hipStreamNonBlocking));
@@ -243,6 +246,8 @@ class HipBackend : public Backend {
         }
         if (p.words) sl.flag = DoneFlagArgs{reinterpret_cast<const DevSlotHdr*>(sl.base + p.L.hdr),
                                             p.words + ((size_t)w * d_ + s) * 8};
+        if (!copy_streams_.empty() && in_ahead(t) && (cfg_.mode == SET_MODE_SET || s == 0))
+          HIPCK(hipEventCreateWithFlags(&sl.in_ev, hipEventDisableTiming));
         const uint64_t ch = canary_value(id, w, s, 0), ct = canary_value(id, w, s, 1);
         HIPCK(hipMemcpy(sl.base + p.L.hdr, &ch, 8, hipMemcpyHostToDevice));
         HIPCK(hipMemcpy(sl.base + p.L.tail, &ct, 8, hipMemcpyHostToDevice));
@@ -289,7 +294,7 @@ class HipBackend : public Backend {
     hipStream_t st = streams_[w];
     sl.cb = CbCtx{j, done, ctx};
     sl.flag_seq = j->seq;
-    HIPCK(input_ahead(p, sl, st));
+    HIPCK(input_ahead(p, sl, st, w));
     HIPCK(hipGraphLaunch(sl.exec, st));
     switch (cfg_.callback_mode) {
       case SET_CB_EVENT_CHAIN:
@@ -322,7 +327,7 @@ class HipBackend : public Backend {
     Pipe& p = *pipes_[j->tmpl];
     Slot& sl = p.slots[(size_t)j->worker * d_ + j->slot];
     hipStream_t st = streams_[j->worker];
-    HIPCK(input_ahead(p, sl, st));
+    HIPCK(input_ahead(p, sl, st, j->worker));
     HIPCK(hipGraphLaunch(sl.exec, st));
     HIPCK(hipEventRecord(sl.ev, st));
     return SET_OK;
@@ -354,6 +359,8 @@ class HipBackend : public Backend {
       if (in_by_kernel(p.t)) {
         sl.h2d_copy = CopyArgs{sl.host_in, sl.base + p.L.in, sl.in_bytes};
         HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(kCopyBlocks), dim3(kBlock), sl.h2d_argv, 0, st));
+      } else if (in_ahead(p.t)) {
+        HIPCK(input_ahead(p, sl, st, si));
       } else {
         HIPCK(hipMemcpyAsync(sl.base + p.L.in, sl.host_in, sl.in_bytes, hipMemcpyHostToDevice, st));
       }
@@ -382,7 +389,7 @@ class HipBackend : public Backend {
     int rc = update_exec(p, sl, sl.exec, sl.nodes, err);
     if (rc != SET_OK) return rc;
     hipStream_t st = streams_[si];
-    HIPCK(input_ahead(p, sl, st));
+    HIPCK(input_ahead(p, sl, st, si));
     HIPCK(hipGraphLaunch(sl.exec, st));
     const uint64_t t0 = now_ns();
     HIPCK(hipStreamSynchronize(st));
@@ -416,7 +423,7 @@ class HipBackend : public Backend {
       set_scalars(p, sl, jobs[i]);
       int rc = update_exec(p, sl, bg.ex, bg.chains[i], err);
       if (rc != SET_OK) return rc;
-      HIPCK(input_ahead(p, sl, streams_[0]));
+      HIPCK(input_ahead(p, sl, streams_[0], i));
     }
     HIPCK(hipGraphLaunch(bg.ex, streams_[0]));
     const uint64_t t0 = now_ns();
@@ -490,6 +497,7 @@ class HipBackend : public Backend {
         if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
         if (sl.graph) (void)hipGraphDestroy(sl.graph);
         if (sl.ev) (void)hipEventDestroy(sl.ev);
+        if (sl.in_ev) (void)hipEventDestroy(sl.in_ev);
       }
       for (BatchGraph& bg : p.batch) {
         if (bg.ex) (void)hipGraphExecDestroy(bg.ex);
@@ -503,6 +511,8 @@ class HipBackend : public Backend {
     pipes_.clear();
     for (hipStream_t s : cb_streams_) (void)hipStreamDestroy(s);
     cb_streams_.clear();
+    for (hipStream_t s : copy_streams_) (void)hipStreamDestroy(s);
+    copy_streams_.clear();
     if (own_streams_)
       for (hipStream_t s : streams_) (void)hipStreamDestroy(s);
     streams_.clear();
@@ -764,10 +774,21 @@ class HipBackend : public Backend {
                     reinterpret_cast<int64_t*>(sl.base + p.L.out + 64), (size_t)p.t.max_n, st);
   }
 
-  // SET_COPY_ASYNC_IN: the job's input copy, stream-ordered ahead of its graph.
-  hipError_t input_ahead(Pipe& p, Slot& sl, hipStream_t st) {
+  // SET_COPY_ASYNC_IN: the job's input copy, ordered ahead of its graph on
+  // stream st.  Without input-copy streams it runs on st itself.  With them it
+  // runs on input-copy stream w % C, and st waits on its event: at most C DMA
+  // copies are then in flight, however many workers there are.  The slot was
+  // released before this job was bound to it, so the copy cannot overwrite
+  // an input that a running graph still reads.
+  hipError_t input_ahead(Pipe& p, Slot& sl, hipStream_t st, int w) {
     if (!in_ahead(p.t) || sl.in_bytes == 0) return hipSuccess;
-    return hipMemcpyAsync(sl.base + p.L.in, sl.host_in, sl.in_bytes, hipMemcpyHostToDevice, st);
+    if (copy_streams_.empty() || !sl.in_ev)
+      return hipMemcpyAsync(sl.base + p.L.in, sl.host_in, sl.in_bytes, hipMemcpyHostToDevice, st);
+    hipStream_t cs = copy_streams_[(size_t)w % copy_streams_.size()];
+    hipError_t e = hipMemcpyAsync(sl.base + p.L.in, sl.host_in, sl.in_bytes, hipMemcpyHostToDevice, cs);
+    if (e == hipSuccess) e = hipEventRecord(sl.in_ev, cs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, sl.in_ev, 0);
+    return e;
   }
 
   int add_chain(Pipe& p, Slot& sl, hipGraph_t g, ChainNodes* cn, std::string* err) {
@@ -938,6 +959,7 @@ class HipBackend : public Backend {
   int b_ = 0, d_ = 0, dev_ = -1;
   bool own_streams_ = false, down_ = false;
   std::vector<hipStream_t> streams_, cb_streams_;
+  std::vector<hipStream_t> copy_streams_;  // input-copy streams (set_config.input_copy_streams)
   std::vector<std::unique_ptr<Pipe>> pipes_;
   std::atomic<uint64_t> sync_ns_{0};
   // event polling

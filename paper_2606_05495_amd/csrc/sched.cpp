@@ -1295,6 +1295,7 @@ int set_ctx_create(const set_config* cfg, set_ctx** out) {
       cfg->callback_mode > SET_CB_HOST_FLAG || cfg->submit_policy < 0 || cfg->submit_policy > SET_SUBMIT_SKEW0 ||
       cfg->inflight_per_worker < 0 || cfg->queue_capacity < 0 || cfg->spin_us < 0 || cfg->staging_capacity < 0 ||
       cfg->dispatch_threads < 0 || cfg->dispatch_threads > setrt::kMaxWorkers ||
+      cfg->input_copy_streams < 0 || cfg->input_copy_streams > setrt::kMaxWorkers ||
       (cfg->backend != SET_BACKEND_HIP && cfg->backend != SET_BACKEND_FAKE)) {
     setrt::g_create_error = "invalid configuration";
     return SET_EINVAL;

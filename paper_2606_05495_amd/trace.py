@@ -7,6 +7,9 @@ Definitions (the paper gives prose definitions; these are the readings):
   timeline).  Kernels of all streams are merged by start time; gap_k =
   max(0, start_{k+1} - max_{i<=k} end_i).  The headline is the mean over all
   k (zeros included); the mean of the positive gaps is reported beside it.
+  The same gap taken over kernels and DMA copies merged (mean_gap) counts a
+  running copy as GPU work; it equals the kernel gap when every copy is a
+  kernel, and it is the figure comparable across copy mechanisms.
 * GPU-idle fraction -- 1 - |union of kernel and copy intervals| / span, the
   reading of the scheduling-overhead fraction t_schedule / T_measured
   (Section 5.3 with Eq. 4): T_measured is the span of the timeline and
@@ -68,7 +71,9 @@ def timeline_metrics(kernels: Sequence[Interval], copies_h2d: Sequence[Interval]
     busy = union_length(allv)
     gaps = kernel_gaps(kernels)
     pos = [g for g in gaps if g > 0]
+    ogaps = kernel_gaps(allv)
     out = {
+        "mean_gap": (sum(ogaps) / len(ogaps)) if ogaps else 0.0,
         "span": span,
         "busy": busy,
         "gpu_idle_fraction": (1.0 - busy / span) if span > 0 else 0.0,
@@ -180,9 +185,11 @@ def _col(row, *names):
     raise KeyError(names)
 
 
-def load_rocprof(dirpath: str, kernel_filter=None):
+def load_rocprof(dirpath: str, kernel_filter=None, copy_streams=None):
     """Kernel and copy intervals (ns) from rocprofv3 --kernel-trace
-    --memory-copy-trace --output-format csv output under dirpath."""
+    --memory-copy-trace --output-format csv output under dirpath.  If
+    copy_streams is a dict, it receives the stream of every DMA copy
+    ({"h2d": [...], "d2h": [...]}, in the order of the returned intervals)."""
     kfiles = glob.glob(os.path.join(dirpath, "**", "*kernel_trace.csv"), recursive=True)
     cfiles = glob.glob(os.path.join(dirpath, "**", "*memory_copy_trace.csv"), recursive=True)
     kernels, names, streams = [], [], []
@@ -197,26 +204,39 @@ def load_rocprof(dirpath: str, kernel_filter=None):
                 names.append(name)
                 streams.append(row.get("Stream_Id") or row.get("Queue_Id") or "0")
     h2d, d2h = [], []
+    cs = {"h2d": [], "d2h": []}
     for f in cfiles:
         with open(f) as fh:
             for row in csv.DictReader(fh):
                 d = _col(row, "Direction", "Kind", "Operation")
                 iv = (float(_col(row, "Start_Timestamp", "BeginNs")), float(_col(row, "End_Timestamp", "EndNs")))
+                sid = row.get("Stream_Id") or "0"
                 if "HOST_TO_DEVICE" in d.upper() or "H2D" in d.upper():
                     h2d.append(iv)
+                    cs["h2d"].append(sid)
                 elif "DEVICE_TO_HOST" in d.upper() or "D2H" in d.upper():
                     d2h.append(iv)
+                    cs["d2h"].append(sid)
+    if copy_streams is not None:
+        copy_streams.update(cs)
     return kernels, names, h2d, d2h, streams
 
 
 def analyze_dir(dirpath: str, batch: int = 0) -> dict:
+    cs = {}
     kernels, names, h2d, d2h, streams = load_rocprof(
-        dirpath, kernel_filter=lambda n: "setrt" in n or "copyBuffer" in n)
+        dirpath, kernel_filter=lambda n: "setrt" in n or "copyBuffer" in n, copy_streams=cs)
     m = timeline_metrics(kernels, h2d, d2h)
-    m.update(stream_gaps(kernels, streams, names))
+    # DMA copies join their stream's sequence (as "dma_copy_*"), so a job whose
+    # input went by DMA still reads as [input copy, stages, output copy]; the
+    # kernel gap above stays over kernels only.
+    ev = kernels + h2d + d2h
+    ev_streams = streams + cs.get("h2d", []) + cs.get("d2h", [])
+    ev_names = names + ["dma_copy_h2d"] * len(h2d) + ["dma_copy_d2h"] * len(d2h)
+    m.update(stream_gaps(ev, ev_streams, ev_names))
     m["eq_terms"] = {k: (v / 1e3 if (v is not None and k != "jobs") else v)
-                     for k, v in eq_terms(kernels, streams, names).items()}
-    us_keys = ("span", "busy", "t_schedule", "mean_kernel_gap", "mean_positive_kernel_gap", "mean_stream_gap",
+                     for k, v in eq_terms(ev, ev_streams, ev_names).items()}
+    us_keys = ("span", "busy", "t_schedule", "mean_gap", "mean_kernel_gap", "mean_positive_kernel_gap", "mean_stream_gap",
                "mean_intra_job_gap", "mean_job_boundary_gap")
     m = {k: (v / 1e3 if k in us_keys and v is not None else v) for k, v in m.items()}  # ns -> us
     m["unit"] = "us"
@@ -293,7 +313,8 @@ def timeline_record(summaries: dict, command: str) -> dict:
     for mode, path in summaries.items():
         with open(path) as fh:
             t = json.load(fh)["timeline"]
-        modes[mode] = {k: t.get(k) for k in ("mean_kernel_gap", "mean_positive_kernel_gap", "gpu_idle_fraction",
+        modes[mode] = {k: t.get(k) for k in ("mean_gap", "mean_kernel_gap", "mean_positive_kernel_gap", "gpu_idle_fraction",
+                                             "compute_idle_fraction", "h2d_idle_fraction", "h2d_copies",
                                              "mean_stream_gap", "mean_intra_job_gap", "mean_job_boundary_gap",
                                              "span", "kernels", "mean_inter_batch_us")}
     return {"csrc_sha256": csrc_digest(), "command": command, "unit": "us", "modes": modes}

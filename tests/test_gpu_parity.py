@@ -669,6 +669,32 @@ def test_async_input_copy_all_modes(torch_gpu, vec_pools, mode):
             assert abs(res[i] - S) <= oracle.vec_tolerance(S, E)
 
 
+@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "queue", "set"])
+@pytest.mark.parametrize("copy_streams", [1, 3])
+def test_async_input_copy_streams(torch_gpu, mode, copy_streams):
+    """Input copies on library-owned copy streams (worker w on stream w % C, 3 of them not dividing the 8
+    workers): every job still reads its own input, with slots reused many times over."""
+    _say("input copy streams", mode, copy_streams)
+    imgs = [synth.box_image(1, j, 64, 96) for j in range(40)]
+    outs, _ = _run_images(mode, "box_hist", imgs, np.uint8, workers=8, slots=2, flags=0, copy="async_in",
+                          input_copy_streams=copy_streams, callback="host_flag", dispatchers=2)
+    for img, o in zip(imgs, outs):
+        assert np.array_equal(o[64:64 + 1024].view(np.uint32), oracle.box_hist(img)[2])
+    big = [synth.normal_image(1, k) for k in range(3)]
+    outs, _ = _run_images(mode, "gauss_sobel", big * 4, np.float32, workers=8, slots=2, flags=0, copy="async_in",
+                          input_copy_streams=copy_streams)
+    for k, o in enumerate(outs):
+        ref = oracle.gauss_sobel(big[k % 3], want_images=False)
+        assert abs(int(o[64:68].view(np.uint32)[0]) - ref["count"]) <= ref["band"]
+        assert abs(float(o[68:72].view(np.float32)[0]) - ref["sum"]) <= 1e-5 * abs(ref["sum"])
+    for k in range(3):
+        assert np.array_equal(outs[k][64:72], outs[k + 9][64:72])
+    rng = np.random.default_rng(13)
+    ins = [rng.integers(-(1 << 20), (1 << 20) + 1, n).astype(np.int32) for n in (3, 4097, 1 << 20)] * 3
+    for v, r in zip(ins, _run_scan(mode, ins, max_n=1 << 20, copy="async_in", input_copy_streams=copy_streams)):
+        assert np.array_equal(r, oracle.scan(v))
+
+
 # ------------------------------------------------------------------ library call captured into the job graph
 @pytest.mark.parametrize("mode,copy,callback", [("set", "kernels", "host_flag"), ("set", "async_in", "event_poll"),
                                                 ("set", "nodes", "host_flag"), ("graph", "kernels", "host_flag"),

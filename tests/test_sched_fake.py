@@ -259,6 +259,10 @@ def test_invalid_arguments_rejected():
         _fake(workers=2, slots=2, callback=A.SET_CB_HOST_FLAG + 1)  # no such completion mechanism
     with pytest.raises(A.SetError):
         _fake(workers=2, slots=2, dispatchers=-1)
+    for bad in (-1, 65):
+        with pytest.raises(A.SetError):
+            _fake(workers=2, slots=2, input_copy_streams=bad)
+    _fake(workers=2, slots=2, input_copy_streams=64).close()  # capped at the worker count
     for cb in ("event_poll", "event_chain", "same_stream", "host_flag"):
         _fake(workers=2, slots=2, callback=cb).close()
 

@@ -84,3 +84,37 @@ def test_eq_terms_hand_timeline():
     assert t["t_in_k"] == pytest.approx((2 + 0) / 2)
     assert t["delta_t_k"] == pytest.approx((1 + 0) / 2)
     assert t["t_k_out"] == pytest.approx((2 + 4) / 2)
+
+
+def test_dma_copies_join_their_stream(tmp_path):
+    """rocprofv3 CSVs where the input copies went by DMA (memory-copy trace,
+    with its stream) and the rest as kernels: the per-job terms see
+    [DMA input copy, stages, output copy kernel], the kernel gap only kernels,
+    and the idle fraction the union of both."""
+    k = tmp_path / "run_kernel_trace.csv"
+    c = tmp_path / "run_memory_copy_trace.csv"
+    # stream 7: job 1 = dma(0,10) g(12,20) s(21,25) k_copy(27,30); job 2 = dma(40,50) g(50,55) s(55,56) k_copy(60,62)
+    krows = [(12, 20, "setrt::k_gauss"), (21, 25, "setrt::k_sobel"), (27, 30, "setrt::k_copy_bytes"),
+             (50, 55, "setrt::k_gauss"), (55, 56, "setrt::k_sobel"), (60, 62, "setrt::k_copy_bytes")]
+    with open(k, "w") as fh:
+        fh.write('"Kind","Stream_Id","Kernel_Name","Start_Timestamp","End_Timestamp"\n')
+        for a, b, n in krows:
+            fh.write('"KERNEL_DISPATCH",7,"%s",%d,%d\n' % (n, a, b))
+    with open(c, "w") as fh:
+        fh.write('"Kind","Direction","Stream_Id","Start_Timestamp","End_Timestamp"\n')
+        for a, b in ((0, 10), (40, 50)):
+            fh.write('"MEMORY_COPY","MEMORY_COPY_HOST_TO_DEVICE",7,%d,%d\n' % (a, b))
+    m = trace.analyze_dir(str(tmp_path))
+    e = m["eq_terms"]  # ns in the files, us in the result
+    assert e["jobs"] == 2
+    assert e["t_in"] == pytest.approx(10 / 1e3)
+    assert e["t_k"] == pytest.approx((8 + 4 + 5 + 1) / 2 / 1e3)
+    assert e["t_in_k"] == pytest.approx((2 + 0) / 2 / 1e3)
+    assert e["t_k_out"] == pytest.approx((2 + 4) / 2 / 1e3)
+    # kernel gaps over the 6 kernels only: 1, 2, 20, 0, 4
+    assert m["mean_kernel_gap"] == pytest.approx((1 + 2 + 20 + 0 + 4) / 5 / 1e3)
+    # busy = [0,10] + [12,20] + [21,25] + [27,30] + [40,56] + [60,62] = 10+8+4+3+16+2 = 43 of 62
+    assert m["gpu_idle_fraction"] == pytest.approx(1 - 43 / 62)
+    # gaps with the DMA copies as GPU work: 2, 1, 2, 10, 0, 0, 4
+    assert m["mean_gap"] == pytest.approx(19 / 7 / 1e3)
+    assert m["h2d_copies"] == 2
