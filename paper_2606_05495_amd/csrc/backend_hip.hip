@@ -81,6 +81,8 @@ struct Slot {
   ChainNodes nodes;
   hipEvent_t ev = nullptr;
   hipEvent_t in_ev = nullptr;  // end of the input copy on an input-copy stream
+  bool in_prefetched = false;  // SET mode: the bound job's input copy was issued at bind
+  bool in_stale = false;       // a prefetched copy of a job stolen from this slot may still be landing
   CbCtx cb{};
   const void* host_in = nullptr;
   uint64_t in_bytes = 0;
@@ -283,7 +285,30 @@ class HipBackend : public Backend {
     Pipe& p = *pipes_[j->tmpl];
     Slot& sl = p.slots[(size_t)j->worker * d_ + j->slot];
     set_scalars(p, sl, j);
-    return update_exec(p, sl, sl.exec, sl.nodes, err);
+    const int rc = update_exec(p, sl, sl.exec, sl.nodes, err);
+    if (rc != SET_OK) return rc;
+    // SET mode with input-copy streams: the input copy starts here, when the
+    // job takes its FREE slot (nothing reads that slot's input any more), so
+    // it overlaps the jobs ahead of it on the worker and is usually complete
+    // when the graph is launched.  A stolen job's copy is left to its launch,
+    // on the thief's own stream, rather than queued behind the copy stream's
+    // backlog.
+    // A slot still marked prefetched was left by a job stolen before launch,
+    // whose copy may not have landed yet.  A prefetched successor copies on
+    // the same copy stream, after it; any other successor waits for that
+    // copy's event before its own copy (in_stale).
+    const bool stale = sl.in_prefetched;
+    sl.in_prefetched = false;
+    sl.in_stale = false;
+    if (cfg_.mode == SET_MODE_SET && in_ahead(p.t) && sl.in_ev && sl.in_bytes && !j->stolen) {
+      hipStream_t cs = copy_streams_[(size_t)j->worker % copy_streams_.size()];
+      HIPCK(hipMemcpyAsync(sl.base + p.L.in, sl.host_in, sl.in_bytes, hipMemcpyHostToDevice, cs));
+      HIPCK(hipEventRecord(sl.in_ev, cs));
+      sl.in_prefetched = true;
+    } else {
+      sl.in_stale = stale;
+    }
+    return SET_OK;
   }
 
   int launch(JobRec* j, DoneFn done, void* ctx, std::string* err) override {
@@ -775,14 +800,25 @@ class HipBackend : public Backend {
   }
 
   // SET_COPY_ASYNC_IN: the job's input copy, ordered ahead of its graph on
-  // stream st.  Without input-copy streams it runs on st itself.  With them it
-  // runs on input-copy stream w % C, and st waits on its event: at most C DMA
-  // copies are then in flight, however many workers there are.  The slot was
-  // released before this job was bound to it, so the copy cannot overwrite
-  // an input that a running graph still reads.
+  // stream st.  If bind already issued it (SET mode with input-copy
+  // streams), st only waits on its event.  Otherwise, without input-copy
+  // streams (and for a stolen job in SET mode) it runs on st itself; in the
+  // other modes with input-copy streams it runs on input-copy stream w % C
+  // and st waits on its event, so at most C DMA copies are in flight.  The
+  // slot was released before this job was bound to it, so the copy cannot
+  // overwrite an input that a running graph still reads.
   hipError_t input_ahead(Pipe& p, Slot& sl, hipStream_t st, int w) {
     if (!in_ahead(p.t) || sl.in_bytes == 0) return hipSuccess;
-    if (copy_streams_.empty() || !sl.in_ev)
+    if (sl.in_prefetched) {
+      sl.in_prefetched = false;
+      return hipStreamWaitEvent(st, sl.in_ev, 0);
+    }
+    if (sl.in_stale) {
+      sl.in_stale = false;
+      const hipError_t e = hipStreamWaitEvent(st, sl.in_ev, 0);
+      if (e != hipSuccess) return e;
+    }
+    if (copy_streams_.empty() || !sl.in_ev || cfg_.mode == SET_MODE_SET)
       return hipMemcpyAsync(sl.base + p.L.in, sl.host_in, sl.in_bytes, hipMemcpyHostToDevice, st);
     hipStream_t cs = copy_streams_[(size_t)w % copy_streams_.size()];
     hipError_t e = hipMemcpyAsync(sl.base + p.L.in, sl.host_in, sl.in_bytes, hipMemcpyHostToDevice, cs);

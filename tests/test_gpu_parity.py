@@ -695,6 +695,68 @@ def test_async_input_copy_streams(torch_gpu, mode, copy_streams):
         assert np.array_equal(r, oracle.scan(v))
 
 
+@pytest.mark.parametrize("callback", ["event_poll", "host_flag"])
+def test_prefetched_input_with_stealing(torch_gpu, callback):
+    """SET with input-copy streams issues each input copy at bind.  With every job submitted to worker 0's
+    queue, thieves retarget prefetched jobs (their copy is redone on the thief's stream) and the victim's
+    slot takes a new job while the abandoned copy may still be landing: every result must still match."""
+    _say("prefetched input + stealing", callback)
+    imgs = [synth.box_image(2, j, 128, 128) for j in range(64)]
+    outs, st = _run_images("set", "box_hist", imgs, np.uint8, workers=4, slots=4, flags=0, copy="async_in",
+                           input_copy_streams=2, submit_policy=A.SET_SUBMIT_SKEW0, callback=callback,
+                           dispatchers=4, inflight=1)
+    for img, o in zip(imgs, outs):
+        assert np.array_equal(o[64:64 + 1024].view(np.uint32), oracle.box_hist(img)[2])
+    assert st.stolen > 0
+    rng = np.random.default_rng(14)
+    ins = [rng.integers(-(1 << 20), (1 << 20) + 1, n).astype(np.int32) for n in (7, 4096, 100003)] * 8
+    for v, r in zip(ins, _run_scan("set", ins, max_n=1 << 17, copy="async_in", input_copy_streams=2,
+                                   submit_policy=A.SET_SUBMIT_SKEW0, callback=callback, dispatchers=4)):
+        assert np.array_equal(r, oracle.scan(v))
+
+
+def test_prefetch_stale_copy_under_steals(torch_gpu):
+    """Regression: a job stolen before launch leaves its prefetched copy queued behind one backlogged
+    input-copy stream; a stolen job later bound to that slot copies on its own stream and must wait for
+    the abandoned copy, or the abandoned copy lands on top of its input.  8 workers x 16 slots, 4 MiB
+    inputs, one input-copy stream, 3 of 4 jobs hinted onto workers 0-3 so the others drain and steal
+    in every direction; every job's result is checked."""
+    _say("prefetch stale copy under steals")
+    P, J = 8, 480
+    imgs = [synth.normal_image(5, k) for k in range(P)]
+    refs = [oracle.gauss_sobel(im, want_images=False) for im in imgs]
+    ctx = Context(mode="set", workers=8, slots=16, inflight=1, input_copy_streams=1, callback="event_poll",
+                  dispatchers=4)
+    tid = ctx.define("gauss_sobel", width=1024, height=1024, flags=0, copy="async_in")
+    ib, ob = ctx.in_bytes(tid), ctx.out_bytes(tid)
+    tin, nin = pinned(ib * P)
+    for k in range(P):
+        nin[k * ib:(k + 1) * ib].view(np.float32)[:] = imgs[k].ravel()
+    tout, nout = pinned(128 * J)
+    arr = ctx.job_array(J)
+    j = np.arange(J, dtype=np.uint64)
+    arr["host_in"] = tin.data_ptr() + (j % np.uint64(P)) * np.uint64(ib)
+    arr["in_bytes"] = ib
+    arr["host_out"] = tout.data_ptr() + j * np.uint64(128)
+    arr["out_bytes"] = ob
+    arr["user_tag"] = j
+    arr["worker_hint"] = np.where(j % 4 == 3, 4 + (j // 4) % 4, (j // 4) % 4).astype(np.int32)
+    first = ctx.submit_many(tid, arr)
+    ctx.drain()
+    st = ctx.stats()
+    ctx.close()
+    out = nout.reshape(J, 128)
+    bad = []
+    for i in range(J):
+        _check_header(out[i], first + i, i)
+        r = refs[i % P]
+        if abs(int(out[i, 64:68].view(np.uint32)[0]) - r["count"]) > r["band"] or \
+                abs(float(out[i, 68:72].view(np.float32)[0]) - r["sum"]) > 1e-5 * abs(r["sum"]):
+            bad.append(i)
+    assert not bad, bad[:20]
+    assert st.stolen > 0
+
+
 # ------------------------------------------------------------------ library call captured into the job graph
 @pytest.mark.parametrize("mode,copy,callback", [("set", "kernels", "host_flag"), ("set", "async_in", "event_poll"),
                                                 ("set", "nodes", "host_flag"), ("graph", "kernels", "host_flag"),
