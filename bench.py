@@ -572,7 +572,8 @@ def main():
                     help="SET launch permits per worker (default 1 with async_in copies, else the library's "
                          "min(2, d))")
     ap.add_argument("--spin-us", type=int, default=0)
-    ap.add_argument("--dispatchers", type=int, default=4, help="SET dispatcher threads")
+    ap.add_argument("--dispatchers", type=int, default=None,
+                    help="SET dispatcher threads (default 1 for the image workload, 4 otherwise)")
     ap.add_argument("--callback", default=None, choices=["event_chain", "same_stream", "event_poll", "host_flag"],
                     help="SET completion mechanism (default event_poll with async_in copies, host_flag otherwise)")
     ap.add_argument("--copy", default=None, choices=["nodes", "kernels", "async_in"],
@@ -619,6 +620,13 @@ def main():
         args.inflight = 1 if args.copy == "async_in" else 0
     if args.callback is None:
         args.callback = "event_poll" if args.copy == "async_in" else "host_flag"
+    if args.dispatchers is None:
+        # The image workload needs about 13,600 launches/s, within one thread's
+        # reach; with several threads, launches onto streams that share a
+        # hardware queue interleave, and a graph's wait on its DMA input copy
+        # can then sit between another job's kernels (traced: 50-66 us gaps
+        # inside jobs with 4 threads, none with 1, at the same jobs/s).
+        args.dispatchers = 1 if args.workload == "images" else 4
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the job path shards by running one independent scheduler per GPU, "
