@@ -383,7 +383,7 @@ class HipBackend : public Backend {
     if (sl.in_bytes) {
       if (in_by_kernel(p.t)) {
         sl.h2d_copy = CopyArgs{sl.host_in, sl.base + p.L.in, sl.in_bytes};
-        HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(kCopyBlocks), dim3(kBlock), sl.h2d_argv, 0, st));
+        HIPCK(hipLaunchKernel((const void*)&k_copy_in, dim3(kCopyBlocks), dim3(kBlock), sl.h2d_argv, 0, st));
       } else if (in_ahead(p.t)) {
         HIPCK(input_ahead(p, sl, st, si));
       } else {
@@ -396,7 +396,7 @@ class HipBackend : public Backend {
     }
     if (out_by_kernel(p.t)) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, sl.host_out, sl.out_bytes};
-      HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(d2h_copy_blocks(p.L.out_cap)), dim3(kBlock), sl.d2h_argv, 0, st));
+      HIPCK(hipLaunchKernel((const void*)&k_copy_out, dim3(d2h_copy_blocks(p.L.out_cap)), dim3(kBlock), sl.d2h_argv, 0, st));
     } else {
       HIPCK(hipMemcpyAsync(sl.host_out, sl.base + p.L.out, sl.out_bytes, hipMemcpyDeviceToHost, st));
     }
@@ -780,9 +780,9 @@ class HipBackend : public Backend {
     return kp;
   }
 
-  hipKernelNodeParams copy_params(void** argv, unsigned blocks = kCopyBlocks) {
+  hipKernelNodeParams copy_params(void** argv, bool to_device, unsigned blocks = kCopyBlocks) {
     hipKernelNodeParams kp{};
-    kp.func = (void*)&k_copy_bytes;
+    kp.func = to_device ? (void*)&k_copy_in : (void*)&k_copy_out;
     kp.gridDim = dim3(blocks);
     kp.blockDim = dim3(kBlock);
     kp.sharedMemBytes = 0;
@@ -837,7 +837,7 @@ class HipBackend : public Backend {
     if (p.L.in_cap > 0 && !in_ahead(p.t)) {
       if (kcopy) {
         sl.h2d_copy = CopyArgs{p.placeholder, sl.base + p.L.in, p.L.in_cap};
-        hipKernelNodeParams kp = copy_params(sl.h2d_argv);
+        hipKernelNodeParams kp = copy_params(sl.h2d_argv, true);
         HIPCK(hipGraphAddKernelNode(&cn->h2d, g, nullptr, 0, &kp));
       } else {
         HIPCK(hipGraphAddMemcpyNode1D(&cn->h2d, g, nullptr, 0, sl.base + p.L.in, p.placeholder, p.L.in_cap,
@@ -852,7 +852,7 @@ class HipBackend : public Backend {
     }
     if (out_by_kernel(p.t)) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, p.placeholder, p.L.out_cap};
-      hipKernelNodeParams kp = copy_params(sl.d2h_argv, d2h_copy_blocks(p.L.out_cap));
+      hipKernelNodeParams kp = copy_params(sl.d2h_argv, false, d2h_copy_blocks(p.L.out_cap));
       HIPCK(hipGraphAddKernelNode(&cn->d2h, g, &prev, 1, &kp));
     } else {
       HIPCK(hipGraphAddMemcpyNode1D(&cn->d2h, g, &prev, 1, p.placeholder, sl.base + p.L.out, p.L.out_cap,
@@ -886,7 +886,7 @@ class HipBackend : public Backend {
     if (in_node) {
       if (kcopy) {
         sl.h2d_copy = CopyArgs{p.placeholder, sl.base + p.L.in, p.L.in_cap};
-        HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(kCopyBlocks), dim3(kBlock), sl.h2d_argv, 0, st));
+        HIPCK(hipLaunchKernel((const void*)&k_copy_in, dim3(kCopyBlocks), dim3(kBlock), sl.h2d_argv, 0, st));
       } else {
         HIPCK(hipMemcpyAsync(sl.base + p.L.in, p.placeholder, p.L.in_cap, hipMemcpyHostToDevice, st));
       }
@@ -897,7 +897,7 @@ class HipBackend : public Backend {
     }
     if (out_by_kernel(p.t)) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, p.placeholder, p.L.out_cap};
-      HIPCK(hipLaunchKernel((const void*)&k_copy_bytes, dim3(d2h_copy_blocks(p.L.out_cap)), dim3(kBlock), sl.d2h_argv, 0, st));
+      HIPCK(hipLaunchKernel((const void*)&k_copy_out, dim3(d2h_copy_blocks(p.L.out_cap)), dim3(kBlock), sl.d2h_argv, 0, st));
     } else {
       HIPCK(hipMemcpyAsync(p.placeholder, sl.base + p.L.out, p.L.out_cap, hipMemcpyDeviceToHost, st));
     }
@@ -971,7 +971,7 @@ class HipBackend : public Backend {
     if (sl.in_bytes && cn.h2d) {
       if (kcopy) {
         sl.h2d_copy = CopyArgs{sl.host_in, sl.base + p.L.in, sl.in_bytes};
-        hipKernelNodeParams kp = copy_params(sl.h2d_argv);
+        hipKernelNodeParams kp = copy_params(sl.h2d_argv, true);
         HIPCK(hipGraphExecKernelNodeSetParams(ex, cn.h2d, &kp));
       } else {
         HIPCK(hipGraphExecMemcpyNodeSetParams1D(ex, cn.h2d, sl.base + p.L.in, sl.host_in, sl.in_bytes,
@@ -982,7 +982,7 @@ class HipBackend : public Backend {
     HIPCK(hipGraphExecKernelNodeSetParams(ex, cn.k[0], &kp));
     if (out_by_kernel(p.t)) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, sl.host_out, sl.out_bytes};
-      hipKernelNodeParams kd = copy_params(sl.d2h_argv, d2h_copy_blocks(p.L.out_cap));
+      hipKernelNodeParams kd = copy_params(sl.d2h_argv, false, d2h_copy_blocks(p.L.out_cap));
       HIPCK(hipGraphExecKernelNodeSetParams(ex, cn.d2h, &kd));
     } else {
       HIPCK(hipGraphExecMemcpyNodeSetParams1D(ex, cn.d2h, sl.host_out, sl.base + p.L.out, sl.out_bytes,

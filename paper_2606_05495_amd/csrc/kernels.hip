@@ -103,11 +103,13 @@ __device__ inline void stage_tile(T (*tile)[P], Get get) {
   }
 }
 
-// ------------------------------------------------------------------ copy kernel (H2D pull / D2H push)
+// ------------------------------------------------------------------ copy kernels (H2D pull / D2H push)
 // Grid-stride over 16-byte words with four independent loads in flight per
 // thread, then a byte tail.  Source and destination are 16-byte aligned (slot
-// buffers are 256-aligned; host buffers are checked by the binder).
-__global__ __launch_bounds__(kBlock) void k_copy_bytes(CopyArgs a) {
+// buffers are 256-aligned; host buffers are checked by the binder).  The two
+// directions are separate kernels only so that a kernel trace tells them
+// apart (input-copy idle time, batch boundaries).
+__device__ __forceinline__ void copy_bytes(const CopyArgs& a) {
   const uint64_t nvec = a.bytes >> 4;
   const uint4* __restrict__ src = reinterpret_cast<const uint4*>(a.src);
   uint4* __restrict__ dst = reinterpret_cast<uint4*>(a.dst);
@@ -125,6 +127,8 @@ __global__ __launch_bounds__(kBlock) void k_copy_bytes(CopyArgs a) {
   const uint64_t t = tail + (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t < a.bytes) reinterpret_cast<uint8_t*>(a.dst)[t] = reinterpret_cast<const uint8_t*>(a.src)[t];
 }
+__global__ __launch_bounds__(kBlock) void k_copy_in(CopyArgs a) { copy_bytes(a); }
+__global__ __launch_bounds__(kBlock) void k_copy_out(CopyArgs a) { copy_bytes(a); }
 
 // ------------------------------------------------------------------ completion word
 // Runs after the job's device-to-host copy node; the kernel boundary orders

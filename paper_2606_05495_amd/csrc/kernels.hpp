@@ -126,7 +126,8 @@ struct CopyArgs {
   void* dst;
   uint64_t bytes;
 };
-__global__ void k_copy_bytes(CopyArgs a);
+__global__ void k_copy_in(CopyArgs a);   // host-to-device
+__global__ void k_copy_out(CopyArgs a);  // device-to-host
 
 // Completion word: one thread stores the job's binding sequence number (from
 // the slot header) into a pinned host word with a system-scope release.

@@ -14,7 +14,8 @@ Definitions (the paper gives prose definitions; these are the readings):
   reading of the scheduling-overhead fraction t_schedule / T_measured
   (Section 5.3 with Eq. 4): T_measured is the span of the timeline and
   T_ideal the time some engine was busy, so t_schedule = T_measured - T_ideal.
-  Compute-idle uses kernels only, copy-idle the host-to-device copies only.
+  Compute-idle uses kernels only, copy-idle the host-to-device copies only
+  (DMA copies and k_copy_in kernels).
 * inter-batch overhead (Eq. 3) -- for a batch-synchronised run, the start of
   batch i+1's first copy minus the end of batch i's last copy.
 
@@ -242,10 +243,15 @@ def analyze_dir(dirpath: str, batch: int = 0) -> dict:
     m["unit"] = "us"
     m["h2d_copies"] = len(h2d)
     m["d2h_copies"] = len(d2h)
-    if h2d:
-        m["h2d_busy_GBps_hint"] = None
-    if batch and h2d and d2h:
-        g = inter_batch_gaps(h2d, d2h, batch)
+    # input and output copies of either kind: DMA copies and the copy kernels
+    # (k_copy_in host-to-device, k_copy_out device-to-host)
+    cin = h2d + [iv for iv, n in zip(kernels, names) if "k_copy_in" in n]
+    cout = d2h + [iv for iv, n in zip(kernels, names) if "k_copy_out" in n]
+    span = m.get("span") or 0.0
+    if cin and span > 0:
+        m["h2d_idle_fraction"] = 1.0 - union_length(cin) / (span * 1e3)
+    if batch and cin and cout:
+        g = inter_batch_gaps(cin, cout, batch)
         m["mean_inter_batch_us"] = (sum(g) / len(g) / 1e3) if g else None
     return m
 

@@ -94,8 +94,8 @@ def test_dma_copies_join_their_stream(tmp_path):
     k = tmp_path / "run_kernel_trace.csv"
     c = tmp_path / "run_memory_copy_trace.csv"
     # stream 7: job 1 = dma(0,10) g(12,20) s(21,25) k_copy(27,30); job 2 = dma(40,50) g(50,55) s(55,56) k_copy(60,62)
-    krows = [(12, 20, "setrt::k_gauss"), (21, 25, "setrt::k_sobel"), (27, 30, "setrt::k_copy_bytes"),
-             (50, 55, "setrt::k_gauss"), (55, 56, "setrt::k_sobel"), (60, 62, "setrt::k_copy_bytes")]
+    krows = [(12, 20, "setrt::k_gauss"), (21, 25, "setrt::k_sobel"), (27, 30, "setrt::k_copy_out"),
+             (50, 55, "setrt::k_gauss"), (55, 56, "setrt::k_sobel"), (60, 62, "setrt::k_copy_out")]
     with open(k, "w") as fh:
         fh.write('"Kind","Stream_Id","Kernel_Name","Start_Timestamp","End_Timestamp"\n')
         for a, b, n in krows:
@@ -118,3 +118,24 @@ def test_dma_copies_join_their_stream(tmp_path):
     # gaps with the DMA copies as GPU work: 2, 1, 2, 10, 0, 0, 4
     assert m["mean_gap"] == pytest.approx(19 / 7 / 1e3)
     assert m["h2d_copies"] == 2
+
+
+def test_copy_kernels_give_copy_idle_and_batch_boundaries(tmp_path):
+    """With copy kernels (k_copy_in / k_copy_out) and no DMA records, the
+    input-copy idle fraction and Eq. 3's inter-batch gap come from the
+    kernels: two batches of two jobs on one stream, the second starting 16
+    after the first's last output copy."""
+    k = tmp_path / "run_kernel_trace.csv"
+    rows = [(0, 10, "k_copy_in"), (10, 20, "k_copy_in"), (20, 25, "k_g"), (25, 30, "k_g"),
+            (30, 32, "k_copy_out"), (32, 34, "k_copy_out"),
+            (50, 60, "k_copy_in"), (60, 70, "k_copy_in"), (70, 75, "k_g"), (75, 80, "k_g"),
+            (80, 82, "k_copy_out"), (82, 84, "k_copy_out")]
+    with open(k, "w") as fh:
+        fh.write('"Kind","Stream_Id","Kernel_Name","Start_Timestamp","End_Timestamp"\n')
+        for a, b, n in rows:
+            fh.write('"KERNEL_DISPATCH",3,"setrt::%s",%d,%d\n' % (n, a, b))
+    m = trace.analyze_dir(str(tmp_path), batch=2)
+    assert m["mean_inter_batch_us"] == pytest.approx(16 / 1e3)
+    # input copies busy 40 of the 84-long span
+    assert m["h2d_idle_fraction"] == pytest.approx(1 - 40 / 84)
+    assert m["h2d_copies"] == 0
