@@ -648,7 +648,7 @@ class HipBackend : public Backend {
         sl.gauss = GaussArgs{(const float*)(b + L.in), (float*)(b + L.b1), h, w, taps[0], taps[1], taps[2], sc.hdr,
                              JobScalars{}};
         const Grid3 sg = sobel_grid(h, w);
-        const unsigned nb = sg.x * sg.y;
+        const unsigned nb = (unsigned)sobel_partials(h, w);
         const uint64_t q = ((uint64_t)nb * 4 + 255) / 256 * 256;
         sl.sobel = SobelArgs{(const float*)(b + L.b1), (uint8_t*)(b + L.b2), h, w,
                              t.threshold != 0.f ? t.threshold : 1.0f, (uint32_t*)(b + L.scratch),
@@ -660,7 +660,10 @@ class HipBackend : public Backend {
                          : gauss_win_rows(h, w) == 2 ? (const void*)&k_gauss5_win_f32<2>
                                                      : (const void*)&k_gauss5_win_f32<4>;
         stage(gk, to_dim3(gauss_grid(h, w)), &sl.gauss);
-        stage(win ? (const void*)&k_sobel_thresh_win_f32 : (const void*)&k_sobel_thresh_f32, to_dim3(sg), &sl.sobel);
+        const void* sk = !win                        ? (const void*)&k_sobel_thresh_f32
+                         : sobel_win_rows(h, w) == 2 ? (const void*)&k_sobel_thresh_win_f32<2>
+                                                     : (const void*)&k_sobel_thresh_win_f32<4>;
+        stage(sk, to_dim3(sg), &sl.sobel);
         stage((const void*)&k_sobel_final, dim3(1), &sl.sobelf);
         break;
       }

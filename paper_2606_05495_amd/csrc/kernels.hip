@@ -411,14 +411,17 @@ __global__ __launch_bounds__(kBlock) void k_gauss5_win_f32(GaussArgs a) {
 template __global__ void k_gauss5_win_f32<2>(GaussArgs a);
 template __global__ void k_gauss5_win_f32<4>(GaussArgs a);
 
-// Sobel with the same window: per input row, the horizontal smoothing
-// (left + 2*centre + right) and difference (right - left); per output row,
-// gx = d[y-1] + 2*d[y] + d[y+1] and gy = s[y+1] - s[y-1] (the two 3x3
-// kernels factored).  Mask bytes of a lane go out as one 4-byte store.
+// Sobel with the same window, vertical pass first.  The two 3x3 kernels
+// factor into a vertical and a horizontal 3-tap pass: gx = horizontal
+// difference of the vertical smoothing, gy = horizontal smoothing of the
+// vertical difference.  Each lane forms both vertical terms for its 4 columns
+// (lanes 0 and 63 also for the column beyond the wave's edge), then takes the
+// neighbouring columns' terms by DPP lane shift.  Mask bytes of a lane go out
+// as one 4-byte store; each wave writes its own (count, sum) partial, so there
+// is no block-wide barrier, and the final kernel combines the partials in a
+// fixed order.
+template <int R>
 __global__ __launch_bounds__(kBlock) void k_sobel_thresh_win_f32(SobelArgs a) {
-  constexpr int R = kSobelWinRows;
-  __shared__ float s4f[4];
-  __shared__ uint32_t s4u[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   unsigned bx, by;
   xcd_tile(bx, by);
@@ -439,49 +442,56 @@ __global__ __launch_bounds__(kBlock) void k_sobel_thresh_win_f32(SobelArgs a) {
   const float thr = a.thr;
   float sum = 0.f;
   uint32_t cnt = 0;
-  float sm[R + 2][4], df[R + 2][4];  // per input row: smoothing and difference along x
-#pragma unroll
-  for (int r = 0; r < R + 2; ++r) {
-    float left = __shfl_up(v[r].w, 1, 64), right = __shfl_down(v[r].x, 1, 64);
-    if (lane == 0) left = e[r];
-    if (lane == 63) right = e[r];
-    const float c[6] = {left, v[r].x, v[r].y, v[r].z, v[r].w, right};
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      sm[r][j] = (c[j] + 2.f * c[j + 1]) + c[j + 2];
-      df[r][j] = c[j + 2] - c[j];
-    }
-  }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int y = y0 + r;
-    uint32_t packed = 0;
-    float rs = 0.f;
-    uint32_t rc = 0;
+    float vs[4], vd[4];  // vertical smoothing (above + 2*centre + below) and difference (below - above)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float gx = (df[r][j] + 2.f * df[r + 1][j]) + df[r + 2][j];
-      const float gy = sm[r + 2][j] - sm[r][j];
+      const float t0 = (&v[r].x)[j], t1 = (&v[r + 1].x)[j], t2 = (&v[r + 2].x)[j];
+      vs[j] = (t0 + 2.f * t1) + t2;
+      vd[j] = t2 - t0;
+    }
+    const float es = (e[r] + 2.f * e[r + 1]) + e[r + 2], ed = e[r + 2] - e[r];
+    float ls = up1(vs[3]), ld = up1(vd[3]), rs = down1(vs[0]), rd = down1(vd[0]);
+    if (lane == 0) {
+      ls = es;
+      ld = ed;
+    }
+    if (lane == 63) {
+      rs = es;
+      rd = ed;
+    }
+    const float cs[6] = {ls, vs[0], vs[1], vs[2], vs[3], rs};
+    const float cd[6] = {ld, vd[0], vd[1], vd[2], vd[3], rd};
+    uint32_t packed = 0, rc = 0;
+    float rsum = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float gx = cs[j + 2] - cs[j];
+      const float gy = (cd[j] + 2.f * cd[j + 1]) + cd[j + 2];
       const float mag = sqrt_hw(gx * gx + gy * gy);
       const uint32_t on = mag > thr ? 1u : 0u;
       packed |= on << (8 * j);
       rc += on;
-      rs += mag;
+      rsum += mag;
     }
     if (y < h && in4) {
       *reinterpret_cast<uint32_t*>(a.mask + (size_t)y * w + x) = packed;
       cnt += rc;
-      sum += rs;
+      sum += rsum;
     }
   }
-  const unsigned b = by * gridDim.x + bx;
-  const float bs = block_sum_f32(sum, s4f);
-  const uint32_t bc = block_sum_u32(cnt, s4u);
-  if (threadIdx.x == 0) {
-    a.psum[b] = bs;
-    a.pcount[b] = bc;
+  const float ws = wave_sum_f32(sum);
+  const uint32_t wc = wave_sum_u32(cnt);
+  if (lane == 0) {
+    const unsigned part = (by * gridDim.x + bx) * 4 + wave;
+    a.psum[part] = ws;
+    a.pcount[part] = wc;
   }
 }
+template __global__ void k_sobel_thresh_win_f32<2>(SobelArgs a);
+template __global__ void k_sobel_thresh_win_f32<4>(SobelArgs a);
 
 // ------------------------------------------------------------------ thermal grid step
 // T' = T + CP*P + CY*(N + S - 2T) + CX*(W + E - 2T) + CZ*(T_AMB - T), a
@@ -551,15 +561,45 @@ __global__ __launch_bounds__(kBlock) void k_hotspot_f32(HotspotArgs a) {
   a.tout[i] = hotspot::step(t, a.p[i], n, s, wv, ev);
 }
 
-// One block: fixed-order combination of the per-block count and sum.
+// One block: fixed-order combination of the partial counts and sums (one per
+// wave on the window path, one per block on the LDS-tile path).
 __global__ __launch_bounds__(kBlock) void k_sobel_final(SobelFinalArgs a) {
   __shared__ float s4f[4];
   __shared__ uint32_t s4u[4];
+  // Thread t takes 16-byte groups t, t + 256, t + 512, ... (four partials
+  // each), four groups per step with independent loads in flight, then the
+  // last nparts % 4 partials.  The order depends only on nparts.  Both arrays
+  // start 256-byte aligned.
+  const float4* ps4 = reinterpret_cast<const float4*>(a.psum);
+  const uint4* pc4 = reinterpret_cast<const uint4*>(a.pcount);
+  const unsigned n4 = a.nparts >> 2;
   float s = 0.f;
   uint32_t c = 0;
-  for (unsigned k = threadIdx.x; k < a.nblocks; k += kBlock) {
-    s += a.psum[k];
-    c += a.pcount[k];
+  unsigned k = threadIdx.x;
+  for (; k + 3 * kBlock < n4; k += 4 * kBlock) {
+    float4 f[4];
+    uint4 u[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      f[i] = ps4[k + i * kBlock];
+      u[i] = pc4[k + i * kBlock];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      s += (f[i].x + f[i].y) + (f[i].z + f[i].w);
+      c += (u[i].x + u[i].y) + (u[i].z + u[i].w);
+    }
+  }
+  for (; k < n4; k += kBlock) {
+    const float4 f = ps4[k];
+    const uint4 u = pc4[k];
+    s += (f.x + f.y) + (f.z + f.w);
+    c += (u.x + u.y) + (u.z + u.w);
+  }
+  const unsigned t = 4 * n4 + threadIdx.x;
+  if (t < a.nparts) {
+    s += a.psum[t];
+    c += a.pcount[t];
   }
   s = block_sum_f32(s, s4f);
   c = block_sum_u32(c, s4u);

@@ -63,7 +63,7 @@ struct SobelArgs {
 struct SobelFinalArgs {
   const uint32_t* pcount;
   const float* psum;
-  unsigned nblocks;
+  unsigned nparts;     // partial pairs to combine
   uint32_t* out_count; // output payload
   float* out_sum;
   SlotConst sc;
@@ -173,6 +173,7 @@ __global__ void k_gauss5_f32(GaussArgs a);
 template <int R>
 __global__ void k_gauss5_win_f32(GaussArgs a);
 __global__ void k_sobel_thresh_f32(SobelArgs a);
+template <int R>
 __global__ void k_sobel_thresh_win_f32(SobelArgs a);
 __global__ void k_sobel_final(SobelFinalArgs a);
 __global__ void k_saxpy_tanh_sum_f32(VecArgs a);

@@ -115,10 +115,9 @@ static SlotLayout layout_of(const set_job_template& t) {
         L.b2 = off;
         off = up(off + npix);
       }
-      const Grid3 g = sobel_grid((int)t.height, (int)t.width);
-      const uint64_t nb = (uint64_t)g.x * g.y;
+      const uint64_t nb = sobel_partials((int)t.height, (int)t.width);
       L.scratch = off;
-      L.scratch_bytes = up(nb * 4) + up(nb * 4);  // per-block count, per-block sum
+      L.scratch_bytes = up(nb * 4) + up(nb * 4);  // partial counts, partial sums
       off = up(off + L.scratch_bytes);
       break;
     }
@@ -287,8 +286,7 @@ int pipeline_sizes(const set_job_template& t, TemplateSizes* out) {
       break;
     }
     case SET_PIPE_GAUSS_SOBEL_F32: {
-      const Grid3 g = sobel_grid((int)t.height, (int)t.width);
-      const uint64_t nb = (uint64_t)g.x * g.y;
+      const uint64_t nb = sobel_partials((int)t.height, (int)t.width);
       stage("gauss5_f32", 4 * npix + 4 * npix);
       stage("sobel_thresh_f32", 4 * npix + npix + 8 * nb);
       stage("sobel_final", 8 * nb + 8 + 64);

@@ -55,14 +55,13 @@ inline unsigned hist_blocks(int64_t npix) {
 // Float images whose width is a multiple of 4 take the register-window
 // kernels: a lane owns 4 adjacent columns (16-byte loads and stores), a wave
 // 256 columns x R rows, a block 4 waves stacked vertically.  The Gaussian
-// takes R = 2 up to 2048^2 pixels and R = 4 above (more blocks in flight pay
-// on the smaller images, fewer re-read halo rows on the larger); Sobel takes
-// R = 2 (the fastest of 2, 4, 8 at 1024^2 .. 4096^2).  Other widths take the
-// LDS-tile kernels.
+// takes R = 2 up to 2048^2 pixels and Sobel up to 1024^2, both R = 4 above
+// (more blocks in flight pay on the smaller images, fewer re-read halo rows on
+// the larger).  Other widths take the LDS-tile kernels.
 constexpr int kWinCols = 256;                 // columns per wave (and per block)
-constexpr int kSobelWinRows = 2;              // Sobel: output rows per wave
 inline bool image_window_path(int w) { return w > 0 && (w % 4) == 0; }
 inline int gauss_win_rows(int h, int w) { return (int64_t)h * w <= (int64_t)2048 * 2048 ? 2 : 4; }
+inline int sobel_win_rows(int h, int w) { return (int64_t)h * w <= (int64_t)1024 * 1024 ? 2 : 4; }
 inline Grid3 window_grid(int h, int w, int rows_per_wave) {
   const int rows = 4 * rows_per_wave;
   return {(unsigned)((w + kWinCols - 1) / kWinCols), (unsigned)((h + rows - 1) / rows), 1u};
@@ -72,8 +71,14 @@ inline Grid3 gauss_grid(int h, int w) {
   return {(unsigned)((w + kGaussTW - 1) / kGaussTW), (unsigned)((h + kGaussTH - 1) / kGaussTH), 1u};
 }
 inline Grid3 sobel_grid(int h, int w) {
-  if (image_window_path(w)) return window_grid(h, w, kSobelWinRows);
+  if (image_window_path(w)) return window_grid(h, w, sobel_win_rows(h, w));
   return {(unsigned)((w + kSobelTW - 1) / kSobelTW), (unsigned)((h + kSobelTH - 1) / kSobelTH), 1u};
+}
+// Sobel's partial (count, sum) pairs: one per wave on the window path, one per
+// block on the LDS-tile path.
+inline uint64_t sobel_partials(int h, int w) {
+  const Grid3 g = sobel_grid(h, w);
+  return (uint64_t)g.x * g.y * (image_window_path(w) ? 4u : 1u);
 }
 // Thermal-grid step: the register window (4 columns x kHotWinRows rows per
 // lane) for widths that are multiples of 4, one pixel per thread otherwise.
