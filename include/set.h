@@ -107,8 +107,10 @@ enum set_callback_mode {
      * array (system-scope release store, after the device-to-host copy node
      * has finished).  The completion thread watches each worker's oldest
      * word with plain host loads and calls no HIP function, so it never
-     * contends with the dispatcher inside the HIP runtime.  SET mode only;
-     * the configuration the benchmark runs. */
+     * contends with the dispatcher inside the HIP runtime.  SET mode only.
+     * Faster than event polling for short jobs with copy kernels; with DMA
+     * input copies the extra kernel costs more than it saves, and event
+     * polling is the faster. */
     SET_CB_HOST_FLAG = 3
 };
 
@@ -180,10 +182,13 @@ enum set_copy_mode {
                              Default: ROCm runs graph memcpy nodes as large-grid blit kernels that crowd
                              out the stage kernels */
     SET_COPY_NODES = 1,   /* graph memcpy nodes (hipMemcpyAsync in the synchronous model) */
-    SET_COPY_ASYNC_IN = 2 /* for jobs that move much data both ways: the input goes by hipMemcpyAsync on
-                             the worker stream right before the graph launch (the graph holds the stages
-                             and a device-to-host copy kernel); that pair moved 77 GB/s in both directions
-                             together against 67 GB/s for two copy kernels.  Host buffers 16-byte aligned */
+    SET_COPY_ASYNC_IN = 2 /* the input goes by hipMemcpyAsync (the DMA engines) on the worker stream
+                             right before the graph launch, or on an input-copy stream (see
+                             set_config.input_copy_streams); the graph holds the stages and a
+                             device-to-host copy kernel.  For link-bound jobs and long kernel chains: the
+                             CUs keep the stages while the DMA engines fill the link (57 GB/s host-to-device;
+                             77 GB/s in both directions with the output kernel).  One job in flight per
+                             worker suits it best.  Host buffers 16-byte aligned */
 };
 
 /* template flags */
@@ -223,12 +228,15 @@ typedef struct set_config {
      * at num_workers.  ROCm's graph launch is host-bound (about 16 us per
      * launch) but scales across threads. */
     int32_t dispatch_threads;
-    /* SET_COPY_ASYNC_IN templates, every mode: the number C of library-owned
-     * streams that carry the input copies (worker w's on stream w % C; the
-     * worker's stream waits on that copy's event before the graph).  At most
-     * C DMA copies are then in flight whatever the worker count; on a PCIe
-     * Gen5 link 4 MiB copies are fastest with 2 to 4 in flight.  0 = each
-     * input copy on its worker's own stream.  0..64, capped at num_workers. */
+    /* SET_COPY_ASYNC_IN templates: the number C of library-owned streams that
+     * carry the input copies, worker w's on stream w % C.  In SET mode a
+     * job's copy is issued when the submitter binds it to its FREE slot, and
+     * the graph waits on the copy's event at launch (a stolen job copies at
+     * launch on the thief's stream, after any copy still landing in its new
+     * slot); in the other modes the copy is issued at launch and the worker's
+     * stream waits on its event.  At most C DMA copies then run at once.
+     * 0 = each input copy on its worker's own stream, right before the graph.
+     * 0..64, capped at num_workers. */
     int32_t input_copy_streams;
 } set_config;
 
