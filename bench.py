@@ -485,6 +485,7 @@ def bench_serve(args, torch):
     from paper_2606_05495_amd import _abi as A
     from paper_2606_05495_amd import autotune, synth
     from paper_2606_05495_amd.runtime import Context, pinned
+    import oracle
     sides = synth.SERVE_SIDES
     P = args.serve_pool
     log("generating serving pools (%d images per size)" % P)
@@ -497,8 +498,33 @@ def bench_serve(args, torch):
     for s_ in sides:
         nin[offs[s_]:offs[s_] + P * 4 * s_ * s_].view(np.float32)[:] = imgs[s_].ravel()
     L = synth.VEC_POOL_LEN
-    xd = torch.from_numpy(synth.vec_pool(0, "x", L)).cuda()
-    yd = torch.from_numpy(synth.vec_pool(0, "y", L)).cuda()
+    xh, yh = synth.vec_pool(0, "x", L), synth.vec_pool(0, "y", L)
+    xd = torch.from_numpy(xh).cuda()
+    yd = torch.from_numpy(yh).cuda()
+    img_refs = {}
+
+    def check_sample(req, isimg, side, mix, done, vres, nout, rate, count=200):
+        """A seeded sample of completed requests of each kind against the oracle."""
+        rng = np.random.default_rng(int(rate))
+        ok = True
+        idx_img = np.flatnonzero(isimg & (done > 0))
+        idx_vec = np.flatnonzero(~isimg & (done > 0))
+        picks_img = rng.choice(idx_img, min(count, idx_img.size), replace=False) if idx_img.size else []
+        picks_vec = rng.choice(idx_vec, min(count, idx_vec.size), replace=False) if idx_vec.size else []
+        for i in picks_img:
+            key = (int(side[i]), int(mix["pool_idx"][i] % P))
+            if key not in img_refs:
+                img_refs[key] = oracle.gauss_sobel(imgs[key[0]][key[1]], want_images=False)
+            r = img_refs[key]
+            o = nout[i * 128:(i + 1) * 128]
+            ok &= abs(int(o[64:68].view(np.uint32)[0]) - r["count"]) <= r["band"]
+            ok &= abs(float(o[68:72].view(np.float32)[0]) - r["sum"]) <= 1e-5 * abs(r["sum"])
+        for i in picks_vec:
+            n_, xo, yo = int(req["n"][i]), int(req["x_off"][i]), int(req["y_off"][i])
+            S, E = oracle.saxpy_tanh_sum(xh[xo:xo + n_], yh[yo:yo + n_], req["a"][i])
+            ok &= abs(float(vres[i]) - S) <= oracle.vec_tolerance(S, E)
+        return bool(ok), len(picks_img) + len(picks_vec)
+
     results = []
     for rate in [float(r) for r in args.rates.split(",")]:
         ctx = Context(mode="set", workers=args.workers, slots=args.slots, mem_budget=int(args.mem_budget),
@@ -547,6 +573,7 @@ def bench_serve(args, torch):
                "max_backlog": int(st.max_backlog), "vec_batches": int(st.vec_batches),
                "offered_h2d_GBps": round(h2d_offered, 1), "mem_high_water_GB": round(ctx.stats().mem_high_water / 1e9, 2),
                "drain_after_window_s": round(span - args.serve_seconds, 3)}
+        res["verified"], res["checked"] = check_sample(req, isimg, side, mix, done, vres, nout, rate)
         log(json.dumps(res))
         results.append(res)
         ctx.close()
