@@ -68,14 +68,17 @@ def run_mode(mode, args, jobs_per_step, steps, warmup, tin, tout, pool, torch, c
     ctx.reset_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    step_s = []
     for _ in range(steps):
+        ts = time.perf_counter()
         ctx.submit_many(tid, arr)
         ctx.drain()
+        step_s.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = ctx.stats()
     times = ctx.job_times()
-    return ctx, tid, dt, st, times
+    return ctx, tid, dt, st, (times, step_s)
 
 
 def verify(tout, n_jobs, pool_imgs, refs):
@@ -106,9 +109,58 @@ def cpu_baseline(pool_imgs, passes):
     with concurrent.futures.ThreadPoolExecutor(max_workers=ncores) as ex:
         list(ex.map(lambda im: oracle.gauss_sobel(im, want_images=False), work))
     dt = time.perf_counter() - t0
+    single = pool_imgs[:min(16, len(pool_imgs))]
+    t1 = time.perf_counter()
+    for im in single:
+        oracle.gauss_sobel(im, want_images=False)
+    dt1 = time.perf_counter() - t1
     return {"value": round(len(work) / dt, 2), "unit": "jobs/s", "cores": ncores, "kind": "oracle",
             "sample": "%d jobs = %d passes over the 61 pool images (1024x1024 Gaussian->Sobel->threshold->count/sum, "
-                      "float64 C oracle), thread pool of %d" % (len(work), passes, ncores)}
+                      "float64 C oracle), thread pool of %d" % (len(work), passes, ncores),
+            "single_thread_jobs_per_s": round(len(single) / dt1, 2), "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def nearest_rank(values, p):
+    """The p-th percentile by nearest rank: the smallest value with at least
+    p% of the sample at or below it."""
+    v = np.sort(np.asarray(values, dtype=np.float64))
+    if v.size == 0:
+        return None
+    k = max(1, int(np.ceil(p / 100.0 * v.size)))
+    return float(v[k - 1])
+
+
+def link_probe(torch, chunk=16 << 20, rounds=8):
+    """Host-to-device bandwidth of the link with nothing else running: the
+    best of 1, 2 and 4 streams, each copying `rounds` chunks of pinned memory."""
+    best = 0.0
+    src = torch.empty(chunk * 4, dtype=torch.uint8, pin_memory=True)
+    dst = torch.empty(chunk * 4, dtype=torch.uint8, device="cuda")
+    for streams in (1, 2, 4):
+        sts = [torch.cuda.Stream() for _ in range(streams)]
+
+        def burst(n):
+            for _ in range(n):
+                for i, st in enumerate(sts):
+                    with torch.cuda.stream(st):
+                        dst[i * chunk:(i + 1) * chunk].copy_(src[i * chunk:(i + 1) * chunk], non_blocking=True)
+        burst(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        burst(rounds)
+        torch.cuda.synchronize()
+        best = max(best, chunk * streams * rounds / (time.perf_counter() - t0) / 1e9)
+    return round(best, 2)
 
 
 def traffic_for(kernel_name):
@@ -303,6 +355,9 @@ def bench_scan(args, torch):
     # every copy mechanism (it is scored by its fastest)
     configs = [("set", w, st, args.copy) for w in (4, 8, 16) for st in (True, False)]
     configs += [(m, 8, False, cp) for m in ("batch", "sync", "queue") for cp in ("kernels", "async_in")]
+    if args.only:
+        # traced runs: one mode, 8 workers, the given copy mechanism
+        configs = [(args.only, 8, args.only == "set", args.copy)]
     for mode, workers, steal, copy in configs:
         ctx = Context(mode=mode, workers=workers, slots=4 if mode == "set" else 1, stealing=steal,
                       batch_size=min(args.batch, workers) if mode == "batch" else 0, callback=args.callback,
@@ -327,6 +382,11 @@ def bench_scan(args, torch):
                      "stolen": int(st.stolen), "verified": ok})
         log(json.dumps(runs[-1]))
         ctx.close()
+    if args.only:
+        r = runs[0]
+        print(json.dumps({"mode": args.only, "workload": "scan", "jobs_per_s": r["jobs_per_s"], "verified": r["verified"],
+                          "copy": r["copy"]}), flush=True)
+        return
     best = max((r for r in runs if r["mode"] == "set"), key=lambda r: r["jobs_per_s"])
     base = {m: max((r for r in runs if r["mode"] == m), key=lambda r: r["jobs_per_s"]) for m in ("batch", "sync", "queue")}
     line = {"metric": METRIC, "workload": "scan jobs: %d x (8 MiB int32 H2D -> int64 inclusive scan -> 16 MiB D2H)" % J,
@@ -565,11 +625,11 @@ def bench_serve(args, torch):
         h2d_offered = float(np.sum(req["in_bytes"])) / args.serve_seconds / 1e9
         res = {"rate": rate, "requests": int(n), "completed": int(st.completed), "failed": int(st.failed),
                "throughput_jobs_per_s": round(st.completed / span, 1) if span > 0 else None,
-               "p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
-               "p50_image_us": round(float(np.percentile(lat[isimg[ok]], 50)), 1),
-               "p99_image_us": round(float(np.percentile(lat[isimg[ok]], 99)), 1),
-               "p50_vector_us": round(float(np.percentile(lat[~isimg[ok]], 50)), 1),
-               "p99_vector_us": round(float(np.percentile(lat[~isimg[ok]], 99)), 1),
+               "p50_us": round(nearest_rank(lat, 50), 1), "p99_us": round(nearest_rank(lat, 99), 1),
+               "p50_image_us": round(nearest_rank(lat[isimg[ok]], 50), 1),
+               "p99_image_us": round(nearest_rank(lat[isimg[ok]], 99), 1),
+               "p50_vector_us": round(nearest_rank(lat[~isimg[ok]], 50), 1),
+               "p99_vector_us": round(nearest_rank(lat[~isimg[ok]], 99), 1),
                "max_backlog": int(st.max_backlog), "vec_batches": int(st.vec_batches),
                "offered_h2d_GBps": round(h2d_offered, 1), "mem_high_water_GB": round(ctx.stats().mem_high_water / 1e9, 2),
                "drain_after_window_s": round(span - args.serve_seconds, 3)}
@@ -589,7 +649,7 @@ def bench_serve(args, torch):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--jobs", type=int, default=10000, help="jobs per step")
     ap.add_argument("--workers", type=int, default=8)
@@ -701,7 +761,7 @@ def main():
                           "verified": ok2}), flush=True)
         return
     log("SET mode: %d jobs x %d steps" % (args.jobs, args.steps))
-    ctx, tid, dt, st, times = run_mode("set", args, args.jobs, args.steps, args.warmup, tin, tout, pool, torch,
+    ctx, tid, dt, st, (times, step_s) = run_mode("set", args, args.jobs, args.steps, args.warmup, tin, tout, pool, torch,
                                        callback=args.callback)
     n_total = args.jobs * args.steps
     set_jps = n_total / dt
@@ -757,6 +817,9 @@ def main():
         cpu = cpu_baseline(imgs, args.cpu_passes)
 
     h2d = ib * set_jps / 1e9
+    per_step = [args.jobs / t for t in step_s]
+    log("link probe")
+    link_peak = link_probe(torch)
     tl = timeline_from_profile()
     line = {
         "metric": METRIC,
@@ -785,10 +848,16 @@ def main():
         "speedup_vs_queue": round(set_jps / extra["queue"]["jobs_per_s"], 3) if "queue" in extra else None,
         "speedup_vs_sync": round(set_jps / extra["sync"]["jobs_per_s"], 3) if "sync" in extra else None,
         "baselines": extra,
-        "job_latency_us": {"launch_to_done_p50": round(float(np.percentile(lat_dev, 50)), 1),
-                           "launch_to_done_p99": round(float(np.percentile(lat_dev, 99)), 1),
-                           "submit_to_done_p50": round(float(np.percentile(lat_sub, 50)), 1),
-                           "submit_to_done_p99": round(float(np.percentile(lat_sub, 99)), 1)},
+        "job_latency_us": {"launch_to_done_p50": round(nearest_rank(lat_dev, 50), 1),
+                           "launch_to_done_p99": round(nearest_rank(lat_dev, 99), 1),
+                           "submit_to_done_p50": round(nearest_rank(lat_sub, 50), 1),
+                           "submit_to_done_p99": round(nearest_rank(lat_sub, 99), 1)},
+        "steps_jobs_per_s": {"median": round(float(np.median(per_step)), 1), "min": round(float(min(per_step)), 1),
+                             "max": round(float(max(per_step)), 1), "each": [round(float(v), 1) for v in per_step]},
+        "pipeline_roofline": {"bound": "host-to-device link", "achieved_GBps": round(h2d, 2),
+                              "peak_GBps": link_peak, "frac": round(h2d / link_peak, 4) if link_peak else None,
+                              "peak_source": "pinned host-to-device copies alone, best of 1 / 2 / 4 streams, "
+                                             "measured in this run"},
         "sched": {"stolen": int(st.stolen), "inflight_high_water": int(st.inflight_high_water),
                   "host_us_per_job_bind": round(st.host_ns_bind / 1e3 / max(1, st.completed), 2),
                   "host_us_per_job_launch": round(st.host_ns_launch / 1e3 / max(1, st.completed), 2),

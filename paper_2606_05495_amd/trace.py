@@ -15,7 +15,8 @@ Definitions (the paper gives prose definitions; these are the readings):
   (Section 5.3 with Eq. 4): T_measured is the span of the timeline and
   T_ideal the time some engine was busy, so t_schedule = T_measured - T_ideal.
   Compute-idle uses kernels only, copy-idle the host-to-device copies only
-  (DMA copies and k_copy_in kernels).
+  (DMA copies and k_copy_in kernels).  The copy overlap fraction is the time
+  both directions are busy over the time either is.
 * inter-batch overhead (Eq. 3) -- for a batch-synchronised run, the start of
   batch i+1's first copy minus the end of batch i's last copy.
 
@@ -46,6 +47,33 @@ def union_length(intervals: Iterable[Interval]) -> float:
             cur_b = max(cur_b, b)
     if cur_b is not None:
         total += cur_b - cur_a
+    return total
+
+
+def merged(intervals: Iterable[Interval]) -> List[Interval]:
+    """Disjoint, sorted union of the intervals."""
+    out: List[Interval] = []
+    for a, b in sorted((a, b) for a, b in intervals if b > a):
+        if out and a <= out[-1][1]:
+            out[-1] = (out[-1][0], max(out[-1][1], b))
+        else:
+            out.append((a, b))
+    return out
+
+
+def overlap_length(x: Iterable[Interval], y: Iterable[Interval]) -> float:
+    """|union(x) intersect union(y)|."""
+    mx, my = merged(x), merged(y)
+    i = j = 0
+    total = 0.0
+    while i < len(mx) and j < len(my):
+        lo, hi = max(mx[i][0], my[j][0]), min(mx[i][1], my[j][1])
+        if hi > lo:
+            total += hi - lo
+        if mx[i][1] < my[j][1]:
+            i += 1
+        else:
+            j += 1
     return total
 
 
@@ -250,6 +278,9 @@ def analyze_dir(dirpath: str, batch: int = 0) -> dict:
     span = m.get("span") or 0.0
     if cin and span > 0:
         m["h2d_idle_fraction"] = 1.0 - union_length(cin) / (span * 1e3)
+    if cin and cout:
+        # both directions on the link at once, as a share of the time either is
+        m["h2d_d2h_overlap_fraction"] = overlap_length(cin, cout) / union_length(cin + cout)
     if batch and cin and cout:
         g = inter_batch_gaps(cin, cout, batch)
         m["mean_inter_batch_us"] = (sum(g) / len(g) / 1e3) if g else None

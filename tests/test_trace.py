@@ -139,3 +139,12 @@ def test_copy_kernels_give_copy_idle_and_batch_boundaries(tmp_path):
     # input copies busy 40 of the 84-long span
     assert m["h2d_idle_fraction"] == pytest.approx(1 - 40 / 84)
     assert m["h2d_copies"] == 0
+
+
+def test_copy_overlap_fraction():
+    """Input copies [0,10] and [20,30], output copies [5,25]: both directions
+    busy for 5 + 5 = 10 of the 30 that either is."""
+    assert trace.overlap_length([(0, 10), (20, 30)], [(5, 25)]) == pytest.approx(10)
+    assert trace.overlap_length([(0, 10), (5, 12)], [(11, 20)]) == pytest.approx(1)
+    assert trace.overlap_length([(0, 1)], [(2, 3)]) == 0
+    assert trace.merged([(5, 6), (0, 2), (1, 3)]) == [(0, 3), (5, 6)]
