@@ -140,21 +140,31 @@ def nearest_rank(values, p):
     return float(v[k - 1])
 
 
-def link_probe(torch, chunk=16 << 20, rounds=8):
+def link_probe(torch, chunk=64 << 20, total=1 << 30):
     """Host-to-device bandwidth of the link with nothing else running: the
-    best of 1, 2 and 4 streams, each copying `rounds` chunks of pinned memory."""
-    best = 0.0
+    best of 2 and 4 streams, each issuing hipMemcpyAsync copies of 64 MiB
+    from pinned memory (the DMA engines, as the jobs' input copies), 1 GiB in
+    all per setting (less data leaves the ramp in the figure)."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    hip.hipMemcpyAsync.restype = ctypes.c_int
+    h2d = 1  # hipMemcpyHostToDevice
     src = torch.empty(chunk * 4, dtype=torch.uint8, pin_memory=True)
     dst = torch.empty(chunk * 4, dtype=torch.uint8, device="cuda")
-    for streams in (1, 2, 4):
+    best = 0.0
+    for streams in (2, 4):
         sts = [torch.cuda.Stream() for _ in range(streams)]
+        rounds = max(1, total // (chunk * streams))
 
         def burst(n):
             for _ in range(n):
                 for i, st in enumerate(sts):
-                    with torch.cuda.stream(st):
-                        dst[i * chunk:(i + 1) * chunk].copy_(src[i * chunk:(i + 1) * chunk], non_blocking=True)
-        burst(2)
+                    rc = hip.hipMemcpyAsync(dst.data_ptr() + i * chunk, src.data_ptr() + i * chunk, chunk, h2d,
+                                            st.cuda_stream)
+                    if rc != 0:
+                        raise RuntimeError("hipMemcpyAsync failed: %d" % rc)
+        burst(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         burst(rounds)
@@ -856,8 +866,8 @@ def main():
                              "max": round(float(max(per_step)), 1), "each": [round(float(v), 1) for v in per_step]},
         "pipeline_roofline": {"bound": "host-to-device link", "achieved_GBps": round(h2d, 2),
                               "peak_GBps": link_peak, "frac": round(h2d / link_peak, 4) if link_peak else None,
-                              "peak_source": "pinned host-to-device copies alone, best of 1 / 2 / 4 streams, "
-                                             "measured in this run"},
+                              "peak_source": "hipMemcpyAsync of 64 MiB from pinned memory alone, best of 2 / 4 "
+                                             "streams, 1 GiB each, measured in this run"},
         "sched": {"stolen": int(st.stolen), "inflight_high_water": int(st.inflight_high_water),
                   "host_us_per_job_bind": round(st.host_ns_bind / 1e3 / max(1, st.completed), 2),
                   "host_us_per_job_launch": round(st.host_ns_launch / 1e3 / max(1, st.completed), 2),
