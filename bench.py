@@ -670,7 +670,8 @@ def main():
                          "min(2, d))")
     ap.add_argument("--spin-us", type=int, default=0)
     ap.add_argument("--dispatchers", type=int, default=None,
-                    help="SET dispatcher threads (default 1 for the image workload, 4 otherwise)")
+                    help="SET dispatcher threads (default: 1 for the image workload; for the thermal grid 2 up to "
+                         "256^2 and 1 above; 4 otherwise)")
     ap.add_argument("--callback", default=None, choices=["event_chain", "same_stream", "event_poll", "host_flag"],
                     help="SET completion mechanism (default event_poll with async_in copies, host_flag otherwise)")
     ap.add_argument("--copy", default=None, choices=["nodes", "kernels", "async_in"],
@@ -718,12 +719,20 @@ def main():
     if args.callback is None:
         args.callback = "event_poll" if args.copy == "async_in" else "host_flag"
     if args.dispatchers is None:
-        # The image workload needs about 13,600 launches/s, within one thread's
-        # reach; with several threads, launches onto streams that share a
-        # hardware queue interleave, and a graph's wait on its DMA input copy
-        # can then sit between another job's kernels (traced: 50-66 us gaps
-        # inside jobs with 4 threads, none with 1, at the same jobs/s).
-        args.dispatchers = 1 if args.workload == "images" else 4
+        # As few dispatcher threads as the launch rate allows: with several,
+        # launches onto streams that share a hardware queue interleave, and a
+        # graph's wait on its DMA input copy can then sit between another
+        # job's kernels (traced: 50-66 us gaps inside jobs with 4 threads,
+        # none with 1).  One thread sustains about 30k launches/s of the
+        # 18-node thermal-grid graph: enough for 1024^2 images (13.6k jobs/s)
+        # and 512^2 grids (22k), not for 256^2 grids (39k), which take two.
+        # Per-job vector dispatch is host-bound and keeps four.
+        if args.workload == "images":
+            args.dispatchers = 1
+        elif args.workload == "hotspot":
+            args.dispatchers = 1 if args.hot_side >= 512 else 2
+        else:
+            args.dispatchers = 4
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the job path shards by running one independent scheduler per GPU, "
