@@ -791,10 +791,10 @@ def test_library_scan_stage_timing(torch_gpu):
 
 
 # ------------------------------------------------------------------ thermal grid (iterative stencil)
-def _run_hotspot(mode, grids, steps, workers=4, slots=4, **kw):
+def _run_hotspot(mode, grids, steps, workers=4, slots=4, copy="kernels", **kw):
     h, w = grids[0][0].shape
     ctx = Context(mode=mode, workers=workers, slots=slots, **kw)
-    tid = ctx.define("hotspot", width=w, height=h, max_n=steps)
+    tid = ctx.define("hotspot", width=w, height=h, max_n=steps, copy=copy)
     ib, ob = ctx.in_bytes(tid), ctx.out_bytes(tid)
     assert ib == 8 * h * w and ob == 64 + 4 * h * w
     istride, ostride = _up64(ib), _up64(ob)
@@ -854,3 +854,48 @@ def test_hotspot_pins_on_gpu(torch_gpu):
     amb = (np.full((h, w), 300.0, np.float32), np.zeros((h, w), np.float32))
     o = _run_hotspot("set", [amb], 32)[0]
     assert np.all(o == np.float32(300.0))
+
+
+# ------------------------------------------------------------------ the benchmark's configurations at full size
+BENCH_DMA = dict(callback="event_poll", inflight=1)
+
+
+def test_bench_config_images_full_size(torch_gpu):
+    """1024^2 images as the benchmark runs them: 8 workers x 16 slots, DMA input copies, one job in flight per
+    worker, event polling, one dispatcher thread; 24 jobs over 8 images, each image's result identical in
+    every slot it ran in."""
+    _say("bench config: images 1024^2")
+    imgs = [synth.normal_image(0, k) for k in range(8)]
+    outs, _ = _run_images("set", "gauss_sobel", imgs * 3, np.float32, workers=8, slots=16, flags=0,
+                          copy="async_in", dispatchers=1, **BENCH_DMA)
+    for k, o in enumerate(outs):
+        ref = oracle.gauss_sobel(imgs[k % 8], want_images=False)
+        assert abs(int(o[64:68].view(np.uint32)[0]) - ref["count"]) <= ref["band"]
+        assert abs(float(o[68:72].view(np.float32)[0]) - ref["sum"]) <= 1e-5 * abs(ref["sum"])
+        assert np.array_equal(o[64:72], outs[k % 8][64:72])
+
+
+def test_bench_config_scan_full_size(torch_gpu):
+    """2^21-element scans as the benchmark runs them: 8 workers x 4 slots, DMA input copies, one job in flight
+    per worker, event polling, 4 dispatcher threads, stealing on."""
+    _say("bench config: scan 2^21")
+    inputs = [synth.scan_input(0, k) for k in range(4)] * 3
+    res = _run_scan("set", inputs, max_n=1 << 21, workers=8, slots=4, copy="async_in", dispatchers=4, **BENCH_DMA)
+    for v, r in zip(inputs, res):
+        assert np.array_equal(r, oracle.scan(v))
+
+
+@pytest.mark.parametrize("side,dispatchers", [(256, 2), (512, 1)])
+def test_bench_config_hotspot_full_size(torch_gpu, side, dispatchers):
+    """Thermal grids as the benchmark runs them: 16 steps, 8 workers x 16 slots, DMA input copies, one job in
+    flight per worker, event polling, 2 dispatcher threads at 256^2 and 1 at 512^2."""
+    _say("bench config: hotspot", side)
+    grids = [synth.hotspot_input(0, k, side, side) for k in range(4)]
+    outs = _run_hotspot("set", grids * 4, 16, workers=8, slots=16, copy="async_in", dispatchers=dispatchers,
+                        **BENCH_DMA)
+    for i, o in enumerate(outs):
+        if i < 4:
+            t0, p = grids[i]
+            ref = oracle.hotspot(t0, p, 16)
+            assert np.max(np.abs(o - ref)) <= oracle.hotspot_tolerance(ref, 16)
+        assert np.array_equal(o, outs[i % 4])
