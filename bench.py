@@ -825,7 +825,7 @@ def main():
                 c2.close()
                 ok2, bad2 = verify(tout, args.jobs, imgs, refs)
                 per[key] = {"jobs_per_s": round(args.jobs * args.baseline_steps / dt2, 1), "verified": ok2,
-                            "host_sync_ms": round(st2.host_ns_sync / 1e6, 2)}
+                            "wrong_jobs": int(bad2), "host_sync_ms": round(st2.host_ns_sync / 1e6, 2)}
             best = max(per, key=lambda c: per[c]["jobs_per_s"])
             extra[mode] = {"jobs_per_s": per[best]["jobs_per_s"], "copy": best,
                            "verified": all(v["verified"] for v in per.values()), "by_copy": per}
@@ -859,6 +859,7 @@ def main():
                    "input_copy_streams": args.input_copy_streams, "inflight_per_worker": args.inflight,
                    "image_pool": pool},
         "verified": bool(set_ok),
+        "wrong_jobs": int(set_bad),
         "h2d_GBps": round(h2d, 2),
         "batch_sync_jobs_per_s": extra.get("batch", {}).get("jobs_per_s"),
         "speedup_vs_batch_sync": round(set_jps / extra["batch"]["jobs_per_s"], 3) if "batch" in extra else None,
