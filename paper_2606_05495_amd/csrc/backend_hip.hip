@@ -655,14 +655,19 @@ class HipBackend : public Backend {
                              (float*)(b + L.scratch + q)};
         sl.sobelf = SobelFinalArgs{(const uint32_t*)(b + L.scratch), (const float*)(b + L.scratch + q), nb,
                                    (uint32_t*)(b + L.out + 64), (float*)(b + L.out + 68), sc};
-        const bool win = image_window_path(w);
-        const void* gk = !win                       ? (const void*)&k_gauss5_f32
-                         : gauss_win_rows(h, w) == 2 ? (const void*)&k_gauss5_win_f32<2>
-                                                     : (const void*)&k_gauss5_win_f32<4>;
+        const bool win = image_window_path(w), full = window_full_width(w);
+        const int gr = gauss_win_rows(h, w), sr = sobel_win_rows(h, w);
+        const void* gk = !win   ? (const void*)&k_gauss5_f32
+                         : full ? (gr == 2 ? (const void*)&k_gauss5_win_f32<2, true>
+                                           : (const void*)&k_gauss5_win_f32<4, true>)
+                                : (gr == 2 ? (const void*)&k_gauss5_win_f32<2, false>
+                                           : (const void*)&k_gauss5_win_f32<4, false>);
         stage(gk, to_dim3(gauss_grid(h, w)), &sl.gauss);
-        const void* sk = !win                        ? (const void*)&k_sobel_thresh_f32
-                         : sobel_win_rows(h, w) == 2 ? (const void*)&k_sobel_thresh_win_f32<2>
-                                                     : (const void*)&k_sobel_thresh_win_f32<4>;
+        const void* sk = !win   ? (const void*)&k_sobel_thresh_f32
+                         : full ? (sr == 2 ? (const void*)&k_sobel_thresh_win_f32<2, true>
+                                           : (const void*)&k_sobel_thresh_win_f32<4, true>)
+                                : (sr == 2 ? (const void*)&k_sobel_thresh_win_f32<2, false>
+                                           : (const void*)&k_sobel_thresh_win_f32<4, false>);
         stage(sk, to_dim3(sg), &sl.sobel);
         stage((const void*)&k_sobel_final, dim3(1), &sl.sobelf);
         break;
@@ -691,13 +696,14 @@ class HipBackend : public Backend {
         // step writes the output payload, the others alternate b1 / b2
         const int K = (int)t.max_n;
         const float* P = (const float*)(b + L.in) + (size_t)h * w;
-        const bool win = image_window_path(w);
+        const void* hk = !image_window_path(w)  ? (const void*)&k_hotspot_f32
+                         : window_full_width(w) ? (const void*)&k_hotspot_win_f32<true>
+                                                : (const void*)&k_hotspot_win_f32<false>;
         for (int k = 0; k < K; ++k) {
           const float* src = (k == 0) ? (const float*)(b + L.in) : sl.hot[k - 1].tout;
           float* dst = (k == K - 1) ? (float*)(b + L.out + 64) : (float*)(b + ((k % 2 == 0) ? L.b1 : L.b2));
           sl.hot[k] = HotspotArgs{src, P, dst, h, w, k == 0 ? 1 : 0, sc.hdr, JobScalars{}};
-          stage(win ? (const void*)&k_hotspot_win_f32 : (const void*)&k_hotspot_f32, to_dim3(hotspot_grid(h, w)),
-                &sl.hot[k]);
+          stage(hk, to_dim3(hotspot_grid(h, w)), &sl.hot[k]);
         }
         sl.je = JobEndArgs{sc};
         stage((const void*)&k_job_end, dim3(1), &sl.je);

@@ -329,20 +329,46 @@ __device__ inline void xcd_tile(unsigned& bx, unsigned& by) {
 }
 
 // Whole-wave shifts by one lane (DPP wave_shr:1 / wave_shl:1, a VALU move
-// instead of an LDS permute): up1 gives lane i the value of lane i-1, down1
-// the value of lane i+1.  Lanes 0 and 63 get 0 and are overwritten by the
-// caller.
-__device__ inline float up1(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+// instead of an LDS permute).  from_left gives lane i the value of lane i-1,
+// from_right the value of lane i+1.  With bound_ctrl off, the lane whose
+// source lies outside the wave (lane 0 for from_left, lane 63 for
+// from_right) keeps the old value, which is its own `edge`: the tile's halo
+// column arrives without a per-lane select.
+__device__ inline float from_left(float v, float edge) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x138, 0xf, 0xf, false));
 }
-__device__ inline float down1(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+__device__ inline float from_right(float v, float edge) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
-__device__ inline float4 load_row4(const float* row, int x, bool in4, int wm) {
-  if (in4) return *reinterpret_cast<const float4*>(row + x);
-  const float e = row[wm];  // lanes past the right edge hold the replicated border
-  return make_float4(e, e, e, e);
+// Register-window geometry of one lane.  The wave index goes through
+// readfirstlane, so the wave's rows (and every row address, clamp and bounds
+// test derived from them) live in scalar registers; a load or store is then a
+// scalar row base plus the lane's 32-bit byte offset.  FULL: the width is a
+// multiple of 256, so every lane's 4 columns lie inside the image.  Otherwise
+// lanes past the right edge load the last 4 columns and keep only the border
+// column (replicated), and store nothing.
+template <bool FULL>
+struct WinLane {
+  int lane, y0;       // y0: first output row of the wave (wave-uniform)
+  unsigned x;         // first of the lane's 4 columns
+  unsigned xl;        // column the lane loads from
+  bool past;          // lane lies beyond the right edge (never when FULL)
+  __device__ WinLane(int w, unsigned bx, unsigned by, int rows) {
+    lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    y0 = ((int)by * 4 + wave) * rows;
+    x = bx * kWinCols + 4u * lane;
+    past = FULL ? false : x >= (unsigned)w;
+    xl = past ? (unsigned)w - 4u : x;
+  }
+  __device__ float4 load4(const float* row) const {
+    const float4 t = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(row) + xl * 4u);
+    return past ? make_float4(t.w, t.w, t.w, t.w) : t;
+  }
+};
+__device__ inline float load1(const float* row, unsigned col) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(row) + col * 4u);
 }
 
 // Separable 5-tap Gaussian on the register window, vertical pass first: each
@@ -351,28 +377,25 @@ __device__ inline float4 load_row4(const float* row, int x, bool in4, int wm) {
 // the neighbouring columns' vertical results by lane shift.  Vertical first
 // costs (R + 4)/R fewer lane shifts and FMAs than horizontal first, since the
 // horizontal pass then runs on R rows instead of R + 4.
-template <int R>
+template <int R, bool FULL>
 __global__ __launch_bounds__(kBlock) void k_gauss5_win_f32(GaussArgs a) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   unsigned bx, by;
   xcd_tile(bx, by);
   if (bx == 0 && by == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
   const int w = a.w, h = a.h, wm = w - 1, hm = h - 1;
+  const WinLane<FULL> L(w, bx, by, R);
   const int xw = (int)bx * kWinCols;
-  const int x = xw + 4 * lane;
-  const int y0 = ((int)by * 4 + wave) * R;
-  const bool in4 = x + 3 <= wm;
   // lane 0 needs columns xw-2, xw-1; lane 63 needs xw+256, xw+257
-  const int hx0 = clampi(lane == 0 ? xw - 2 : xw + kWinCols, 0, wm);
-  const int hx1 = clampi(lane == 0 ? xw - 1 : xw + kWinCols + 1, 0, wm);
+  const unsigned hx0 = clampi(L.lane == 0 ? xw - 2 : xw + kWinCols, 0, wm);
+  const unsigned hx1 = clampi(L.lane == 0 ? xw - 1 : xw + kWinCols + 1, 0, wm);
   float4 v[R + 4];
   float e0[R + 4], e1[R + 4];
 #pragma unroll
   for (int r = 0; r < R + 4; ++r) {
-    const float* row = a.in + (size_t)clampi(y0 + r - 2, 0, hm) * w;
-    v[r] = load_row4(row, x, in4, wm);
-    e0[r] = row[hx0];
-    e1[r] = row[hx1];
+    const float* row = a.in + (size_t)clampi(L.y0 + r - 2, 0, hm) * w;
+    v[r] = L.load4(row);
+    e0[r] = load1(row, hx0);
+    e1[r] = load1(row, hx1);
   }
   const float g0 = a.g0, g1 = a.g1, g2 = a.g2;
   auto vert = [&](float t0, float t1, float t2, float t3, float t4) {
@@ -390,26 +413,20 @@ __global__ __launch_bounds__(kBlock) void k_gauss5_win_f32(GaussArgs a) {
     const float c3 = vert(v[r].w, v[r + 1].w, v[r + 2].w, v[r + 3].w, v[r + 4].w);
     const float f0 = vert(e0[r], e0[r + 1], e0[r + 2], e0[r + 3], e0[r + 4]);
     const float f1 = vert(e1[r], e1[r + 1], e1[r + 2], e1[r + 3], e1[r + 4]);
-    float l2 = up1(c2), l1 = up1(c3);
-    float r1 = down1(c0), r2 = down1(c1);
-    if (lane == 0) {
-      l2 = f0;
-      l1 = f1;
-    }
-    if (lane == 63) {
-      r1 = f0;
-      r2 = f1;
-    }
-    const float c[8] = {l2, l1, c0, c1, c2, c3, r1, r2};
+    const float c[8] = {from_left(c2, f0), from_left(c3, f1), c0, c1, c2, c3, from_right(c0, f0), from_right(c1, f1)};
     float o[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) o[j] = vert(c[j], c[j + 1], c[j + 2], c[j + 3], c[j + 4]);
-    const int y = y0 + r;
-    if (y < h && in4) *reinterpret_cast<float4*>(a.out + (size_t)y * w + x) = make_float4(o[0], o[1], o[2], o[3]);
+    const int y = L.y0 + r;
+    if (y < h && !L.past)
+      *reinterpret_cast<float4*>(reinterpret_cast<char*>(a.out + (size_t)y * w) + L.x * 4u) =
+          make_float4(o[0], o[1], o[2], o[3]);
   }
 }
-template __global__ void k_gauss5_win_f32<2>(GaussArgs a);
-template __global__ void k_gauss5_win_f32<4>(GaussArgs a);
+template __global__ void k_gauss5_win_f32<2, true>(GaussArgs a);
+template __global__ void k_gauss5_win_f32<4, true>(GaussArgs a);
+template __global__ void k_gauss5_win_f32<2, false>(GaussArgs a);
+template __global__ void k_gauss5_win_f32<4, false>(GaussArgs a);
 
 // Sobel with the same window, vertical pass first.  The two 3x3 kernels
 // factor into a vertical and a horizontal 3-tap pass: gx = horizontal
@@ -417,34 +434,31 @@ template __global__ void k_gauss5_win_f32<4>(GaussArgs a);
 // vertical difference.  Each lane forms both vertical terms for its 4 columns
 // (lanes 0 and 63 also for the column beyond the wave's edge), then takes the
 // neighbouring columns' terms by DPP lane shift.  Mask bytes of a lane go out
-// as one 4-byte store; each wave writes its own (count, sum) partial, so there
-// is no block-wide barrier, and the final kernel combines the partials in a
-// fixed order.
-template <int R>
+// as one 4-byte store, and their popcount is the lane's count for the row;
+// each wave writes its own (count, sum) partial, so there is no block-wide
+// barrier, and the final kernel combines the partials in a fixed order.
+template <int R, bool FULL>
 __global__ __launch_bounds__(kBlock) void k_sobel_thresh_win_f32(SobelArgs a) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   unsigned bx, by;
   xcd_tile(bx, by);
   const int w = a.w, h = a.h, wm = w - 1, hm = h - 1;
+  const WinLane<FULL> L(w, bx, by, R);
   const int xw = (int)bx * kWinCols;
-  const int x = xw + 4 * lane;
-  const int y0 = ((int)by * 4 + wave) * R;
-  const bool in4 = x + 3 <= wm;
-  const int hx = clampi(lane == 0 ? xw - 1 : xw + kWinCols, 0, wm);
+  const unsigned hx = clampi(L.lane == 0 ? xw - 1 : xw + kWinCols, 0, wm);
   float4 v[R + 2];
   float e[R + 2];
 #pragma unroll
   for (int r = 0; r < R + 2; ++r) {
-    const float* row = a.blur + (size_t)clampi(y0 + r - 1, 0, hm) * w;
-    v[r] = load_row4(row, x, in4, wm);
-    e[r] = row[hx];
+    const float* row = a.blur + (size_t)clampi(L.y0 + r - 1, 0, hm) * w;
+    v[r] = L.load4(row);
+    e[r] = load1(row, hx);
   }
   const float thr = a.thr;
   float sum = 0.f;
   uint32_t cnt = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int y = y0 + r;
+    const int y = L.y0 + r;
     float vs[4], vd[4];  // vertical smoothing (above + 2*centre + below) and difference (below - above)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -453,45 +467,36 @@ __global__ __launch_bounds__(kBlock) void k_sobel_thresh_win_f32(SobelArgs a) {
       vd[j] = t2 - t0;
     }
     const float es = (e[r] + 2.f * e[r + 1]) + e[r + 2], ed = e[r + 2] - e[r];
-    float ls = up1(vs[3]), ld = up1(vd[3]), rs = down1(vs[0]), rd = down1(vd[0]);
-    if (lane == 0) {
-      ls = es;
-      ld = ed;
-    }
-    if (lane == 63) {
-      rs = es;
-      rd = ed;
-    }
-    const float cs[6] = {ls, vs[0], vs[1], vs[2], vs[3], rs};
-    const float cd[6] = {ld, vd[0], vd[1], vd[2], vd[3], rd};
-    uint32_t packed = 0, rc = 0;
+    const float cs[6] = {from_left(vs[3], es), vs[0], vs[1], vs[2], vs[3], from_right(vs[0], es)};
+    const float cd[6] = {from_left(vd[3], ed), vd[0], vd[1], vd[2], vd[3], from_right(vd[0], ed)};
+    uint32_t packed = 0;
     float rsum = 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float gx = cs[j + 2] - cs[j];
       const float gy = (cd[j] + 2.f * cd[j + 1]) + cd[j + 2];
       const float mag = sqrt_hw(gx * gx + gy * gy);
-      const uint32_t on = mag > thr ? 1u : 0u;
-      packed |= on << (8 * j);
-      rc += on;
+      packed |= (mag > thr ? 1u : 0u) << (8 * j);
       rsum += mag;
     }
-    if (y < h && in4) {
-      *reinterpret_cast<uint32_t*>(a.mask + (size_t)y * w + x) = packed;
-      cnt += rc;
+    if (y < h && !L.past) {
+      *reinterpret_cast<uint32_t*>(a.mask + (size_t)y * w + L.x) = packed;
+      cnt += __builtin_popcount(packed);
       sum += rsum;
     }
   }
   const float ws = wave_sum_f32(sum);
   const uint32_t wc = wave_sum_u32(cnt);
-  if (lane == 0) {
-    const unsigned part = (by * gridDim.x + bx) * 4 + wave;
+  if (L.lane == 0) {
+    const unsigned part = (by * gridDim.x + bx) * 4 + (threadIdx.x >> 6);
     a.psum[part] = ws;
     a.pcount[part] = wc;
   }
 }
-template __global__ void k_sobel_thresh_win_f32<2>(SobelArgs a);
-template __global__ void k_sobel_thresh_win_f32<4>(SobelArgs a);
+template __global__ void k_sobel_thresh_win_f32<2, true>(SobelArgs a);
+template __global__ void k_sobel_thresh_win_f32<4, true>(SobelArgs a);
+template __global__ void k_sobel_thresh_win_f32<2, false>(SobelArgs a);
+template __global__ void k_sobel_thresh_win_f32<4, false>(SobelArgs a);
 
 // ------------------------------------------------------------------ thermal grid step
 // T' = T + CP*P + CY*(N + S - 2T) + CX*(W + E - 2T) + CZ*(T_AMB - T), a
@@ -508,44 +513,43 @@ __device__ inline float step(float t, float p, float n, float s, float w, float 
 // Register window as for the image stages: a lane owns 4 columns, a wave 256
 // columns x kHotWinRows rows with its rows of T (plus one above and below)
 // and of P loaded before the first result.
+template <bool FULL>
 __global__ __launch_bounds__(kBlock) void k_hotspot_win_f32(HotspotArgs a) {
   constexpr int R = kHotWinRows;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   unsigned bx, by;
   xcd_tile(bx, by);
   if (a.first && bx == 0 && by == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
   const int w = a.w, h = a.h, wm = w - 1, hm = h - 1;
+  const WinLane<FULL> L(w, bx, by, R);
   const int xw = (int)bx * kWinCols;
-  const int x = xw + 4 * lane;
-  const int y0 = ((int)by * 4 + wave) * R;
-  const bool in4 = x + 3 <= wm;
-  const int hx = clampi(lane == 0 ? xw - 1 : xw + kWinCols, 0, wm);
+  const unsigned hx = clampi(L.lane == 0 ? xw - 1 : xw + kWinCols, 0, wm);
   float4 v[R + 2], pv[R];
   float e[R + 2];
 #pragma unroll
   for (int r = 0; r < R + 2; ++r) {
-    const float* row = a.tin + (size_t)clampi(y0 + r - 1, 0, hm) * w;
-    v[r] = load_row4(row, x, in4, wm);
-    e[r] = row[hx];
+    const float* row = a.tin + (size_t)clampi(L.y0 + r - 1, 0, hm) * w;
+    v[r] = L.load4(row);
+    e[r] = load1(row, hx);
   }
 #pragma unroll
-  for (int r = 0; r < R; ++r) pv[r] = load_row4(a.p + (size_t)clampi(y0 + r, 0, hm) * w, x, in4, wm);
+  for (int r = 0; r < R; ++r) pv[r] = L.load4(a.p + (size_t)clampi(L.y0 + r, 0, hm) * w);
 #pragma unroll
   for (int r = 1; r <= R; ++r) {
-    const int y = y0 + r - 1;
-    float left = up1(v[r].w), right = down1(v[r].x);
-    if (lane == 0) left = e[r];
-    if (lane == 63) right = e[r];
-    const float c[6] = {left, v[r].x, v[r].y, v[r].z, v[r].w, right};
+    const int y = L.y0 + r - 1;
+    const float c[6] = {from_left(v[r].w, e[r]), v[r].x, v[r].y, v[r].z, v[r].w, from_right(v[r].x, e[r])};
     const float n4[4] = {v[r - 1].x, v[r - 1].y, v[r - 1].z, v[r - 1].w};
     const float s4[4] = {v[r + 1].x, v[r + 1].y, v[r + 1].z, v[r + 1].w};
     const float p4[4] = {pv[r - 1].x, pv[r - 1].y, pv[r - 1].z, pv[r - 1].w};
     float o[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) o[j] = hotspot::step(c[j + 1], p4[j], n4[j], s4[j], c[j], c[j + 2]);
-    if (y < h && in4) *reinterpret_cast<float4*>(a.tout + (size_t)y * w + x) = make_float4(o[0], o[1], o[2], o[3]);
+    if (y < h && !L.past)
+      *reinterpret_cast<float4*>(reinterpret_cast<char*>(a.tout + (size_t)y * w) + L.x * 4u) =
+          make_float4(o[0], o[1], o[2], o[3]);
   }
 }
+template __global__ void k_hotspot_win_f32<true>(HotspotArgs a);
+template __global__ void k_hotspot_win_f32<false>(HotspotArgs a);
 
 // Widths that are not a multiple of 4: one cell per thread.
 __global__ __launch_bounds__(kBlock) void k_hotspot_f32(HotspotArgs a) {

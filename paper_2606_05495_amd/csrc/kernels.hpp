@@ -162,6 +162,7 @@ struct HotspotArgs {
   DevSlotHdr* hdr;
   JobScalars js;
 };
+template <bool FULL>
 __global__ void k_hotspot_win_f32(HotspotArgs a);
 __global__ void k_hotspot_f32(HotspotArgs a);
 
@@ -170,10 +171,10 @@ __global__ void k_div9_u16_u8(Div9Args a);
 __global__ void k_hist256_u8(HistArgs a);
 __global__ void k_hist256_final(HistFinalArgs a);
 __global__ void k_gauss5_f32(GaussArgs a);
-template <int R>
+template <int R, bool FULL>
 __global__ void k_gauss5_win_f32(GaussArgs a);
 __global__ void k_sobel_thresh_f32(SobelArgs a);
-template <int R>
+template <int R, bool FULL>
 __global__ void k_sobel_thresh_win_f32(SobelArgs a);
 __global__ void k_sobel_final(SobelFinalArgs a);
 __global__ void k_saxpy_tanh_sum_f32(VecArgs a);

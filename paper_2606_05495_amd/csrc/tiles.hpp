@@ -55,12 +55,14 @@ inline unsigned hist_blocks(int64_t npix) {
 // Float images whose width is a multiple of 4 take the register-window
 // kernels: a lane owns 4 adjacent columns (16-byte loads and stores), a wave
 // 256 columns x R rows, a block 4 waves stacked vertically.  The Gaussian
-// takes R = 2 up to 2048^2 pixels and Sobel up to 1024^2, both R = 4 above
+// takes R = 2 below 1024^2 pixels and Sobel up to 1024^2, both R = 4 above
 // (more blocks in flight pay on the smaller images, fewer re-read halo rows on
 // the larger).  Other widths take the LDS-tile kernels.
 constexpr int kWinCols = 256;                 // columns per wave (and per block)
 inline bool image_window_path(int w) { return w > 0 && (w % 4) == 0; }
-inline int gauss_win_rows(int h, int w) { return (int64_t)h * w <= (int64_t)2048 * 2048 ? 2 : 4; }
+// Every tile of the window path full width: no lane lies past the right edge.
+inline bool window_full_width(int w) { return w > 0 && (w % kWinCols) == 0; }
+inline int gauss_win_rows(int h, int w) { return (int64_t)h * w < (int64_t)1024 * 1024 ? 2 : 4; }
 inline int sobel_win_rows(int h, int w) { return (int64_t)h * w <= (int64_t)1024 * 1024 ? 2 : 4; }
 inline Grid3 window_grid(int h, int w, int rows_per_wave) {
   const int rows = 4 * rows_per_wave;
