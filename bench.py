@@ -414,7 +414,7 @@ def bench_scan(args, torch):
 
 def bench_sweep(args, torch):
     """Worker-count sweep (the batch size b of Section 5.2): per-job vector jobs
-    (the configs[2] length distribution, device-resident inputs, two kernels and
+    (the uneven vector workload's length distribution, device-resident inputs, two kernels and
     a 68-byte D2H each) through SET (b workers, 16 slots each, min(4, b)
     dispatcher threads), batch-sync (one graph of b chains per batch) and the
     queue model (b workers), at b = 1 .. 64.  Prints one JSON line."""
@@ -433,8 +433,13 @@ def bench_sweep(args, torch):
             for i in range(0, J, max(1, J // 20))}
     tout, nout = pinned(128 * J)
     rows = []
+    modes = ("set", "batch", "queue")
+    if args.only:
+        if args.only not in modes:
+            raise SystemExit("--only for the sweep takes set, batch or queue")
+        modes = (args.only,)
     for b in [int(v) for v in args.sweep_b.split(",")]:
-        for mode in ("set", "batch", "queue"):
+        for mode in modes:
             c = Context(mode=mode, workers=b, slots=16 if mode == "set" else 1,
                         batch_size=b if mode == "batch" else 0, callback=args.callback,
                         dispatchers=min(args.dispatchers, b), inflight=args.inflight)
@@ -465,8 +470,8 @@ def bench_sweep(args, torch):
     line = {"metric": METRIC, "workload": "worker-count sweep, %d per-job vector jobs per point" % J,
             "unit": "jobs/s", "n_gpus": 1, "dtype": "f32", "data": "synthetic", "higher_is_better": True,
             "vs_baseline": None, "table": table,
-            "set_over_batch": {b: round(t["set"] / t["batch"], 3) for b, t in table.items()},
-            "set_over_queue": {b: round(t["set"] / t["queue"], 3) for b, t in table.items()},
+            "set_over_batch": {b: round(t["set"] / t["batch"], 3) for b, t in table.items() if len(t) == 3},
+            "set_over_queue": {b: round(t["set"] / t["queue"], 3) for b, t in table.items() if len(t) == 3},
             "runs": rows, "config": {"callback": args.callback, "dispatchers": args.dispatchers, "copy": args.copy}}
     print(json.dumps(line), flush=True)
 

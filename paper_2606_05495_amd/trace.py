@@ -251,10 +251,29 @@ def load_rocprof(dirpath: str, kernel_filter=None, copy_streams=None):
     return kernels, names, h2d, d2h, streams
 
 
-def analyze_dir(dirpath: str, batch: int = 0) -> dict:
+def _clip(intervals, keep, t0, t1):
+    """Intervals overlapping [t0, t1], clipped to it, with the parallel lists
+    in `keep` filtered alike."""
+    idx = [i for i, (a, b) in enumerate(intervals) if b > t0 and a < t1]
+    return ([(max(intervals[i][0], t0), min(intervals[i][1], t1)) for i in idx],
+            [[lst[i] for i in idx] for lst in keep])
+
+
+def analyze_dir(dirpath: str, batch: int = 0, library_window: bool = False) -> dict:
+    """Timeline metrics of a rocprofv3 trace directory.  library_window: the
+    span runs from the first to the last of the library's own kernels only,
+    and every other kernel or copy is clipped to it (for programs whose set-up
+    uploads or host-side work come before the jobs)."""
     cs = {}
     kernels, names, h2d, d2h, streams = load_rocprof(
         dirpath, kernel_filter=lambda n: "setrt" in n or "copyBuffer" in n, copy_streams=cs)
+    if library_window:
+        lib = [iv for iv, n in zip(kernels, names) if "setrt" in n]
+        if lib:
+            t0, t1 = min(a for a, _ in lib), max(b for _, b in lib)
+            kernels, (names, streams) = _clip(kernels, [names, streams], t0, t1)
+            h2d, (cs["h2d"],) = _clip(h2d, [cs.get("h2d", [])], t0, t1)
+            d2h, (cs["d2h"],) = _clip(d2h, [cs.get("d2h", [])], t0, t1)
     m = timeline_metrics(kernels, h2d, d2h)
     # DMA copies join their stream's sequence (as "dma_copy_*"), so a job whose
     # input went by DMA still reads as [input copy, stages, output copy]; the
@@ -357,8 +376,9 @@ def timeline_record(summaries: dict, command: str) -> dict:
     return {"csrc_sha256": csrc_digest(), "command": command, "unit": "us", "modes": modes}
 
 
-def summarize(dirpath: str, kernel: str = "", batch: int = 0) -> dict:
-    out = {"timeline": analyze_dir(dirpath, batch=batch), "kernel_stats": kernel_stats(dirpath)}
+def summarize(dirpath: str, kernel: str = "", batch: int = 0, library_window: bool = False) -> dict:
+    out = {"timeline": analyze_dir(dirpath, batch=batch, library_window=library_window),
+           "kernel_stats": kernel_stats(dirpath)}
     if kernel:
         out["isolated"] = {kernel: isolated_run(dirpath, kernel)}
     return out
@@ -377,8 +397,10 @@ if __name__ == "__main__":
         ap.add_argument("dir")
         ap.add_argument("--kernel", default="")
         ap.add_argument("--batch", type=int, default=0)
+        ap.add_argument("--library-window", action="store_true",
+                        help="span from the first to the last library kernel only")
         a = ap.parse_args()
-        print(json.dumps(summarize(a.dir, a.kernel, a.batch), indent=1))
+        print(json.dumps(summarize(a.dir, a.kernel, a.batch, a.library_window), indent=1))
     else:
         b = int(sys.argv[2]) if len(sys.argv) > 2 else 0
         print(json.dumps(analyze_dir(sys.argv[1], batch=b), indent=1))

@@ -148,3 +148,30 @@ def test_copy_overlap_fraction():
     assert trace.overlap_length([(0, 10), (5, 12)], [(11, 20)]) == pytest.approx(1)
     assert trace.overlap_length([(0, 1)], [(2, 3)]) == 0
     assert trace.merged([(5, 6), (0, 2), (1, 3)]) == [(0, 3), (5, 6)]
+
+
+def test_library_window_drops_setup_before_the_jobs(tmp_path):
+    """A runtime copy kernel and a DMA copy long before the library's first
+    kernel (a program's set-up uploads) count in the plain span; with the
+    library window the span runs from the first to the last library kernel,
+    and a copy overlapping the window's start is clipped to it."""
+    k = tmp_path / "run_kernel_trace.csv"
+    c = tmp_path / "run_memory_copy_trace.csv"
+    krows = [(0, 5, "__amd_rocclr_copyBuffer"), (100, 110, "setrt::k_a"), (112, 120, "setrt::k_b"),
+             (130, 140, "setrt::k_a")]
+    with open(k, "w") as fh:
+        fh.write('"Kind","Stream_Id","Kernel_Name","Start_Timestamp","End_Timestamp"\n')
+        for a, b, n in krows:
+            fh.write('"KERNEL_DISPATCH",1,"%s",%d,%d\n' % (n, a, b))
+    with open(c, "w") as fh:
+        fh.write('"Kind","Direction","Stream_Id","Start_Timestamp","End_Timestamp"\n')
+        for a, b in ((10, 20), (95, 104)):
+            fh.write('"MEMORY_COPY","MEMORY_COPY_HOST_TO_DEVICE",1,%d,%d\n' % (a, b))
+    plain = trace.analyze_dir(str(tmp_path))
+    # busy [0,5] [10,20] [95,110] [112,120] [130,140] = 5+10+15+8+10 = 48 of 140
+    assert plain["gpu_idle_fraction"] == pytest.approx(1 - 48 / 140)
+    win = trace.analyze_dir(str(tmp_path), library_window=True)
+    # window [100,140]: busy [100,110] (copy clipped into it) [112,120] [130,140] = 28 of 40
+    assert win["span"] == pytest.approx(40 / 1e3)
+    assert win["gpu_idle_fraction"] == pytest.approx(1 - 28 / 40)
+    assert win["h2d_copies"] == 1
