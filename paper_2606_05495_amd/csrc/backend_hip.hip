@@ -657,17 +657,15 @@ class HipBackend : public Backend {
                                    (uint32_t*)(b + L.out + 64), (float*)(b + L.out + 68), sc};
         const bool win = image_window_path(w), full = window_full_width(w);
         const int gr = gauss_win_rows(h, w), sr = sobel_win_rows(h, w);
-        const void* gk = !win   ? (const void*)&k_gauss5_f32
-                         : full ? (gr == 2 ? (const void*)&k_gauss5_win_f32<2, true>
-                                           : (const void*)&k_gauss5_win_f32<4, true>)
-                                : (gr == 2 ? (const void*)&k_gauss5_win_f32<2, false>
-                                           : (const void*)&k_gauss5_win_f32<4, false>);
+        // window kernels by rows per wave (2 or 4) and full-width variant
+        const void* gks[2][2] = {{(const void*)&k_gauss5_win_f32<2, false>, (const void*)&k_gauss5_win_f32<2, true>},
+                                 {(const void*)&k_gauss5_win_f32<4, false>, (const void*)&k_gauss5_win_f32<4, true>}};
+        const void* sks[2][2] = {
+            {(const void*)&k_sobel_thresh_win_f32<2, false>, (const void*)&k_sobel_thresh_win_f32<2, true>},
+            {(const void*)&k_sobel_thresh_win_f32<4, false>, (const void*)&k_sobel_thresh_win_f32<4, true>}};
+        const void* gk = win ? gks[gr == 2 ? 0 : 1][full ? 1 : 0] : (const void*)&k_gauss5_f32;
         stage(gk, to_dim3(gauss_grid(h, w)), &sl.gauss);
-        const void* sk = !win   ? (const void*)&k_sobel_thresh_f32
-                         : full ? (sr == 2 ? (const void*)&k_sobel_thresh_win_f32<2, true>
-                                           : (const void*)&k_sobel_thresh_win_f32<4, true>)
-                                : (sr == 2 ? (const void*)&k_sobel_thresh_win_f32<2, false>
-                                           : (const void*)&k_sobel_thresh_win_f32<4, false>);
+        const void* sk = win ? sks[sr == 2 ? 0 : 1][full ? 1 : 0] : (const void*)&k_sobel_thresh_f32;
         stage(sk, to_dim3(sg), &sl.sobel);
         stage((const void*)&k_sobel_final, dim3(1), &sl.sobelf);
         break;

@@ -341,6 +341,35 @@ __device__ inline float from_right(float v, float edge) {
   return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
+// Sum over the wave in six DPP steps: two quad permutes, the half-row and row
+// mirrors (each lane then holds its 16-lane row's sum), then row_bcast:15 into
+// rows 1 and 3 and row_bcast:31 into rows 2 and 3; lane 63 ends with the total,
+// which readlane returns to every lane.  Lanes of rows a broadcast leaves out
+// add the old value 0.  The order of the additions is fixed.
+template <int CTRL, int ROWS = 0xf>
+__device__ inline int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);
+}
+__device__ inline float wave_total_f32(float v) {
+  v += __int_as_float(dpp_i<0xb1>(__float_as_int(v)));        // quad_perm [1,0,3,2]
+  v += __int_as_float(dpp_i<0x4e>(__float_as_int(v)));        // quad_perm [2,3,0,1]
+  v += __int_as_float(dpp_i<0x141>(__float_as_int(v)));       // row_half_mirror
+  v += __int_as_float(dpp_i<0x140>(__float_as_int(v)));       // row_mirror
+  v += __int_as_float(dpp_i<0x142, 0xa>(__float_as_int(v)));  // row_bcast:15
+  v += __int_as_float(dpp_i<0x143, 0xc>(__float_as_int(v)));  // row_bcast:31
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ inline uint32_t wave_total_u32(uint32_t v) {
+  int x = (int)v;
+  x += dpp_i<0xb1>(x);
+  x += dpp_i<0x4e>(x);
+  x += dpp_i<0x141>(x);
+  x += dpp_i<0x140>(x);
+  x += dpp_i<0x142, 0xa>(x);
+  x += dpp_i<0x143, 0xc>(x);
+  return (uint32_t)__builtin_amdgcn_readlane(x, 63);
+}
+
 // Register-window geometry of one lane.  The wave index goes through
 // readfirstlane, so the wave's rows (and every row address, clamp and bounds
 // test derived from them) live in scalar registers; a load or store is then a
@@ -485,8 +514,8 @@ __global__ __launch_bounds__(kBlock) void k_sobel_thresh_win_f32(SobelArgs a) {
       sum += rsum;
     }
   }
-  const float ws = wave_sum_f32(sum);
-  const uint32_t wc = wave_sum_u32(cnt);
+  const float ws = wave_total_f32(sum);
+  const uint32_t wc = wave_total_u32(cnt);
   if (L.lane == 0) {
     const unsigned part = (by * gridDim.x + bx) * 4 + (threadIdx.x >> 6);
     a.psum[part] = ws;
