@@ -499,17 +499,18 @@ __global__ __launch_bounds__(kBlock) void k_sobel_thresh_win_f32(SobelArgs a) {
     const float cs[6] = {from_left(vs[3], es), vs[0], vs[1], vs[2], vs[3], from_right(vs[0], es)};
     const float cd[6] = {from_left(vd[3], ed), vd[0], vd[1], vd[2], vd[3], from_right(vd[0], ed)};
     uint32_t packed = 0;
-    float rsum = 0.f;
+    float rsum;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float gx = cs[j + 2] - cs[j];
       const float gy = (cd[j] + 2.f * cd[j + 1]) + cd[j + 2];
       const float mag = sqrt_hw(gx * gx + gy * gy);
       packed |= (mag > thr ? 1u : 0u) << (8 * j);
-      rsum += mag;
+      rsum = (j == 0) ? mag : rsum + mag;
     }
     if (y < h && !L.past) {
-      *reinterpret_cast<uint32_t*>(a.mask + (size_t)y * w + L.x) = packed;
+      uint8_t* mrow = a.mask + (size_t)y * w;  // wave-uniform row base
+      *reinterpret_cast<uint32_t*>(mrow + L.x) = packed;
       cnt += __builtin_popcount(packed);
       sum += rsum;
     }
@@ -790,16 +791,38 @@ __device__ inline void scan_load(const int32_t* in, uint64_t n, unsigned t, int 
   }
 }
 
+// One DPP move of a 64-bit value (both halves): lanes whose source lies
+// outside their row, or whose row or bank the masks leave out, read 0.
+template <int CTRL, int ROWS, int BANKS>
+__device__ inline int64_t dpp_i64(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, BANKS, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, BANKS, false);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Inclusive scan of one int64 per lane over the wave, in registers: adding
+// the input shifted right by 1, 2 and 3 lanes gives each lane the sum of its
+// 4-lane window; row_shr:4 into banks 1-3 and row_shr:8 into banks 2-3 extend
+// that to the lane's prefix of its 16-lane row; row_bcast:15 into rows 1 and
+// 3 and row_bcast:31 into rows 2 and 3 add the totals of the rows below.
+__device__ inline int64_t wave_inclusive_i64(int64_t x) {
+  int64_t v = x;
+  v += dpp_i64<0x111, 0xf, 0xf>(x);  // row_shr:1
+  v += dpp_i64<0x112, 0xf, 0xf>(x);  // row_shr:2
+  v += dpp_i64<0x113, 0xf, 0xf>(x);  // row_shr:3
+  v += dpp_i64<0x114, 0xf, 0xe>(v);  // row_shr:4
+  v += dpp_i64<0x118, 0xf, 0xc>(v);  // row_shr:8
+  v += dpp_i64<0x142, 0xa, 0xf>(v);  // row_bcast:15
+  v += dpp_i64<0x143, 0xc, 0xf>(v);  // row_bcast:31
+  return v;
+}
+
 // Exclusive block scan of one int64 per thread; returns the thread's exclusive
 // prefix and the block total.
 __device__ inline int64_t block_exclusive_i64(int64_t x, int64_t* s_wave, int64_t* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int64_t inc = x;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int64_t y = __shfl_up(inc, off, 64);
-    if (lane >= off) inc += y;
-  }
+  const int64_t inc = wave_inclusive_i64(x);
   __syncthreads();
   if (lane == 63) s_wave[wave] = inc;
   __syncthreads();
@@ -861,12 +884,13 @@ __global__ __launch_bounds__(kBlock) void k_scan_down_i32_i64(ScanDownArgs a) {
   const uint64_t n = a.hdr->n;
   const unsigned t = blockIdx.x;
   if ((uint64_t)t * kScanTile >= n) return;
+  const int64_t tile_off = a.tile_excl[t];  // issued before the block barriers, not after them
   int64_t v[kScanItems];
   scan_load(a.in, n, t, threadIdx.x, v);
 #pragma unroll
   for (int k = 1; k < kScanItems; ++k) v[k] += v[k - 1];
   int64_t total;
-  const int64_t off0 = a.tile_excl[t] + block_exclusive_i64(v[kScanItems - 1], s_wave, &total);
+  const int64_t off0 = tile_off + block_exclusive_i64(v[kScanItems - 1], s_wave, &total);
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) s_out[threadIdx.x * kPitch + k] = off0 + v[k];
   __syncthreads();
