@@ -200,10 +200,22 @@ def test_gauss_sobel_largest_serving_size(torch_gpu):
 
 
 def test_gauss_sobel_above_2048sq_per_pixel(torch_gpu):
-    """2056x2052 (more than 2048^2 pixels: the Gaussian's 4-row window; ragged
-    against the 256-column and 16-row blocks), every pixel of blur and mask."""
+    """2056x2052 (more than 2048^2 pixels: four rows per wave in both stages;
+    ragged against the 256-column and 16-row blocks, so lanes past the right
+    edge), every pixel of blur and mask."""
     _say("gauss_sobel 2056x2052 per pixel")
     imgs = [synth.normal_image(4, 0, 2056, 2052)]
+    outs, _ = _run_images("set", "gauss_sobel", imgs, np.float32, workers=1, slots=1)
+    _check_gauss(imgs[0], outs[0])
+
+
+def test_gauss_sobel_full_width_four_rows_per_pixel(torch_gpu):
+    """1210x2048: the width is a multiple of 256 (the full-width window
+    kernels, no lane past the right edge) and the image has more than 1024^2
+    pixels (four rows per wave in both stages); the height is ragged against
+    the 16-row blocks.  Every pixel of blur and mask."""
+    _say("gauss_sobel 1210x2048 per pixel")
+    imgs = [synth.normal_image(5, 0, 1210, 2048)]
     outs, _ = _run_images("set", "gauss_sobel", imgs, np.float32, workers=1, slots=1)
     _check_gauss(imgs[0], outs[0])
 
