@@ -417,7 +417,8 @@ def bench_sweep(args, torch):
     (the uneven vector workload's length distribution, device-resident inputs, two kernels and
     a 68-byte D2H each) through SET (b workers, 16 slots each, min(4, b)
     dispatcher threads), batch-sync (one graph of b chains per batch) and the
-    queue model (b workers), at b = 1 .. 64.  Prints one JSON line."""
+    queue model (b workers), at b = 1 .. 64 by default; batch-sync also runs
+    larger batches (64 workers, ceil(b / 64) slots each).  Prints one JSON line."""
     from paper_2606_05495_amd import synth
     from paper_2606_05495_amd.runtime import Context, pinned
     import oracle
@@ -440,9 +441,15 @@ def bench_sweep(args, torch):
         modes = (args.only,)
     for b in [int(v) for v in args.sweep_b.split(",")]:
         for mode in modes:
-            c = Context(mode=mode, workers=b, slots=16 if mode == "set" else 1,
+            # SET and the queue model run b workers (at most 64); a batch graph
+            # of b > 64 chains spans slots: 64 workers x ceil(b / 64) slots
+            if mode != "batch" and b > 64:
+                continue
+            nw = min(b, 64)
+            slots = 16 if mode == "set" else (-(-b // 64) if mode == "batch" else 1)
+            c = Context(mode=mode, workers=nw, slots=slots,
                         batch_size=b if mode == "batch" else 0, callback=args.callback,
-                        dispatchers=min(args.dispatchers, b), inflight=args.inflight)
+                        dispatchers=min(args.dispatchers, nw), inflight=args.inflight)
             tid = c.define("saxpy_tanh_sum", max_n=int(js["n"].max()), x_pool=xd, y_pool=yd, copy=args.copy)
             arr = c.job_array(J)
             arr["host_out"] = tout.data_ptr() + np.arange(J, dtype=np.uint64) * 128
@@ -470,8 +477,8 @@ def bench_sweep(args, torch):
     line = {"metric": METRIC, "workload": "worker-count sweep, %d per-job vector jobs per point" % J,
             "unit": "jobs/s", "n_gpus": 1, "dtype": "f32", "data": "synthetic", "higher_is_better": True,
             "vs_baseline": None, "table": table,
-            "set_over_batch": {b: round(t["set"] / t["batch"], 3) for b, t in table.items() if len(t) == 3},
-            "set_over_queue": {b: round(t["set"] / t["queue"], 3) for b, t in table.items() if len(t) == 3},
+            "set_over_batch": {b: round(t["set"] / t["batch"], 3) for b, t in table.items() if "set" in t and "batch" in t},
+            "set_over_queue": {b: round(t["set"] / t["queue"], 3) for b, t in table.items() if "set" in t and "queue" in t},
             "runs": rows, "config": {"callback": args.callback, "dispatchers": args.dispatchers, "copy": args.copy}}
     print(json.dumps(line), flush=True)
 

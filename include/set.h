@@ -211,7 +211,9 @@ typedef struct set_config {
     int32_t queue_capacity;      /* capacity of each per-worker queue Q_i; 0 = max(1, d - inflight) */
     int32_t inflight_per_worker; /* launch permits per worker in the free pool; 0 = min(2, d) */
     int32_t work_stealing;       /* 1: FindJob steals from (w+k) mod b (Algorithm 2); 0: local only */
-    int32_t batch_size;          /* SET_MODE_BATCH_SYNC: job chains per batch graph; 0 = num_workers */
+    int32_t batch_size;          /* SET_MODE_BATCH_SYNC: job chains per batch graph, 0 = num_workers;
+                                  * at most num_workers * slots_per_worker: chain i runs in slot
+                                  * i / num_workers of worker i % num_workers */
     int32_t callback_mode;       /* enum set_callback_mode (SET mode) */
     int32_t submit_policy;       /* enum set_submit_policy */
     int32_t spin_us;             /* dispatcher spin before blocking on its condition variable */

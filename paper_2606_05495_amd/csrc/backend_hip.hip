@@ -275,7 +275,7 @@ class HipBackend : public Backend {
         }
       }
     }
-    if (cfg_.mode == SET_MODE_BATCH_SYNC) p.batch.resize(b_);
+    if (cfg_.mode == SET_MODE_BATCH_SYNC) p.batch.resize((size_t)b_ * d_);
     HIPCK(hipDeviceSynchronize());
     return SET_OK;
   }
@@ -422,6 +422,10 @@ class HipBackend : public Backend {
     return SET_OK;
   }
 
+  // Chain i of a batch graph runs in slot i / b of worker i % b (the
+  // scheduler assigns the jobs' worker and slot the same way).
+  Slot& batch_slot(Pipe& p, int i) { return p.slots[(size_t)(i % b_) * d_ + (size_t)(i / b_)]; }
+
   int run_batch(JobRec** jobs, int count, std::string* err) override {
     ensure_dev();
     if (count < 1) return SET_OK;
@@ -437,18 +441,18 @@ class HipBackend : public Backend {
       HIPCK(hipGraphCreate(&bg.g, 0));
       bg.chains.resize(count);
       for (int i = 0; i < count; ++i) {
-        int rc = add_chain(p, p.slots[(size_t)i * d_], bg.g, &bg.chains[i], err);
+        int rc = add_chain(p, batch_slot(p, i), bg.g, &bg.chains[i], err);
         if (rc != SET_OK) return rc;
       }
       HIPCK(hipGraphInstantiateWithFlags(&bg.ex, bg.g, 0));
       HIPCK(hipGraphUpload(bg.ex, streams_[0]));
     }
     for (int i = 0; i < count; ++i) {
-      Slot& sl = p.slots[(size_t)i * d_];
+      Slot& sl = batch_slot(p, i);
       set_scalars(p, sl, jobs[i]);
       int rc = update_exec(p, sl, bg.ex, bg.chains[i], err);
       if (rc != SET_OK) return rc;
-      HIPCK(input_ahead(p, sl, streams_[0], i));
+      HIPCK(input_ahead(p, sl, streams_[0], i % b_));
     }
     HIPCK(hipGraphLaunch(bg.ex, streams_[0]));
     const uint64_t t0 = now_ns();

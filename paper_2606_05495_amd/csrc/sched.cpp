@@ -880,13 +880,13 @@ class Context {
   int run_batch_locked() {
     if (batch.empty()) return SET_OK;
     const int n = (int)batch.size();
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < n; ++i) {  // chain i: slot i / b of worker i % b (the backend maps it the same way)
       JobRec* j = batch[i];
-      j->worker = i;
-      j->slot = 0;
-      j->seq = ++slot_seq[j->tmpl][(size_t)i * d];
+      j->worker = i % b;
+      j->slot = i / b;
+      j->seq = ++slot_seq[j->tmpl][(size_t)j->worker * d + j->slot];
       j->t_launch = now_ns();
-      ++st_launch[i];
+      ++st_launch[j->worker];
     }
     std::string err;
     const uint64_t t0 = now_ns();
@@ -1291,7 +1291,8 @@ int set_ctx_create(const set_config* cfg, set_ctx** out) {
   }
   if (cfg->num_workers < 1 || cfg->num_workers > setrt::kMaxWorkers || cfg->slots_per_worker < 1 ||
       cfg->slots_per_worker > setrt::kMaxSlots || cfg->mode < SET_MODE_SET || cfg->mode > SET_MODE_QUEUE ||
-      cfg->batch_size < 0 || cfg->batch_size > cfg->num_workers || cfg->callback_mode < SET_CB_EVENT_POLL ||
+      cfg->batch_size < 0 || cfg->batch_size > cfg->num_workers * cfg->slots_per_worker ||
+      cfg->callback_mode < SET_CB_EVENT_POLL ||
       cfg->callback_mode > SET_CB_HOST_FLAG || cfg->submit_policy < 0 || cfg->submit_policy > SET_SUBMIT_SKEW0 ||
       cfg->inflight_per_worker < 0 || cfg->queue_capacity < 0 || cfg->spin_us < 0 || cfg->staging_capacity < 0 ||
       cfg->dispatch_threads < 0 || cfg->dispatch_threads > setrt::kMaxWorkers ||

@@ -276,6 +276,26 @@ def test_vector_parity(torch_gpu, vec_pools, mode):
         assert abs(got[i] - S) <= oracle.vec_tolerance(S, E), (n, got[i], S, E)
 
 
+def test_vector_batch_graph_spans_slots(torch_gpu, vec_pools):
+    """Batch-sync graphs of 10 chains on 3 workers x 4 slots (chain i in slot
+    i // 3 of worker i % 3), 25 jobs: 2 full batches and one of 5 at drain;
+    every header (magic, canaries, job id, tag) and every result against the
+    oracle."""
+    _say("vector batch graph of 10 chains on 3 workers x 4 slots")
+    x, y = vec_pools[0], vec_pools[1]
+    rng = np.random.default_rng(11)
+    ns = rng.integers(1, 300000, 25).astype(np.int64)
+    L = len(x)
+    xo = 64 * (rng.integers(0, (L - ns) // 64))
+    yo = 64 * (rng.integers(0, (L - ns) // 64))
+    av = rng.uniform(0.5, 2, len(ns)).astype(np.float32)
+    got, st = _run_vec("batch", vec_pools, ns, xo, yo, av, workers=3, slots=4, batch_size=10)
+    assert st.batches == 3
+    for i, n in enumerate(ns):
+        S, E = oracle.saxpy_tanh_sum(x[xo[i]:xo[i] + n], y[yo[i]:yo[i] + n], av[i])
+        assert abs(got[i] - S) <= oracle.vec_tolerance(S, E), (n, got[i], S, E)
+
+
 def test_vector_pins_on_gpu(torch_gpu):
     """a=16, x=1, y=0 saturates tanh to exactly 1.0f, so S = n exactly; x=y=0 gives 0."""
     _say("vector pins")

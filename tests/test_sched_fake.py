@@ -238,6 +238,25 @@ def test_baseline_modes_complete_in_order(mode):
             assert st.batches == 10  # 9 full batches of 4 and one of 1 at drain
 
 
+def test_batch_larger_than_worker_count_spans_slots():
+    """A batch of more chains than workers: chain i runs in slot i // b of
+    worker i % b, so batch_size may reach workers * slots and no more."""
+    with _fake(mode="batch", workers=3, slots=4, batch_size=10) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        arr, outs = _vec_jobs(ctx, tid, 25, 30)
+        ctx.submit_many(tid, arr)
+        ctx.drain()
+        st = ctx.stats()
+        assert st.completed == 25 and st.batches == 3  # 10 + 10 + 5 at drain
+        h = _headers(outs)
+        assert np.array_equal(h["job_id"], np.arange(25))
+        pos = np.arange(25) % 10  # chain index within its batch
+        assert np.array_equal(h["worker"], pos % 3)
+        assert np.array_equal(h["slot"], pos // 3)
+    with pytest.raises(A.SetError):
+        _fake(mode="batch", workers=3, slots=4, batch_size=13)
+
+
 def test_invalid_arguments_rejected():
     with _fake(workers=2, slots=2) as ctx:
         tid = ctx.define("saxpy_tanh_sum", max_n=1000, pool_ptrs=DUMMY_POOL)
