@@ -13,6 +13,7 @@ Checked here without a GPU:
 """
 import os
 import subprocess
+import time
 import threading
 
 import numpy as np
@@ -116,6 +117,82 @@ def test_worker_hint_and_local_first():
         for r in t:
             if not r["stolen"]:
                 assert r["worker"] == 2
+
+
+def _wait_until(pred, timeout_s=5.0):
+    t0 = time.monotonic()
+    while not pred():
+        assert time.monotonic() - t0 < timeout_s, "setup did not reach the expected state"
+        time.sleep(0.0005)
+
+
+# Algorithm 2 (FindJob), C7 (ii): the thief's own queue is popped first; only
+# when it is empty are victims probed, in the order (w+1), (w+2), ... (w+b-1)
+# mod b, and the head of the first non-empty one is taken.
+# (thief, workers whose queues get one job each, listed in submission order)
+FINDJOB_SCENES = [
+    (0, [3, 2, 1]),     # victims 1, 2, 3 in that order
+    (2, [1, 0, 3]),     # wraps: 3, then 0, then 1 (a reversed probe would take 1 first)
+    (1, [3, 1, 0, 2]),  # own queue first, then 2, 3, 0 (stealing before the local pop would take 2 first)
+    (3, [2, 0]),        # 0 before 2 (from w+1 = 0 on)
+]
+
+
+@pytest.mark.parametrize("thief,filled", FINDJOB_SCENES)
+def test_findjob_pops_local_then_probes_victims_in_order(thief, filled):
+    """Four workers with one launch permit and one queue entry each.  Every
+    worker first runs one job: the thief's ends after 0.15 s, the others' run
+    0.9 s.  While all four run, one short job is queued on each worker of
+    `filled`.  The only permit that comes back before 0.9 s is the thief's, so
+    the thief takes every queued job, one after the other, and the order it
+    takes them in is the order FindJob probes the queues: its own queue, then
+    (w+1) ... (w+3) mod 4.  The setup is deterministic up to the 0.75 s margin."""
+    with _fake(workers=4, slots=2, inflight=1, queue_capacity=1, dispatchers=1) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        outs = np.zeros((4 + len(filled), 128), np.uint8)
+
+        def job(k, w, dur_us):
+            return ctx.submit(tid, host_out=outs[k].ctypes.data, out_bytes=68, n=dur_us, a=1.0, user_tag=k,
+                              worker_hint=w)
+
+        for w in range(4):  # one running job per worker; each launches from its own queue
+            job(w, w, 150_000 if w == thief else 900_000)
+            _wait_until(lambda: ctx.stats().launches_per_worker[w] == 1)
+        st = ctx.stats()
+        assert st.stolen == 0 and st.inflight_high_water == 4
+        t_fill = time.monotonic()
+        ids = {job(4 + i, w, 1000): w for i, w in enumerate(filled)}
+        assert time.monotonic() - t_fill < 0.1, "the queued jobs must be in place before the thief's permit returns"
+        ctx.drain()
+        rows = sorted((r for r in ctx.job_times() if int(r["job_id"]) in ids), key=lambda r: r["t_launch"])
+        assert len(rows) == len(filled)
+        assert all(int(r["worker"]) == thief for r in rows), "a queued job ran on a worker other than the thief"
+        taken = [ids[int(r["job_id"])] for r in rows]
+        expect = sorted(filled, key=lambda v: (v - thief) % 4)
+        assert taken == expect, (taken, expect)
+        assert [int(r["stolen"]) for r in rows] == [0 if v == thief else 1 for v in expect]
+        assert ctx.stats().stolen == sum(v != thief for v in filled)
+        h = _headers(outs)
+        assert np.all(h["canary_ok"] == 1) and np.all(h["magic"] == A.SET_OUT_MAGIC)
+
+
+def test_findjob_without_stealing_leaves_other_queues():
+    """With stealing off the thief's returned permit finds its own queue empty
+    and takes nothing: the queued jobs wait for their own workers."""
+    with _fake(workers=4, slots=2, inflight=1, queue_capacity=1, dispatchers=1, stealing=False) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        outs = np.zeros((7, 128), np.uint8)
+        for w in range(4):
+            ctx.submit(tid, host_out=outs[w].ctypes.data, out_bytes=68, n=20_000 if w == 0 else 300_000, a=1.0,
+                       worker_hint=w)
+            _wait_until(lambda: ctx.stats().launches_per_worker[w] == 1)
+        ids = {ctx.submit(tid, host_out=outs[4 + i].ctypes.data, out_bytes=68, n=1000, a=1.0, worker_hint=w): w
+               for i, w in enumerate([1, 2, 3])}
+        ctx.drain()
+        for r in ctx.job_times():
+            if int(r["job_id"]) in ids:
+                assert int(r["worker"]) == ids[int(r["job_id"])] and int(r["stolen"]) == 0
+        assert ctx.stats().stolen == 0
 
 
 def test_out_of_order_callbacks_keep_memory_safety():
