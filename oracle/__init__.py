@@ -138,3 +138,12 @@ def hotspot_tolerance(ref: np.ndarray, iters: int) -> float:
 def vec_tolerance(S_ref: float, E: float) -> float:
     """Allowed |S_gpu - S_ref| for the cancelling float32 sum: max(1e-5 |S_ref|, E)."""
     return max(1e-5 * abs(S_ref), E)
+
+
+def vec_verdict(S_gpu: float, S_ref: float, E: float):
+    """(passes, by_floor): whether S_gpu is within vec_tolerance, and whether it
+    passes only because of the floor E (its error is above 1e-5 |S_ref|).  The
+    share of jobs decided by the floor is what the loose bound lets through."""
+    err = abs(float(S_gpu) - S_ref)
+    ok = err <= vec_tolerance(S_ref, E)
+    return ok, bool(ok and err > 1e-5 * abs(S_ref))

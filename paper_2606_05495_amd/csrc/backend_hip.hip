@@ -176,6 +176,10 @@ class HipBackend : public Backend {
       own_streams_ = true;
       for (int i = 0; i < b_; ++i) HIPCK(hipStreamCreateWithFlags(&streams_[i], hipStreamNonBlocking));
     }
+    // Templates are defined (captured, instantiated, uploaded) on a stream of
+    // their own: a capture on a worker stream would also record the job
+    // launches other threads issue onto it meanwhile.
+    HIPCK(hipStreamCreateWithFlags(&define_stream_, hipStreamNonBlocking));
     copy_streams_.resize(std::min(cfg.input_copy_streams, b_));
     for (hipStream_t& cs : copy_streams_) HIPCK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     if (cfg.mode == SET_MODE_SET && cfg.callback_mode == SET_CB_EVENT_CHAIN) {
@@ -262,21 +266,21 @@ class HipBackend : public Backend {
           Slot& sl = p.slots[(size_t)w * d_ + s];
           int rc;
           if ((t.flags & SET_TF_CAPTURE) || lib_template(t)) {
-            rc = capture_chain(p, sl, streams_[w], &sl.graph, &sl.nodes, err);
+            rc = capture_chain(p, sl, define_stream_, &sl.graph, &sl.nodes, err);
           } else {
             HIPCK(hipGraphCreate(&sl.graph, 0));
             rc = add_chain(p, sl, sl.graph, &sl.nodes, err);
           }
           if (rc != SET_OK) return rc;
           HIPCK(hipGraphInstantiateWithFlags(&sl.exec, sl.graph, 0));
-          HIPCK(hipGraphUpload(sl.exec, streams_[w]));
+          HIPCK(hipGraphUpload(sl.exec, define_stream_));
           if (cfg_.mode == SET_MODE_SET || cfg_.mode == SET_MODE_QUEUE)
             HIPCK(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
         }
       }
     }
     if (cfg_.mode == SET_MODE_BATCH_SYNC) p.batch.resize((size_t)b_ * d_);
-    HIPCK(hipDeviceSynchronize());
+    HIPCK(hipStreamSynchronize(define_stream_));
     return SET_OK;
   }
 
@@ -542,6 +546,8 @@ class HipBackend : public Backend {
     cb_streams_.clear();
     for (hipStream_t s : copy_streams_) (void)hipStreamDestroy(s);
     copy_streams_.clear();
+    if (define_stream_) (void)hipStreamDestroy(define_stream_);
+    define_stream_ = nullptr;
     if (own_streams_)
       for (hipStream_t s : streams_) (void)hipStreamDestroy(s);
     streams_.clear();
@@ -1007,6 +1013,7 @@ class HipBackend : public Backend {
   bool own_streams_ = false, down_ = false;
   std::vector<hipStream_t> streams_, cb_streams_;
   std::vector<hipStream_t> copy_streams_;  // input-copy streams (set_config.input_copy_streams)
+  hipStream_t define_stream_ = nullptr;    // template capture and graph upload, never a worker's
   std::vector<std::unique_ptr<Pipe>> pipes_;
   std::atomic<uint64_t> sync_ns_{0};
   // event polling

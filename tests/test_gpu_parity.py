@@ -7,7 +7,9 @@ on the terms summed); Sobel sums within 1e-5 relative; the mask bit-exact
 outside the band |mag - 1| <= 1e-5 and the count within that band; vector sums
 within max(1e-5 |S|, E) with E the float32 error allowance the oracle returns.
 """
+import os
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -21,8 +23,13 @@ pytestmark = pytest.mark.gpu
 
 
 def _say(*a):
+    """Progress and report lines; also appended to the file SET_TEST_REPORT names, if set."""
     print(*a, flush=True)
     sys.stdout.flush()
+    path = os.environ.get("SET_TEST_REPORT")
+    if path:
+        with open(path, "a") as f:
+            f.write(" ".join(str(v) for v in a) + "\n")
 
 
 @pytest.fixture(scope="module")
@@ -271,9 +278,13 @@ def test_vector_parity(torch_gpu, vec_pools, mode):
     yo[5] += 3
     av = rng.uniform(0.5, 2, len(ns)).astype(np.float32)
     got, _ = _run_vec(mode, vec_pools, ns, xo, yo, av)
+    by_floor = 0
     for i, n in enumerate(ns):
         S, E = oracle.saxpy_tanh_sum(x[xo[i]:xo[i] + n], y[yo[i]:yo[i] + n], av[i])
-        assert abs(got[i] - S) <= oracle.vec_tolerance(S, E), (n, got[i], S, E)
+        ok, fl = oracle.vec_verdict(got[i], S, E)
+        assert ok, (n, got[i], S, E)
+        by_floor += fl
+    _say("vector", mode, "passed only by the floor E: %d of %d" % (by_floor, len(ns)))
 
 
 def test_vector_batch_graph_spans_slots(torch_gpu, vec_pools):
@@ -312,6 +323,73 @@ def test_vector_pins_on_gpu(torch_gpu):
     assert np.all(got0 == 0.0)
 
 
+@pytest.fixture(scope="module")
+def ternary_pools(torch_gpu):
+    """x in {-1, 0, 1} (seeded), y = 0: with a = 16 every tanh(a*x + y) is
+    exactly -1, 0 or 1 in float32 (tanh(16) = 1 - 2.5e-14 rounds to 1), so a
+    job's S is an integer of magnitude < 2^24 and every partial sum of it is
+    exact in any order: S equals the integer sum of its x window."""
+    L = 1 << 23
+    x = np.random.default_rng(21).integers(-1, 2, L).astype(np.float32)
+    y = np.zeros(L, np.float32)
+    return x, y, torch_gpu.from_numpy(x).cuda(), torch_gpu.from_numpy(y).cuda()
+
+
+# n spans one item / block up to the largest job, with ragged tails
+EXACT_NS = np.array([1, 3, 4095, 4097, 65549, (1 << 20) + 3, 4194303], np.int64)
+
+
+def _misaligned_windows(ns, L, seed):
+    """Window offsets cycling through every alignment mod 4 for x and y."""
+    rng = np.random.default_rng(seed)
+    xo = 64 * rng.integers(0, (L - ns - 4) // 64) + np.arange(len(ns)) % 4
+    yo = 64 * rng.integers(0, (L - ns - 4) // 64) + (np.arange(len(ns)) * 3 + 1) % 4
+    return xo.astype(np.int64), yo.astype(np.int64)
+
+
+@pytest.mark.parametrize("mode", ["sync", "graph", "batch", "queue", "set"])
+def test_vector_exact_sums_misaligned(torch_gpu, ternary_pools, mode):
+    """Per-job path: S equals the exact integer sum of the x window for every
+    alignment of the x and y windows (16-byte path and scalar path), so one
+    element dropped or counted twice anywhere (tile tails included) fails."""
+    _say("vector exact sums, misaligned windows", mode)
+    x = ternary_pools[0]
+    ns = np.concatenate([EXACT_NS, EXACT_NS[3:]])
+    xo, yo = _misaligned_windows(ns, len(x), 31)
+    xo[len(EXACT_NS):] -= xo[len(EXACT_NS):] % 4  # the second copy: 4-aligned x windows
+    yo[len(EXACT_NS):] -= yo[len(EXACT_NS):] % 4
+    got, _ = _run_vec(mode, ternary_pools, ns, xo, yo, np.full(len(ns), 16.0, np.float32))
+    for i, n in enumerate(ns):
+        exact = int(np.sum(x[xo[i]:xo[i] + n].astype(np.int64)))
+        S, _ = oracle.saxpy_tanh_sum(x[xo[i]:xo[i] + n], ternary_pools[1][yo[i]:yo[i] + n], 16.0)
+        assert S == exact
+        assert got[i] == np.float32(exact), (mode, int(n), int(xo[i]) % 4, int(yo[i]) % 4, got[i], exact)
+
+
+@pytest.mark.parametrize("tile", [1024, 4096, 65536])
+def test_vector_batching_exact_sums_misaligned(torch_gpu, ternary_pools, tile):
+    """Batched path (persistent kernel over a descriptor table): the same
+    exact sums for every window alignment and work-item size."""
+    _say("vector batching exact sums, tile", tile)
+    x, y, xd, yd = ternary_pools
+    ns = np.concatenate([EXACT_NS, EXACT_NS])
+    xo, yo = _misaligned_windows(ns, len(x), 37)
+    xo[len(EXACT_NS):] -= xo[len(EXACT_NS):] % 4
+    yo[len(EXACT_NS):] -= yo[len(EXACT_NS):] % 4
+    jobs = np.zeros(len(ns), dtype=A.VEC_JOB_DTYPE)
+    jobs["n"], jobs["a"], jobs["x_off"], jobs["y_off"] = ns, 16.0, xo, yo
+    tune = A.set_vec_tuning()
+    for b in range(64):
+        tune.tile_elems[b] = tile
+    ctx = Context(mode="set", workers=2, slots=4)
+    tid = ctx.define("saxpy_batch", max_n=1 << 22, x_pool=xd, y_pool=yd, batch_max=8, tiles_max=8192)
+    res, _ = ctx.run_vector_jobs(tid, jobs, tuning=tune)
+    ctx.close()
+    for i, n in enumerate(ns):
+        exact = int(np.sum(x[xo[i]:xo[i] + n].astype(np.int64)))
+        assert res[i] == np.float32(exact), (tile, int(n), int(xo[i]) % 4, int(yo[i]) % 4, res[i], exact)
+
+
 def test_vector_workload_sample(torch_gpu, vec_pools):
     """A sample of the uneven vector workload (n log-uniform in [4096, 4194304)), with stealing."""
     _say("vector workload sample")
@@ -320,11 +398,15 @@ def test_vector_workload_sample(torch_gpu, vec_pools):
     got, st = _run_vec("set", vec_pools, jobs["n"], jobs["x_off"], jobs["y_off"], jobs["a"], workers=8, slots=16,
                        policy=A.SET_SUBMIT_SKEW0, callback="host_flag", dispatchers=4)
     assert st.stolen > 0
+    by_floor = 0
     for i in range(len(got)):
         n = int(jobs["n"][i])
         S, E = oracle.saxpy_tanh_sum(x[jobs["x_off"][i]:jobs["x_off"][i] + n],
                                      y[jobs["y_off"][i]:jobs["y_off"][i] + n], jobs["a"][i])
-        assert abs(got[i] - S) <= oracle.vec_tolerance(S, E)
+        ok, fl = oracle.vec_verdict(got[i], S, E)
+        assert ok, (i, n, got[i], S, E)
+        by_floor += fl
+    _say("vector workload sample: passed only by the floor E: %d of %d" % (by_floor, len(got)))
     # alone vs in the mix: bit-identical
     alone, _ = _run_vec("sync", vec_pools, jobs["n"][:10], jobs["x_off"][:10], jobs["y_off"][:10], jobs["a"][:10],
                         workers=1, slots=1)
@@ -483,11 +565,15 @@ def test_vector_batching_parity(torch_gpu, vec_pools, mode, copy):
     tid = ctx.define("saxpy_batch", max_n=1 << 22, x_pool=xd, y_pool=yd, batch_max=32, tiles_max=1024, copy=copy)
     res, nb = ctx.run_vector_jobs(tid, jobs)
     assert nb >= 10
+    by_floor = 0
     for i in range(200):
         n = int(jobs["n"][i])
         xo, yo = int(jobs["x_off"][i]), int(jobs["y_off"][i])
         S, E = oracle.saxpy_tanh_sum(x[xo:xo + n], y[yo:yo + n], jobs["a"][i])
-        assert abs(res[i] - S) <= oracle.vec_tolerance(S, E), (i, n, res[i], S, E)
+        ok, fl = oracle.vec_verdict(res[i], S, E)
+        assert ok, (i, n, res[i], S, E)
+        by_floor += fl
+    _say("vector batching", mode, copy, "passed only by the floor E: %d of 200" % by_floor)
     perm = np.random.default_rng(9).permutation(200)
     res2, _ = ctx.run_vector_jobs(tid, jobs[perm])
     assert np.array_equal(res2, res[perm])
@@ -620,6 +706,69 @@ def test_captured_templates_match_explicit(torch_gpu, vec_pools, mode, copy):
         S, E = oracle.saxpy_tanh_sum(x[64 * i:64 * i + n], y[128:128 + n], 1.5)
         got = float(nout[128 * i + 64:128 * i + 68].view(np.float32)[0])
         assert abs(got - S) <= oracle.vec_tolerance(S, E)
+    ctx.close()
+
+
+@pytest.mark.parametrize("callback", ["event_poll", "event_chain"])
+def test_define_captured_templates_while_jobs_run(torch_gpu, callback):
+    """Templates built by stream capture (a captured chain and a captured
+    library call) are defined while another template's jobs are being
+    launched onto the worker streams from two dispatcher threads.  The
+    capture runs on the library's own stream, so no job launch is recorded
+    into a new template and every job of every template completes correctly."""
+    import threading
+    _say("define captured templates while jobs run", callback)
+    ctx = Context(mode="set", workers=4, slots=4, callback=callback, dispatchers=2)
+    ta = ctx.define("box_hist", width=256, height=256, flags=0, copy="kernels")
+    imgs = [synth.box_image(0, j) for j in range(16)]
+    refs = [oracle.box_hist(im)[2] for im in imgs]
+    n_a = 3000
+    tin, nin = pinned(65536 * 16)
+    for j, im in enumerate(imgs):
+        nin[j * 65536:(j + 1) * 65536] = im.ravel()
+    tout, nout = pinned(1152 * n_a)
+    arr = ctx.job_array(n_a)
+    idx = np.arange(n_a, dtype=np.uint64)
+    arr["host_in"] = tin.data_ptr() + (idx % np.uint64(16)) * np.uint64(65536)
+    arr["in_bytes"] = 65536
+    arr["host_out"] = tout.data_ptr() + idx * np.uint64(1152)
+    arr["out_bytes"] = 64 + 1024
+    arr["user_tag"] = idx
+    th = threading.Thread(target=lambda: ctx.submit_many(ta, arr))
+    th.start()
+    t0 = time.monotonic()
+    while ctx.stats().completed < 50 and time.monotonic() - t0 < 30:
+        time.sleep(0.001)
+    tb = ctx.define("gauss_sobel", width=136, height=96, flags=A.SET_TF_CAPTURE, copy="kernels")
+    tc = ctx.define("scan_lib", max_n=4097, copy="kernels")
+    during = ctx.stats().completed
+    th.join()
+    assert during < n_a, "the definitions did not overlap the running jobs"
+    g = [synth.normal_image(3, k, 96, 136) for k in range(4)]
+    gin, gnin = pinned(4 * 96 * 136 * 4)
+    gout, gnout = pinned(128 * 4)
+    for k, im in enumerate(g):
+        gnin[k * 4 * 96 * 136:(k + 1) * 4 * 96 * 136].view(np.float32)[:] = im.ravel()
+        ctx.submit(tb, host_in=gin.data_ptr() + k * 4 * 96 * 136, in_bytes=4 * 96 * 136,
+                   host_out=gout.data_ptr() + 128 * k, out_bytes=72)
+    v = np.random.default_rng(4).integers(-(1 << 20), (1 << 20) + 1, 4097).astype(np.int32)
+    sin, snin = pinned(4 * 4097)
+    sout, snout = pinned(64 + 8 * 4097)
+    snin.view(np.int32)[:] = v
+    ctx.submit(tc, host_in=sin.data_ptr(), in_bytes=4 * 4097, host_out=sout.data_ptr(), out_bytes=64 + 8 * 4097)
+    ctx.drain(timeout_ns=int(60e9))
+    st = ctx.stats()
+    assert st.completed == n_a + 5 and st.failed == 0
+    out = nout.reshape(n_a, 1152)
+    for i in range(n_a):
+        _check_header(out[i], i, i)
+        assert np.array_equal(out[i, 64:].view(np.uint32), refs[i % 16]), i
+    for k, im in enumerate(g):
+        ref = oracle.gauss_sobel(im, want_images=False)
+        o = gnout[128 * k:128 * (k + 1)]
+        assert abs(int(o[64:68].view(np.uint32)[0]) - ref["count"]) <= ref["band"]
+        assert abs(float(o[68:72].view(np.float32)[0]) - ref["sum"]) <= 1e-5 * abs(ref["sum"])
+    assert np.array_equal(snout[64:].view(np.int64), oracle.scan(v))
     ctx.close()
 
 

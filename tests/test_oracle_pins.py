@@ -210,6 +210,37 @@ def test_saxpy_saturated_and_zero():
     assert Se == 0.0
 
 
+def test_saxpy_ternary_saturated_sum_is_the_integer_sum(rng):
+    """x in {-1, 0, 1}, a = 16, y = 0: tanh(+-16) is 1 - 2.5e-14 in magnitude,
+    so S is the integer sum of x to within n * 2.5e-14 (the exact-sum pins of
+    the device paths rely on float32 rounding that residue away)."""
+    for n in (1, 3, 4097, 65549):
+        x = rng.integers(-1, 2, n).astype(np.float32)
+        S, _ = oracle.saxpy_tanh_sum(x, np.zeros(n, np.float32), 16.0)
+        exact = int(np.sum(x.astype(np.int64)))
+        assert abs(S - exact) <= n * 2.6e-14
+        assert np.float32(S) == np.float32(exact)
+
+
+def test_saxpy_floor_bounds_float32_evaluations(rng):
+    """The floor E bounds the error of actual float32 evaluations: z and tanh
+    rounded to float32, then summed sequentially, pairwise, in reverse and in
+    blocks of 1024 partials; each stays within E of the float64 S."""
+    for n in (7, 1000, 4096, 65549):
+        x = rng.uniform(-1, 1, n).astype(np.float32)
+        y = rng.uniform(-1, 1, n).astype(np.float32)
+        a = np.float32(rng.uniform(0.5, 2))
+        S, E = oracle.saxpy_tanh_sum(x, y, float(a))
+        t = np.tanh(a * x + y).astype(np.float32)
+        seq = np.cumsum(t, dtype=np.float32)[-1]
+        pair = np.sum(t, dtype=np.float32)
+        rev = np.cumsum(t[::-1], dtype=np.float32)[-1]
+        blocks = np.sum(np.array([np.sum(t[k:k + 1024], dtype=np.float32) for k in range(0, n, 1024)],
+                                 np.float32), dtype=np.float32)
+        for v in (seq, pair, rev, blocks):
+            assert abs(float(v) - S) <= E, (n, float(v), S, E)
+
+
 def test_saxpy_odd_symmetry_and_a_zero(rng):
     x = rng.uniform(-1, 1, 5000).astype(np.float32)
     y = rng.uniform(-1, 1, 5000).astype(np.float32)
