@@ -362,7 +362,9 @@ def test_vector_exact_sums_misaligned(torch_gpu, ternary_pools, mode):
     for i, n in enumerate(ns):
         exact = int(np.sum(x[xo[i]:xo[i] + n].astype(np.int64)))
         S, _ = oracle.saxpy_tanh_sum(x[xo[i]:xo[i] + n], ternary_pools[1][yo[i]:yo[i] + n], 16.0)
-        assert S == exact
+        # the float64 oracle carries tanh(16)'s residue 2.5e-14 per nonzero
+        # element; float32 rounds it away
+        assert abs(S - exact) <= n * 2.6e-14 and np.float32(S) == np.float32(exact)
         assert got[i] == np.float32(exact), (mode, int(n), int(xo[i]) % 4, int(yo[i]) % 4, got[i], exact)
 
 
@@ -762,7 +764,7 @@ def test_define_captured_templates_while_jobs_run(torch_gpu, callback):
     out = nout.reshape(n_a, 1152)
     for i in range(n_a):
         _check_header(out[i], i, i)
-        assert np.array_equal(out[i, 64:].view(np.uint32), refs[i % 16]), i
+        assert np.array_equal(out[i, 64:64 + 1024].view(np.uint32), refs[i % 16]), i
     for k, im in enumerate(g):
         ref = oracle.gauss_sobel(im, want_images=False)
         o = gnout[128 * k:128 * (k + 1)]
