@@ -409,6 +409,51 @@ int set_time_stage(set_ctx *c, int template_id, int stage, int worker, int reps,
 int set_run_vector_jobs(set_ctx *c, int template_id, const set_vec_job *jobs, uint64_t count,
                         float *results, const set_vec_tuning *tuning, uint64_t *batches);
 
+/* ---------------------------------------------------------------- no allocation */
+#define SET_NOALLOC_MAX_JOBS 16384u       /* jobs per call */
+#define SET_NOALLOC_MAX_ITEMS 1048576u    /* work items per call, counted for the worst case (below) */
+
+/* set_run_vector_jobs for callers that cannot allocate memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * needs no context and calls no allocating function (no hipMalloc, hipFree or
+ * pinned allocation).
+ *
+ * Per job: S = sum over i < n of tanh(a*x[x_off+i] + y[y_off+i]), with the
+ * job's work-item size taken per size bucket floor(log2 n) from tuning (zero
+ * entries and tuning == NULL: the default sizes of set_run_vector_jobs).  A
+ * job's S is bit-identical to what set_run_vector_jobs returns for the same
+ * (n, item size); the persistent grid (`grid`, 0 = 1024 blocks) changes no
+ * result.
+ *
+ * device: HIP device ordinal; made current for the call, then restored.
+ * stream: hipStream_t of that device (NULL = its null stream).  The call only
+ *   enqueues three kernels there and returns; results are ready when the
+ *   stream's work before the next synchronisation point has finished.
+ * dev_x_pool, dev_y_pool: device float pools of pool_len elements each.
+ * dev_jobs: device array of count set_vec_job; dev_results: device float
+ *   array of count results, in job order.  Both caller-owned.
+ * max_n: the largest n any job may have (1..2^31).  A job with n outside
+ *   [1, max_n] or a window leaving a pool reads nothing and gets NaN.
+ * tuning: host struct, read during the call (item sizes: multiples of 1024).
+ *
+ * Limits, checked on the host before anything is enqueued (SET_EINVAL, with
+ * set_last_error(NULL) naming the limit): count <= SET_NOALLOC_MAX_JOBS, and
+ * count times the most items a job of length <= max_n can need under the
+ * item sizes <= SET_NOALLOC_MAX_ITEMS.  With the default sizes and max_n =
+ * 4194304 a job needs at most 64 items, so 16384 jobs fit.
+ *
+ * Work area: one static device array of about 4.8 MiB per GPU (descriptor
+ * table, item partials, work counter), held from library load until the
+ * process ends and shared by every call on that GPU.  Each call rewrites it
+ * from its first kernel on (the counter included), so calls on one stream
+ * follow each other safely; calls that overlap on one GPU (different
+ * streams, or different host threads without ordering) race on it and give
+ * wrong results.  Errors: SET_EINVAL as above or for null pointers,
+ * SET_EDEVICE when a HIP call fails (message in set_last_error(NULL)). */
+int set_run_vector_jobs_noalloc(int device, void *stream, const float *dev_x_pool, const float *dev_y_pool,
+                                uint64_t pool_len, uint64_t max_n, const set_vec_job *dev_jobs, uint64_t count,
+                                float *dev_results, const set_vec_tuning *tuning, uint32_t grid);
+
 /* ---------------------------------------------------------------- serving */
 /* One request of an open-loop arrival schedule. */
 typedef struct set_request {
@@ -461,7 +506,8 @@ int set_stage_info(set_ctx *c, int template_id, int *num_stages, uint64_t *bytes
                    int max_stages, char *names, int names_len);
 
 /* Message of the last error on this context ("" if none); c == NULL gives the
- * last error of a failed set_ctx_create on this thread. */
+ * last error on this thread of a call without a context (a failed
+ * set_ctx_create, set_run_vector_jobs_noalloc). */
 const char *set_last_error(const set_ctx *c);
 
 /* Static name of a status code. */

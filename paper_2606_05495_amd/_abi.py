@@ -206,8 +206,10 @@ EXPORTS = [
     "set_ctx_create", "set_ctx_destroy", "set_template_footprint", "set_template_define", "set_submit",
     "set_submit_many", "set_set_completion_cb", "set_drain", "set_get_stats", "set_reset_stats",
     "set_get_job_times", "set_time_stage", "set_stage_info", "set_last_error", "set_strerror",
-    "set_run_vector_jobs", "set_serve", "set_job_io_bytes",
+    "set_run_vector_jobs", "set_serve", "set_job_io_bytes", "set_run_vector_jobs_noalloc",
 ]
+SET_NOALLOC_MAX_JOBS = 16384
+SET_NOALLOC_MAX_ITEMS = 1 << 20
 
 _lib = None
 
@@ -242,6 +244,8 @@ def load():
         "set_job_io_bytes": (I, [P, I, U64, ctypes.POINTER(U64), ctypes.POINTER(U64)]),
         "set_run_vector_jobs": (I, [P, I, P, U64, P, ctypes.POINTER(set_vec_tuning), ctypes.POINTER(U64)]),
         "set_serve": (I, [P, P, U64, ctypes.POINTER(set_serve_config), P, P, ctypes.POINTER(set_serve_stats)]),
+        "set_run_vector_jobs_noalloc": (I, [I, P, P, P, U64, U64, P, U64, P, ctypes.POINTER(set_vec_tuning),
+                                            ctypes.c_uint32]),
         "set_last_error": (ctypes.c_char_p, [P]),
         "set_strerror": (ctypes.c_char_p, [I]),
     }
@@ -358,6 +362,16 @@ def set_run_vector_jobs(ctx, template_id: int, jobs: np.ndarray, results: np.nda
     check(load().set_run_vector_jobs(ctx, template_id, jobs.ctypes.data, jobs.size, results.ctypes.data,
                                      ctypes.byref(tuning) if tuning is not None else None, ctypes.byref(nb)), ctx)
     return nb.value
+
+
+def set_run_vector_jobs_noalloc(device: int, stream: int, dev_x_pool: int, dev_y_pool: int, pool_len: int,
+                                max_n: int, dev_jobs: int, count: int, dev_results: int, tuning=None,
+                                grid: int = 0) -> None:
+    """Device pointers and the stream as integers; enqueues only (results are
+    ready once the stream has reached them)."""
+    check(load().set_run_vector_jobs_noalloc(device, stream, dev_x_pool, dev_y_pool, pool_len, max_n, dev_jobs,
+                                             count, dev_results,
+                                             ctypes.byref(tuning) if tuning is not None else None, grid))
 
 
 def set_serve(ctx, reqs: np.ndarray, cfg: set_serve_config = None, vec_results: np.ndarray = None):

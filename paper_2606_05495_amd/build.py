@@ -21,7 +21,7 @@ TSAN_BIN = os.path.join(OBJ, "sched_tsan_test")
 ARCH = os.environ.get("SET_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HIP_SOURCES = ["kernels.hip", "backend_hip.hip"]
+HIP_SOURCES = ["kernels.hip", "backend_hip.hip", "noalloc.hip"]
 CPP_SOURCES = ["sched.cpp", "layout.cpp", "backend_fake.cpp"]
 HEADERS = ["internal.hpp", "kernels.hpp", "tiles.hpp"]
 

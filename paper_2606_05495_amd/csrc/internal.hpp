@@ -20,6 +20,10 @@ inline uint64_t now_ns() {
       .count();
 }
 
+// Message that set_last_error(NULL) returns on the calling thread (calls
+// that have no context: a failed set_ctx_create, the no-allocation call).
+void set_thread_error(const std::string& msg);
+
 constexpr int kMaxWorkers = 64;
 constexpr int kMaxSlots = 64;
 constexpr int kMaxTemplates = 16;

@@ -762,9 +762,7 @@ __global__ __launch_bounds__(kBlock) void k_vec_batch_final(VecBatchFinalArgs a)
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
   if (j < H->count) {
     const VecBatchDesc d = D[j];
-    float s = 0.f;
-    for (uint32_t k = 0; k < d.ntiles; ++k) s += a.partials[d.tile_start + k];
-    a.results[j] = s;
+    a.results[j] = vec_items_total(a.partials, d.tile_start, d.ntiles);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *a.work = 0u;

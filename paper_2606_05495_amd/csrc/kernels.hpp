@@ -179,6 +179,14 @@ __global__ void k_sobel_thresh_win_f32(SobelArgs a);
 __global__ void k_sobel_final(SobelFinalArgs a);
 __global__ void k_saxpy_tanh_sum_f32(VecArgs a);
 __global__ void k_vec_final(VecFinalArgs a);
+// Sum of one vector job's work-item partials in item order: the fixed order
+// that makes a job's result depend only on its length and item size.
+__device__ inline float vec_items_total(const float* partials, uint32_t first, uint32_t count) {
+  float s = 0.f;
+  for (uint32_t k = 0; k < count; ++k) s += partials[first + k];
+  return s;
+}
+
 __global__ void k_vec_batch_tiles(VecBatchArgs a);
 __global__ void k_vec_batch_final(VecBatchFinalArgs a);
 __global__ void k_scan_reduce_i32(ScanReduceArgs a);

@@ -95,6 +95,8 @@ class WorkerQueue {
 
 }  // namespace
 
+void set_thread_error(const std::string& msg) { g_create_error = msg; }
+
 class Context {
  public:
   set_config cfg{};

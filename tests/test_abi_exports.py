@@ -56,3 +56,24 @@ def test_footprint_is_host_only():
     # input 4 MiB + blur 4 MiB + mask 1 MiB + small
     assert 9 * 2 ** 20 <= slot < 9 * 2 ** 20 + 64 * 1024
     assert total == 128 * slot
+
+
+def test_noalloc_limits_refused_on_the_host():
+    """The no-allocation call checks its limits before touching a device, so
+    these run without a GPU."""
+    lib = A.load()
+    big = A.SET_NOALLOC_MAX_JOBS + 1
+    assert lib.set_run_vector_jobs_noalloc(0, None, 16, 16, 1 << 20, 4096, 16, big, 16, None, 0) == A.SET_EINVAL
+    assert "16384" in A.set_last_error(None)
+    # 16384 jobs of up to 2^22 elements in 1024-element items need far more than 2^20 items
+    t = A.set_vec_tuning()
+    for b in range(64):
+        t.tile_elems[b] = 1024
+    assert lib.set_run_vector_jobs_noalloc(0, None, 16, 16, 1 << 23, 1 << 22, 16, 16384, 16, ctypes.byref(t),
+                                           0) == A.SET_EINVAL
+    assert "work items" in A.set_last_error(None)
+    t.tile_elems[5] = 1000
+    assert lib.set_run_vector_jobs_noalloc(0, None, 16, 16, 1 << 23, 1 << 22, 16, 1, 16, ctypes.byref(t),
+                                           0) == A.SET_EINVAL
+    assert lib.set_run_vector_jobs_noalloc(0, None, None, 16, 1 << 23, 4096, 16, 1, 16, None, 0) == A.SET_EINVAL
+    assert lib.set_run_vector_jobs_noalloc(0, None, 16, 16, 1 << 23, 0, 16, 1, 16, None, 0) == A.SET_EINVAL
