@@ -111,7 +111,15 @@ enum set_callback_mode {
      * Faster than event polling for short jobs with copy kernels; with DMA
      * input copies the extra kernel costs more than it saves, and event
      * polling is the faster. */
-    SET_CB_HOST_FLAG = 3
+    SET_CB_HOST_FLAG = 3,
+    /* hipEventRecord on the worker stream after the job's graph, with the
+     * slot's events created hipEventBlockingSync; one library thread per
+     * worker waits in hipEventSynchronize on that worker's events in launch
+     * order and then runs the release.  Nothing spins on the host and no
+     * host-function packet enters the device queues: the waiting thread
+     * sleeps until the runtime signals the event (Section 4.2, "(3) Free
+     * worker pool": the pool is updated on completion, not by polling). */
+    SET_CB_EVENT_BLOCKING = 4
 };
 
 enum set_submit_policy {
@@ -338,9 +346,15 @@ typedef struct set_ctx set_ctx;
  * abi_version mismatch), SET_ENOMEM, SET_EDEVICE (no device / HIP failure). */
 int set_ctx_create(const set_config *cfg, set_ctx **out);
 
-/* Drain outstanding jobs, stop threads, destroy graphs, events and
- * library-created streams and allocations.  Never frees borrowed memory or
- * streams.  NULL is accepted (no-op). */
+/* The inverse of the initialisation in Section 4.2 ("Initialization": the
+ * main thread sets up the queues and the workers' streams, buffers and graph
+ * executables, then starts the submitter and dispatcher threads): drain
+ * outstanding jobs (c_done reaches the submitted count, Algorithm 3), stop
+ * the threads, destroy graphs, events and library-created streams and
+ * allocations.  Never frees borrowed memory or streams.  NULL is accepted
+ * (no-op).  Always returns SET_OK and frees the handle; a context latched
+ * into SET_EDEVICE is not drained first (its device work is waited for by a
+ * device synchronisation instead). */
 int set_ctx_destroy(set_ctx *c);
 
 /* Bytes of device memory one buffer slot of template t needs, and the total
@@ -369,9 +383,15 @@ int set_submit(set_ctx *c, int template_id, const set_job_args *a, int flags, ui
 int set_submit_many(set_ctx *c, int template_id, const set_job_args *a, uint64_t count,
                     int flags, uint64_t *first_job_id);
 
-/* Register a function called once per completed job, on a library or driver
- * thread, after the job's output is in host memory.  It must not call back
- * into this library or into HIP.  fn == NULL unregisters. */
+/* Register a function called once per completed job, from the release step
+ * of Algorithm 3 (Section 4.2, "Asynchronous Resource Return": the callback
+ * that runs on a separate thread once the worker's stream has finished the
+ * job's graph), after the job's output is in host memory and after c_done
+ * was incremented for it.  It runs on a library or driver thread, must not
+ * call back into this library or into HIP, and should return quickly: the
+ * worker goes back to the free pool only after it returns.  status is SET_OK
+ * or the job's error code.  fn == NULL unregisters; user is passed through
+ * unchanged and stays owned by the caller. */
 int set_set_completion_cb(set_ctx *c, set_completion_fn fn, void *user);
 
 /* Block until every submitted job has completed (c_done == submitted,
@@ -379,22 +399,35 @@ int set_set_completion_cb(set_ctx *c, set_completion_fn fn, void *user);
  * timeout (jobs keep running). */
 int set_drain(set_ctx *c, int64_t timeout_ns);
 
-/* Snapshot of the counters (may run concurrently with jobs). */
+/* Snapshot of the counters (may run concurrently with jobs): submitted and
+ * completed jobs (Algorithm 1's c_next and Algorithm 3's c_done since the
+ * last reset), steals (Algorithm 2), the host time spent binding parameters
+ * (UpdateGraphParams of Algorithm 1), launching and in callbacks, and the
+ * first-submit / last-completion stamps from which the throughput of
+ * Section 5.2 (jobs per second) is taken.  out is caller-owned.  SET_EINVAL
+ * if c or out is NULL. */
 int set_get_stats(set_ctx *c, set_stats *out);
 
-/* Zero counters and per-job time records (call when drained). */
+/* Zero the counters of set_get_stats and the per-job time records, so that
+ * a measurement window (the throughput of Section 5.2, the overhead fraction
+ * t_schedule / T_measured of Section 5.3 with Eq. 4) starts clean.  Call it
+ * when drained; job ids keep counting. */
 int set_reset_stats(set_ctx *c);
 
 /* Copy up to max records of per-job times for jobs completed since the last
  * reset, in completion order; *count receives how many were written. */
 int set_get_job_times(set_ctx *c, set_job_times *out, uint64_t max, uint64_t *count);
 
-/* Measurement helper: launch stage `stage` (0-based kernel of the template's
- * chain) of template `template_id` `reps` times back to back on worker
- * `worker`'s stream against slot 0 of that worker, bracketed by two HIP events
- * on that stream; *avg_us receives the mean duration per launch.  The slot's
- * current contents are used as input, so run one job on that slot first.
- * Requires a drained context. */
+/* Measurement helper for the per-kernel terms of Section 3.2 (Eq. 1-2's
+ * kernel times) and the rooflines: launch stage `stage` (0-based kernel of
+ * the template's chain) of template `template_id` `reps` times back to back,
+ * bracketed by two HIP events on the stream they run on; *avg_us receives the
+ * mean duration per launch.  worker >= 0: every launch on worker `worker`'s
+ * stream against slot 0 of that worker (its working set stays in the caches
+ * when it is small).  worker == -1: launch r uses slot r mod (b*d) of the
+ * template, all on worker 0's stream, so with enough slots the kernel reads
+ * and writes HBM.  The slots' current contents are used as input, so run
+ * jobs on them first.  Requires a drained context. */
 int set_time_stage(set_ctx *c, int template_id, int stage, int worker, int reps, double *avg_us);
 
 /* Bucketed persistent batching of vector jobs (template of pipeline
@@ -404,7 +437,9 @@ int set_time_stage(set_ctx *c, int template_id, int stage, int worker, int reps,
  * it is queued, dispatched, stolen and released like any other job).
  * results[i] receives S of jobs[i].  Blocks until every batch has completed.
  * tuning may be NULL.  Descriptor tables and result staging are pinned host
- * memory owned by the library.  *batches (may be NULL) receives the number of
+ * memory owned by the context, kept between calls and grown only when a call
+ * needs more (so repeated calls allocate nothing); concurrent calls on one
+ * context are serialised.  *batches (may be NULL) receives the number of
  * batches submitted. */
 int set_run_vector_jobs(set_ctx *c, int template_id, const set_vec_job *jobs, uint64_t count,
                         float *results, const set_vec_tuning *tuning, uint64_t *batches);
@@ -507,7 +542,10 @@ int set_stage_info(set_ctx *c, int template_id, int *num_stages, uint64_t *bytes
 
 /* Message of the last error on this context ("" if none); c == NULL gives the
  * last error on this thread of a call without a context (a failed
- * set_ctx_create, set_run_vector_jobs_noalloc). */
+ * set_ctx_create, set_run_vector_jobs_noalloc).  The paper defines no error
+ * channel; this one serves the latch described at the top of this file.  The
+ * string is owned by the library and stays valid until the next failing call
+ * on the same context (or thread, for c == NULL). */
 const char *set_last_error(const set_ctx *c);
 
 /* Static name of a status code. */

@@ -28,7 +28,7 @@ SET_OK, SET_EINVAL, SET_ENOMEM, SET_EDEVICE, SET_EAGAIN, SET_ETIMEOUT, SET_ECLOS
 # modes
 SET_MODE_SET, SET_MODE_SYNC, SET_MODE_GRAPH, SET_MODE_BATCH_SYNC, SET_MODE_QUEUE = 0, 1, 2, 3, 4
 SET_BACKEND_HIP, SET_BACKEND_FAKE = 0, 1
-SET_CB_EVENT_POLL, SET_CB_EVENT_CHAIN, SET_CB_SAME_STREAM, SET_CB_HOST_FLAG = 0, 1, 2, 3
+SET_CB_EVENT_POLL, SET_CB_EVENT_CHAIN, SET_CB_SAME_STREAM, SET_CB_HOST_FLAG, SET_CB_EVENT_BLOCKING = 0, 1, 2, 3, 4
 SET_SUBMIT_ROUND_ROBIN, SET_SUBMIT_SHORTEST, SET_SUBMIT_SKEW0 = 0, 1, 2
 # pipelines
 SET_PIPE_BOX_HIST_U8, SET_PIPE_GAUSS_SOBEL_F32, SET_PIPE_SAXPY_TANH_SUM_F32, SET_PIPE_SCAN_I32_I64 = 0, 1, 2, 3
@@ -44,7 +44,7 @@ SET_OUT_MAGIC = 0x5E7D0A11
 MODES = {"set": SET_MODE_SET, "sync": SET_MODE_SYNC, "graph": SET_MODE_GRAPH, "batch": SET_MODE_BATCH_SYNC,
          "queue": SET_MODE_QUEUE}
 CALLBACKS = {"event_chain": SET_CB_EVENT_CHAIN, "same_stream": SET_CB_SAME_STREAM, "event_poll": SET_CB_EVENT_POLL,
-             "host_flag": SET_CB_HOST_FLAG}
+             "host_flag": SET_CB_HOST_FLAG, "event_blocking": SET_CB_EVENT_BLOCKING}
 
 
 class set_config(ctypes.Structure):

@@ -191,6 +191,14 @@ class HipBackend : public Backend {
       poll_in_.resize(b_);
       poller_ = std::thread([this] { poll_loop(); });
     }
+    blocking_ = cfg.mode == SET_MODE_SET && cfg.callback_mode == SET_CB_EVENT_BLOCKING;
+    if (blocking_) {
+      waiters_.resize(b_);
+      for (int w = 0; w < b_; ++w) {
+        waiters_[w].reset(new Waiter());
+        waiters_[w]->th = std::thread([this, w] { wait_loop(w); });
+      }
+    }
     return SET_OK;
   }
 
@@ -275,7 +283,8 @@ class HipBackend : public Backend {
           HIPCK(hipGraphInstantiateWithFlags(&sl.exec, sl.graph, 0));
           HIPCK(hipGraphUpload(sl.exec, define_stream_));
           if (cfg_.mode == SET_MODE_SET || cfg_.mode == SET_MODE_QUEUE)
-            HIPCK(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+            HIPCK(hipEventCreateWithFlags(&sl.ev, blocking_ ? (hipEventDisableTiming | hipEventBlockingSync)
+                                                            : hipEventDisableTiming));
         }
       }
     }
@@ -334,6 +343,16 @@ class HipBackend : public Backend {
       case SET_CB_SAME_STREAM:
         HIPCK(hipLaunchHostFunc(st, &HipBackend::host_cb, &sl.cb));
         break;
+      case SET_CB_EVENT_BLOCKING: {
+        HIPCK(hipEventRecord(sl.ev, st));
+        Waiter& wt = *waiters_[w];
+        {
+          std::lock_guard<std::mutex> g(wt.mu);
+          wt.q.push_back(&sl);
+        }
+        wt.cv.notify_one();
+        break;
+      }
       case SET_CB_EVENT_POLL:
       case SET_CB_HOST_FLAG: {
         if (!flag_mode_) HIPCK(hipEventRecord(sl.ev, st));
@@ -468,27 +487,34 @@ class HipBackend : public Backend {
   int time_stage(int tmpl, int stage, int worker, int reps, double* avg_us, std::string* err) override {
     ensure_dev();
     Pipe& p = *pipes_[tmpl];
-    Slot& sl = p.slots[(size_t)worker * d_];
+    // worker < 0: launches rotate over every slot of the template (slot r mod
+    // b*d for launch r, on worker 0's stream), so a working set larger than
+    // the caches is read from HBM; otherwise slot 0 of `worker`, every launch.
+    const bool rotate = worker < 0;
+    const size_t nslots = rotate ? p.slots.size() : 1;
+    const size_t first = rotate ? 0 : (size_t)worker * d_;
+    Slot& sl0 = p.slots[first];
     // library-call templates list [stage 0, library call, stage 1]
     const bool lib = lib_template(p.t);
-    const int nlisted = sl.nstages + (lib ? 1 : 0);
+    const int nlisted = sl0.nstages + (lib ? 1 : 0);
     if (stage < 0 || stage >= nlisted) {
       if (err) *err = "no such stage";
       return SET_EINVAL;
     }
     const bool lib_call = lib && stage == 1;
     const int ks = (lib && stage == 2) ? 1 : stage;
-    hipStream_t st = streams_[worker];
-    auto once = [&]() -> hipError_t {
+    hipStream_t st = streams_[rotate ? 0 : worker];
+    auto once = [&](int r) -> hipError_t {
+      Slot& sl = p.slots[first + (size_t)r % nslots];
       if (lib_call) return library_stage(p, sl, st);
       return hipLaunchKernel(sl.func[ks], sl.grid[ks], dim3(kBlock), sl.argv[ks], 0, st);
     };
     hipEvent_t e0, e1;
     HIPCK(hipEventCreate(&e0));
     HIPCK(hipEventCreate(&e1));
-    HIPCK(once());
+    for (size_t r = 0; r < std::min<size_t>(nslots, 64); ++r) HIPCK(once((int)(nslots - 1 - r)));
     HIPCK(hipEventRecord(e0, st));
-    for (int r = 0; r < reps; ++r) HIPCK(once());
+    for (int r = 0; r < reps; ++r) HIPCK(once(r));
     HIPCK(hipEventRecord(e1, st));
     HIPCK(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -514,6 +540,15 @@ class HipBackend : public Backend {
   void shutdown() override {
     if (down_) return;
     down_ = true;
+    for (auto& wt : waiters_) {
+      {
+        std::lock_guard<std::mutex> g(wt->mu);
+        wt->stop = true;
+      }
+      wt->cv.notify_all();
+      wt->th.join();
+    }
+    waiters_.clear();
     if (poller_.joinable()) {
       {
         std::lock_guard<std::mutex> g(poll_mu_);
@@ -619,6 +654,28 @@ class HipBackend : public Backend {
           std::this_thread::yield();
         }
       }
+    }
+  }
+
+  // Completion threads of SET_CB_EVENT_BLOCKING, one per worker: the
+  // worker's launched jobs in launch order, each waited for by a blocking
+  // event synchronisation (the thread sleeps until the runtime signals the
+  // event), then released.  A failed wait completes the job with SET_EDEVICE.
+  void wait_loop(int w) {
+    ensure_dev();
+    Waiter& wt = *waiters_[w];
+    while (true) {
+      Slot* sl = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(wt.mu);
+        wt.cv.wait(lk, [&] { return wt.stop || !wt.q.empty(); });
+        if (wt.q.empty()) return;  // stopping, nothing in flight
+        sl = wt.q.front();
+        wt.q.pop_front();
+      }
+      const hipError_t e = hipEventSynchronize(sl->ev);
+      const CbCtx c = sl->cb;
+      c.done(c.ctx, c.job, e == hipSuccess ? SET_OK : SET_EDEVICE);
     }
   }
 
@@ -1017,6 +1074,15 @@ class HipBackend : public Backend {
   std::vector<std::unique_ptr<Pipe>> pipes_;
   std::atomic<uint64_t> sync_ns_{0};
   // event polling
+  struct Waiter {
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Slot*> q;
+    bool stop = false;
+  };
+  std::vector<std::unique_ptr<Waiter>> waiters_;  // SET_CB_EVENT_BLOCKING
+  bool blocking_ = false;
   std::thread poller_;
   std::mutex poll_mu_;
   std::condition_variable poll_cv_;

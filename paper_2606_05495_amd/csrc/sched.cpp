@@ -214,6 +214,12 @@ class Context {
   };
   ServeState* serve_st = nullptr;
 
+  // ---- set_run_vector_jobs: pinned staging of descriptor tables and results
+  // (grow-only, freed at shutdown); the mutex serialises concurrent calls
+  std::mutex vec_stage_mu;
+  char* vec_stage = nullptr;
+  uint64_t vec_stage_bytes = 0;
+
   ~Context() { shutdown(); }
 
   // ------------------------------------------------------------------ errors
@@ -357,6 +363,8 @@ class Context {
       for (auto& th : dispatchers)
         if (th.joinable()) th.join();
       if (issuer.joinable()) issuer.join();
+      if (be && vec_stage) be->free_host(vec_stage);
+      vec_stage = nullptr;
       if (be) be->shutdown();
     }
   }
@@ -957,8 +965,17 @@ class Context {
       if (nbatches_out) *nbatches_out = 0;
       return SET_OK;
     }
-    char* stage_mem = (char*)be->alloc_host(total);
-    if (!stage_mem) return fail(SET_ENOMEM, "pinned staging for descriptor tables");
+    // Pinned staging for the tables and results: kept by the context and
+    // grown when a call needs more, so repeated calls allocate nothing.
+    std::lock_guard<std::mutex> vg(vec_stage_mu);
+    if (vec_stage_bytes < total) {
+      if (vec_stage) be->free_host(vec_stage);
+      vec_stage_bytes = 0;
+      vec_stage = (char*)be->alloc_host(total);
+      if (!vec_stage) return fail(SET_ENOMEM, "pinned staging for descriptor tables");
+      vec_stage_bytes = total;
+    }
+    char* stage_mem = vec_stage;
     std::vector<char*> outs(plans.size());
     uint64_t off = 0;
     int rc = SET_OK;
@@ -1012,7 +1029,6 @@ class Context {
         for (size_t q = 0; q < plans[k].idx.size(); ++q) results[plans[k].idx[q]] = r[q];
       }
     }
-    be->free_host(stage_mem);
     if (nbatches_out) *nbatches_out = plans.size();
     return rc;
   }
@@ -1295,7 +1311,7 @@ int set_ctx_create(const set_config* cfg, set_ctx** out) {
       cfg->slots_per_worker > setrt::kMaxSlots || cfg->mode < SET_MODE_SET || cfg->mode > SET_MODE_QUEUE ||
       cfg->batch_size < 0 || cfg->batch_size > cfg->num_workers * cfg->slots_per_worker ||
       cfg->callback_mode < SET_CB_EVENT_POLL ||
-      cfg->callback_mode > SET_CB_HOST_FLAG || cfg->submit_policy < 0 || cfg->submit_policy > SET_SUBMIT_SKEW0 ||
+      cfg->callback_mode > SET_CB_EVENT_BLOCKING || cfg->submit_policy < 0 || cfg->submit_policy > SET_SUBMIT_SKEW0 ||
       cfg->inflight_per_worker < 0 || cfg->queue_capacity < 0 || cfg->spin_us < 0 || cfg->staging_capacity < 0 ||
       cfg->dispatch_threads < 0 || cfg->dispatch_threads > setrt::kMaxWorkers ||
       cfg->input_copy_streams < 0 || cfg->input_copy_streams > setrt::kMaxWorkers ||
@@ -1399,7 +1415,7 @@ int set_time_stage(set_ctx* c, int template_id, int stage, int worker, int reps,
   if (st != SET_OK) return st;
   if (!c->impl.valid_template(template_id)) return SET_EINVAL;
   if (stage < 0 || stage >= c->impl.tsizes[template_id].num_stages) return SET_EINVAL;
-  if (worker < 0 || worker >= c->impl.b) return SET_EINVAL;
+  if (worker < -1 || worker >= c->impl.b) return SET_EINVAL;
   std::string err;
   int rc = c->impl.be->time_stage(template_id, stage, worker, reps, avg_us, &err);
   if (rc != SET_OK) return c->impl.fail(rc, "time_stage: " + err);

@@ -349,6 +349,54 @@ def isolated_run(dirpath: str, name_part: str) -> dict:
             "wall_per_dispatch_us": (best[-1][1] - best[1][0]) / (len(best) - 1) / 1e3}
 
 
+def pmc_values(dirpath: str, counter: str):
+    """Per-dispatch values of one counter from a rocprofv3 --pmc run
+    (*counter_collection.csv): [(dispatch_id, kernel_name, value)] in dispatch
+    order, summed over the rows of a dispatch (one per agent block or XCD)."""
+    acc = {}
+    for f in glob.glob(os.path.join(dirpath, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                if _col(row, "Counter_Name") != counter:
+                    continue
+                did = int(_col(row, "Dispatch_Id", "Correlation_Id"))
+                name = _col(row, "Kernel_Name", "Kernel_name")
+                v = float(_col(row, "Counter_Value"))
+                prev = acc.get(did, (name, 0.0))
+                acc[did] = (name, prev[1] + v)
+    return [(d, n, v) for d, (n, v) in sorted(acc.items())]
+
+
+def loop_average(values, name_part: str, skip: int):
+    """Mean counter value over the dispatches of the kernel whose name
+    contains name_part, after the first `skip` of them."""
+    v = [x for _, n, x in values if name_part in n][skip:]
+    return (sum(v) / len(v), len(v)) if v else (None, 0)
+
+
+def traffic_record(fetch_dir: str, write_dir: str, kernels: dict, skip: int, calib_bytes: int,
+                   calib_name: str = "copyBuffer") -> dict:
+    """HBM bytes per launch of each kernel from FETCH_SIZE and WRITE_SIZE runs
+    (KiB per dispatch), each scaled by the factor that makes the counter read
+    calib_bytes for a plain copy of calib_bytes (the last copy kernel of the
+    run).  kernels: {label: name_part}."""
+    fv, wv = pmc_values(fetch_dir, "FETCH_SIZE"), pmc_values(write_dir, "WRITE_SIZE")
+    fc = [x for _, n, x in fv if calib_name in n]
+    wc = [x for _, n, x in wv if calib_name in n]
+    if not fc or not wc:
+        raise ValueError("no calibration copy in the counter runs")
+    ff, wf = calib_bytes / (fc[-1] * 1024.0), calib_bytes / (wc[-1] * 1024.0)
+    out = {"fetch_factor": round(ff, 4), "write_factor": round(wf, 4), "unit": "bytes per launch", "kernels": {}}
+    for label, part in kernels.items():
+        f, nf = loop_average(fv, part, skip)
+        w, nw = loop_average(wv, part, skip)
+        if f is None or w is None:
+            continue
+        out["kernels"][label] = {"fetch": round(f * 1024 * ff), "write": round(w * 1024 * wf),
+                                 "total": round(f * 1024 * ff + w * 1024 * wf), "dispatches": min(nf, nw)}
+    return out
+
+
 def csrc_digest() -> str:
     """sha256 over the native sources (names and bytes), so a stored profile
     summary can tell whether it was taken on the current code."""

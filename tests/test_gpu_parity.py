@@ -481,7 +481,8 @@ def test_scan_full_size_and_low32(torch_gpu):
 
 # ------------------------------------------------------------------ scheduling on the device
 @pytest.mark.parametrize("callback,nd", [("event_chain", 1), ("same_stream", 1), ("event_poll", 1), ("host_flag", 1),
-                                         ("event_poll", 4), ("host_flag", 3)])
+                                         ("event_poll", 4), ("host_flag", 3), ("event_blocking", 1),
+                                         ("event_blocking", 4)])
 def test_set_mode_callbacks_and_steals(torch_gpu, callback, nd):
     """Skewed submission on the GPU: steals retarget jobs to thieves' slots; results stay exact
     (one dispatcher thread, or several each owning a share of the workers)."""
@@ -711,7 +712,7 @@ def test_captured_templates_match_explicit(torch_gpu, vec_pools, mode, copy):
     ctx.close()
 
 
-@pytest.mark.parametrize("callback", ["event_poll", "event_chain"])
+@pytest.mark.parametrize("callback", ["event_poll", "event_chain", "event_blocking"])
 def test_define_captured_templates_while_jobs_run(torch_gpu, callback):
     """Templates built by stream capture (a captured chain and a captured
     library call) are defined while another template's jobs are being
@@ -878,7 +879,7 @@ def test_async_input_copy_streams(torch_gpu, mode, copy_streams):
         assert np.array_equal(r, oracle.scan(v))
 
 
-@pytest.mark.parametrize("callback", ["event_poll", "host_flag"])
+@pytest.mark.parametrize("callback", ["event_poll", "host_flag", "event_blocking"])
 def test_prefetched_input_with_stealing(torch_gpu, callback):
     """SET with input-copy streams issues each input copy at bind.  With every job submitted to worker 0's
     queue, thieves retarget prefetched jobs (their copy is redone on the thief's stream) and the victim's
@@ -942,6 +943,7 @@ def test_prefetch_stale_copy_under_steals(torch_gpu):
 
 # ------------------------------------------------------------------ library call captured into the job graph
 @pytest.mark.parametrize("mode,copy,callback", [("set", "kernels", "host_flag"), ("set", "async_in", "event_poll"),
+                                                ("set", "async_in", "event_blocking"),
                                                 ("set", "nodes", "host_flag"), ("graph", "kernels", "host_flag"),
                                                 ("queue", "kernels", "host_flag"), ("sync", "kernels", "host_flag")])
 def test_library_scan_template(torch_gpu, mode, copy, callback):
@@ -1043,14 +1045,15 @@ def test_hotspot_pins_on_gpu(torch_gpu):
 BENCH_DMA = dict(callback="event_poll", inflight=1)
 
 
-def test_bench_config_images_full_size(torch_gpu):
+@pytest.mark.parametrize("callback", ["event_poll", "event_chain", "event_blocking"])
+def test_bench_config_images_full_size(torch_gpu, callback):
     """1024^2 images as the benchmark runs them: 8 workers x 16 slots, DMA input copies, one job in flight per
-    worker, event polling, one dispatcher thread; 24 jobs over 8 images, each image's result identical in
-    every slot it ran in."""
-    _say("bench config: images 1024^2")
+    worker, one dispatcher thread, each completion mechanism the benchmark compares; 24 jobs over 8 images,
+    each image's result identical in every slot it ran in."""
+    _say("bench config: images 1024^2", callback)
     imgs = [synth.normal_image(0, k) for k in range(8)]
     outs, _ = _run_images("set", "gauss_sobel", imgs * 3, np.float32, workers=8, slots=16, flags=0,
-                          copy="async_in", dispatchers=1, **BENCH_DMA)
+                          copy="async_in", dispatchers=1, callback=callback, inflight=1)
     for k, o in enumerate(outs):
         ref = oracle.gauss_sobel(imgs[k % 8], want_images=False)
         assert abs(int(o[64:68].view(np.uint32)[0]) - ref["count"]) <= ref["band"]

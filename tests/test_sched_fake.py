@@ -352,7 +352,7 @@ def test_invalid_arguments_rejected():
     with pytest.raises(A.SetError):
         _fake(workers=2, slots=4, inflight=5)  # more permits than slots
     with pytest.raises(A.SetError):
-        _fake(workers=2, slots=2, callback=A.SET_CB_HOST_FLAG + 1)  # no such completion mechanism
+        _fake(workers=2, slots=2, callback=A.SET_CB_EVENT_BLOCKING + 1)  # no such completion mechanism
     with pytest.raises(A.SetError):
         _fake(workers=2, slots=2, dispatchers=-1)
     for bad in (-1, 65):
