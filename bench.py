@@ -179,9 +179,10 @@ def link_probe(torch, chunk=64 << 20, total=1 << 30):
     return round(best, 2)
 
 
-def traffic_for(kernel_name):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source (else None)."""
+def traffic_for(kernel_name, workload="gauss_sobel_1024"):
+    """HBM bytes (fetched + written) per launch from committed rocprofv3 counter
+    runs of the cold launch loop, if they were taken on the current kernel
+    source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -190,7 +191,7 @@ def traffic_for(kernel_name):
         src = open(os.path.join(ROOT, "paper_2606_05495_amd", "csrc", "kernels.hip"), "rb").read()
         if rec.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
             return None
-        return rec["kernels"].get(kernel_name)
+        return rec["workloads"][workload]["kernels"][kernel_name]["total"]
     except Exception:
         return None
 

@@ -676,6 +676,91 @@ def test_serve_alone_vs_mix(torch_gpu, vec_pools):
     ctx.close()
 
 
+def test_serve_alone_vs_mix_full_sizes(torch_gpu, vec_pools):
+    """The serving mix at its own image sizes (256^2, 512^2, 1024^2, 2048^2 beside vector jobs) under a
+    device-memory budget that binds: at most a few 2048^2 slots fit at once, so later arrivals wait for
+    memory, and admission must still never exceed the budget.  Each image request gives the same bits
+    alone as in the mix and matches the oracle; each vector request likewise."""
+    _say("serve alone vs mix, full sizes")
+    x, y, xd, yd = vec_pools
+    sides = synth.SERVE_SIDES
+    budget = 96 << 20
+    ctx = Context(mode="set", workers=8, slots=4, mem_budget=budget, callback="event_poll")
+    timg = {s: ctx.define("gauss_sobel", width=s, height=s, copy="async_in") for s in sides}
+    tvec = ctx.define("saxpy_batch", max_n=1 << 20, x_pool=xd, y_pool=yd, batch_max=64, tiles_max=4096, copy="kernels")
+    fp = {s: A.set_template_footprint(ctx.cfg, ctx.templates[timg[s]])[0] for s in sides}
+    assert 2 * fp[2048] < budget < 4 * fp[2048]
+    P = 3
+    pools = {s: list(synth.serve_image_pool(0, s, count=P)) for s in sides}
+    refs = {(s, k): oracle.gauss_sobel(pools[s][k], want_images=False) for s in sides for k in range(P)}
+    offs, total = {}, 0
+    for s in sides:
+        offs[s] = total
+        total += P * 4 * s * s
+    tin, nin = pinned(total)
+    for s in sides:
+        for k in range(P):
+            nin[offs[s] + k * 4 * s * s:offs[s] + (k + 1) * 4 * s * s].view(np.float32)[:] = pools[s][k].ravel()
+    n_req = 160
+    arr = synth.poisson_arrivals(9, 20000.0, 1.0)[:n_req]
+    mix = synth.serve_mix(9, n_req)
+    vj = synth.vec_jobs(9, n_req, pool_len=len(x), n_span=256.0)
+    req = np.zeros(n_req, dtype=A.REQUEST_DTYPE)
+    req["t_arrival_ns"] = (arr * 1e9).astype(np.uint64)
+    req["worker_hint"] = -1
+    tout, nout = pinned(n_req * 128)
+    img = mix["kind"] == 0
+    side = np.array(sides)[mix["side_idx"]]
+    pk = mix["pool_idx"] % P
+    for i in range(n_req):
+        if img[i]:
+            s = int(side[i])
+            req[i]["template_id"] = timg[s]
+            req[i]["host_in"] = tin.data_ptr() + offs[s] + int(pk[i]) * 4 * s * s
+            req[i]["in_bytes"] = 4 * s * s
+            req[i]["host_out"] = tout.data_ptr() + 128 * i
+            req[i]["out_bytes"] = 72
+        else:
+            req[i]["template_id"] = tvec
+            for f in ("n", "a", "x_off", "y_off"):
+                req[i][f] = vj[f][i]
+    assert np.sum(img & (side == 2048)) >= 8
+    vres = np.zeros(n_req, np.float32)
+    done, st = A.set_serve(ctx.h, req, None, vres)
+    assert st.completed == n_req and st.failed == 0, (st.completed, st.failed)
+    assert np.all(done >= req["t_arrival_ns"])
+    hw = ctx.stats().mem_high_water
+    _say("serve full sizes: memory high water %d of %d, max backlog %d" % (hw, budget, st.max_backlog))
+    assert budget // 2 <= hw <= budget  # the budget was approached and held
+    mixed = nout.reshape(n_req, 128)[:, 64:72].copy()
+    for i in np.flatnonzero(img):
+        s = int(side[i])
+        r = refs[(s, int(pk[i]))]
+        o = mixed[i]
+        assert abs(int(o[0:4].view(np.uint32)[0]) - r["count"]) <= r["band"], (i, s)
+        assert abs(float(o[4:8].view(np.float32)[0]) - r["sum"]) <= 1e-5 * abs(r["sum"]), (i, s)
+    # alone: each request by itself through the same templates
+    nout[:] = 0
+    for i in range(n_req):
+        if img[i]:
+            s = int(side[i])
+            ctx.submit(timg[s], host_in=int(req[i]["host_in"]), in_bytes=4 * s * s, host_out=tout.data_ptr() + 128 * i,
+                       out_bytes=72)
+            ctx.drain()
+        else:
+            one = np.zeros(1, dtype=A.VEC_JOB_DTYPE)
+            for f in ("n", "a", "x_off", "y_off"):
+                one[f] = req[i][f]
+            res, _ = ctx.run_vector_jobs(tvec, one)
+            assert res[0].view(np.uint32) == vres[i].view(np.uint32), i
+            n, xo, yo = int(req[i]["n"]), int(req[i]["x_off"]), int(req[i]["y_off"])
+            S, E = oracle.saxpy_tanh_sum(x[xo:xo + n], y[yo:yo + n], req[i]["a"])
+            assert abs(res[0] - S) <= oracle.vec_tolerance(S, E)
+    alone = nout.reshape(n_req, 128)[:, 64:72].copy()
+    assert np.array_equal(alone[img], mixed[img])
+    ctx.close()
+
+
 # ------------------------------------------------------------------ stream-captured templates
 @pytest.mark.parametrize("mode,copy", [("set", "kernels"), ("set", "nodes"), ("graph", "kernels")])
 def test_captured_templates_match_explicit(torch_gpu, vec_pools, mode, copy):
