@@ -456,12 +456,15 @@ def scan_section(args, torch, configs):
 
 
 def bench_sweep(args, torch):
-    """Worker-count sweep (the batch size b of Section 5.2): per-job vector jobs
-    (the uneven vector workload's length distribution, device-resident inputs, two kernels and
-    a 68-byte D2H each) through SET (b workers, 16 slots each, min(4, b)
-    dispatcher threads), batch-sync (one graph of b chains per batch) and the
-    queue model (b workers), at b = 1 .. 64 by default; batch-sync also runs
-    larger batches (64 workers, ceil(b / 64) slots each).  Prints one JSON line."""
+    """Worker-count sweep (the batch size b of Sections 5.2 and 5.3): per-job
+    vector jobs (the uneven vector workload's length distribution,
+    device-resident inputs, two kernels and a 68-byte D2H each) through SET (b
+    workers, 16 slots each up to b = 64 and 4 above, min(4, b) dispatcher
+    threads), batch-sync (one graph of b chains per batch) and the queue model
+    (b workers), at b = 1 .. 256; batch-sync also runs larger batches (64
+    workers, ceil(b / 64) slots each).  Every point carries its untraced
+    scheduling-overhead fraction (Eq. 1-4 with per-job times measured apart,
+    see overhead_fraction).  Prints one JSON line."""
     from paper_2606_05495_amd import synth
     from paper_2606_05495_amd.runtime import Context, pinned
     import oracle
@@ -482,14 +485,17 @@ def bench_sweep(args, torch):
         if args.only not in modes:
             raise SystemExit("--only for the sweep takes set, batch or queue")
         modes = (args.only,)
+    model = None if args.only else job_time_model(args, torch, xd, yd, L)
     for b in [int(v) for v in args.sweep_b.split(",")]:
         for mode in modes:
-            # SET and the queue model run b workers (at most 64); a batch graph
+            # SET and the queue model run b workers (at most 256); a batch graph
             # of b > 64 chains spans slots: 64 workers x ceil(b / 64) slots
-            if mode != "batch" and b > 64:
+            if mode != "batch" and b > 256:
                 continue
-            nw = min(b, 64)
+            nw = min(b, 256) if mode != "batch" else min(b, 64)
             slots = 16 if mode == "set" else (-(-b // 64) if mode == "batch" else 1)
+            if mode == "set" and b > 64:
+                slots = 4  # 4 slots x b workers: the same in-flight depth per worker, fewer graph execs
             c = Context(mode=mode, workers=nw, slots=slots,
                         batch_size=b if mode == "batch" else 0, callback=args.callback,
                         dispatchers=min(args.dispatchers, nw), inflight=args.inflight)
@@ -501,29 +507,100 @@ def bench_sweep(args, torch):
                 arr[f] = js[f]
             c.submit_many(tid, arr[:min(J, 1000)])
             c.drain()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            c.submit_many(tid, arr)
-            c.drain()
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
+            each, ok = [], True
+            for _ in range(args.sweep_repeats):
+                nout[:] = 0
+                c.reset_stats()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                c.submit_many(tid, arr)
+                c.drain()
+                torch.cuda.synchronize()
+                each.append(time.perf_counter() - t0)
+                res = nout.reshape(J, 128)[:, 64:68].copy().view(np.float32).ravel()
+                ok &= all(abs(float(res[i]) - S) <= oracle.vec_tolerance(S, E) for i, (S, E) in refs.items())
             st = c.stats()
             c.close()
-            res = nout.reshape(J, 128)[:, 64:68].copy().view(np.float32).ravel()
-            ok = all(abs(float(res[i]) - S) <= oracle.vec_tolerance(S, E) for i, (S, E) in refs.items())
-            rows.append({"b": b, "mode": mode, "jobs_per_s": round(J / dt, 1), "verified": ok,
-                         "host_sync_ms": round(st.host_ns_sync / 1e6, 2), "stolen": int(st.stolen)})
-            log("b=%d %s %.0f jobs/s" % (b, mode, J / dt))
+            dt = float(np.median(each))
+            row = {"b": b, "mode": mode, "jobs_per_s": round(J / dt, 1), "verified": bool(ok),
+                   "jobs_per_s_each": [round(J / t, 1) for t in each],
+                   "host_sync_ms": round(st.host_ns_sync / 1e6, 2), "stolen": int(st.stolen), "T_measured_ms": round(dt * 1e3, 3)}
+            if model is not None:
+                row.update(overhead_fraction(model, js["n"], b, dt))
+            rows.append(row)
+            log("b=%d %s %.0f jobs/s%s" % (b, mode, J / dt, "" if model is None else
+                                          ", overhead fraction %.3f (Eq. 1 per batch), %.3f (serial)" %
+                                          (row["overhead_fraction_eq1"], row["overhead_fraction_serial"])))
     table = {}
+    frac = {}
     for r in rows:
         table.setdefault(r["b"], {})[r["mode"]] = r["jobs_per_s"]
+        if "overhead_fraction_eq1" in r:
+            frac.setdefault(r["b"], {})[r["mode"]] = {"eq1": r["overhead_fraction_eq1"],
+                                                      "serial": r["overhead_fraction_serial"]}
     line = {"metric": METRIC, "workload": "worker-count sweep, %d per-job vector jobs per point" % J,
             "unit": "jobs/s", "n_gpus": 1, "dtype": "f32", "data": "synthetic", "higher_is_better": True,
-            "vs_baseline": None, "table": table,
+            "vs_baseline": None, "table": table, "overhead_fraction": frac, "job_time_model": model,
             "set_over_batch": {b: round(t["set"] / t["batch"], 3) for b, t in table.items() if "set" in t and "batch" in t},
             "set_over_queue": {b: round(t["set"] / t["queue"], 3) for b, t in table.items() if "set" in t and "queue" in t},
             "runs": rows, "config": {"callback": args.callback, "dispatchers": args.dispatchers, "copy": args.copy}}
     print(json.dumps(line), flush=True)
+
+
+def job_time_model(args, torch, xd, yd, L, reps=64):
+    """Untraced per-job times of the per-job vector pipeline for Eq. 1: t_k(n)
+    (the stage kernels back to back) at n = 2^12 .. 2^22, and t_in / t_out (the
+    job's copies), each the mean over `reps` launches rotating over 64 slots
+    that hold jobs of that length at different pool windows (so large jobs
+    read from HBM, as in the run)."""
+    from paper_2606_05495_amd import _abi as A
+    from paper_2606_05495_amd.runtime import Context, pinned
+    W = 64
+    c = Context(mode="sync", workers=W, slots=1)
+    tid = c.define("saxpy_tanh_sum", max_n=1 << 22, x_pool=xd, y_pool=yd, copy=args.copy)
+    nst = len(c.stage_info(tid))
+    tout, _ = pinned(128 * W)
+    rng = np.random.default_rng(3)
+    tk = {}
+    for e in range(12, 23):
+        n = 1 << e
+        for w in range(W):
+            c.submit(tid, host_out=tout.data_ptr() + 128 * w, out_bytes=68, n=n, a=1.0,
+                     x_off=int(64 * rng.integers(0, (L - n) // 64)), y_off=int(64 * rng.integers(0, (L - n) // 64)))
+        c.drain()
+        tk[n] = sum(c.time_stage(tid, s_, -1, reps) for s_ in range(nst))
+    t_in = c.time_stage(tid, A.SET_STAGE_INPUT_COPY, -1, reps)
+    t_out = c.time_stage(tid, A.SET_STAGE_OUTPUT_COPY, -1, reps)
+    c.close()
+    return {"t_k_us": {str(n): round(v, 3) for n, v in tk.items()}, "t_in_us": round(t_in, 3),
+            "t_out_us": round(t_out, 3), "copy": args.copy, "reps": reps, "slots": W}
+
+
+def model_tk(model, n):
+    """t_k(n) by linear interpolation in n between the measured powers of two."""
+    pts = sorted((int(k), v) for k, v in model["t_k_us"].items())
+    ns = np.array([p[0] for p in pts], np.float64)
+    ts = np.array([p[1] for p in pts], np.float64)
+    return np.interp(np.asarray(n, np.float64), ns, ts)
+
+
+def overhead_fraction(model, n, b, T_measured_s):
+    """Scheduling-overhead fraction t_schedule / T_measured (Section 5.3, Eq. 4)
+    with T_ideal from Eq. 1 per batch of b consecutive jobs in submission order:
+    the batch's input copies back to back plus the largest kernel + output
+    copy time in it (for identical jobs exactly b t_in + t_k + t_out).  The b = 1
+    reading (every job's copies and kernels back to back, no overlap) beside it."""
+    tk = model_tk(model, n)
+    t_in, t_out = model["t_in_us"], model["t_out_us"]
+    J = len(tk)
+    ideal = 0.0
+    for i in range(0, J, b):
+        seg = tk[i:i + b]
+        ideal += len(seg) * t_in + float(seg.max()) + t_out
+    serial = float(J * (t_in + t_out) + tk.sum())
+    T = T_measured_s * 1e6
+    return {"T_ideal_eq1_ms": round(ideal / 1e3, 3), "overhead_fraction_eq1": round(1.0 - ideal / T, 4),
+            "T_ideal_serial_ms": round(serial / 1e3, 3), "overhead_fraction_serial": round(1.0 - serial / T, 4)}
 
 
 def bench_hotspot(args, torch):
@@ -744,8 +821,10 @@ def main():
     ap.add_argument("--hot-side", type=int, default=256)
     ap.add_argument("--hot-steps", type=int, default=16)
     ap.add_argument("--hot-jobs", type=int, default=10000)
-    ap.add_argument("--sweep-b", default="1,2,4,8,16,32,64", help="worker counts of the sweep workload")
+    ap.add_argument("--sweep-b", default="1,2,4,8,16,32,64,128,256,512,1024,2048,4096",
+                    help="batch sizes b of the sweep workload (SET and the queue model stop at 256)")
     ap.add_argument("--sweep-jobs", type=int, default=20000)
+    ap.add_argument("--sweep-repeats", type=int, default=3, help="timed passes per sweep point (median reported)")
     ap.add_argument("--scan-jobs", type=int, default=20000)
     ap.add_argument("--scan-ring", type=int, default=48)
     ap.add_argument("--rates", default="2000,10000,40000")
@@ -973,6 +1052,12 @@ def main_with(args, raw):
     dom = int(np.argmax(stage_us))
     dom_name, dom_bytes = stages[dom]
     achieved = dom_bytes / (stage_us[dom] * 1e-6) / 1e9
+    # Eq. 1's per-job terms, untraced: the job's input copy (DMA from pinned
+    # memory), its stage kernels (cold, as above) and its output copy
+    from paper_2606_05495_amd import _abi as A
+    eq1 = {"t_in_us": round(ctx.time_stage(tid, A.SET_STAGE_INPUT_COPY, -1, 50), 3),
+           "t_k_us": round(float(sum(stage_us)), 3),
+           "t_out_us": round(ctx.time_stage(tid, A.SET_STAGE_OUTPUT_COPY, -1, 50), 3)}
     ctx.close()
     ref = copy_reference(torch, int(dom_bytes), args.stage_reps)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -1031,6 +1116,19 @@ def main_with(args, raw):
             "%d jobs: 8 MiB int32 H2D -> inclusive int64 scan -> 16 MiB D2H, 8 workers" % sa.scan_jobs),
             config={"copy": sa.copy, "callback": sa.callback, "dispatchers": sa.dispatchers,
                     "inflight_per_worker": sa.inflight})
+
+    # Scheduling-overhead fraction t_schedule / T_measured (Section 5.3, Eq. 4)
+    # with T_ideal from Eq. 1 per batch of b jobs (b = the workers or the batch
+    # size; 1 for the synchronous model), and the serial reading beside it.
+    def frac(jobs, T_s, b):
+        ideal = (jobs / b) * (b * eq1["t_in_us"] + eq1["t_k_us"] + eq1["t_out_us"])
+        serial = jobs * (eq1["t_in_us"] + eq1["t_k_us"] + eq1["t_out_us"])
+        T = T_s * 1e6
+        return {"T_measured_ms": round(T / 1e3, 2), "eq1": round(1 - ideal / T, 4), "serial": round(1 - serial / T, 4)}
+    overhead = {"terms": eq1, "set": frac(n_total, dt, args.workers)}
+    for m, b_ in (("batch", args.batch), ("queue", args.workers), ("sync", 1)):
+        if m in extra:
+            overhead[m] = frac(args.jobs * args.baseline_steps, args.jobs * args.baseline_steps / extra[m]["jobs_per_s"], b_)
 
     cpu = None
     if not args.no_cpu:
@@ -1092,6 +1190,7 @@ def main_with(args, raw):
         "mean_kernel_gap_kernels_only_us": tset.get("mean_kernel_gap"),
         "gpu_idle_fraction": tset.get("gpu_idle_fraction"),
         "timeline": tl,
+        "overhead_fraction": overhead,
         "completion_mechanisms": mech,
         "configs": sections,
         "roofline": roofline,

@@ -214,7 +214,7 @@ typedef struct set_config {
     int32_t mode;                /* enum set_mode */
     int32_t backend;             /* enum set_backend */
     int32_t device;              /* HIP device ordinal */
-    int32_t num_workers;         /* b: workers, one stream each (Section 4.2 (1)); 1..64 */
+    int32_t num_workers;         /* b: workers, one stream each (Section 4.2 (1)); 1..256 */
     int32_t slots_per_worker;    /* d: buffer slots (one graph exec each) per worker; 1..64 */
     int32_t queue_capacity;      /* capacity of each per-worker queue Q_i; 0 = max(1, d - inflight) */
     int32_t inflight_per_worker; /* launch permits per worker in the free pool; 0 = min(2, d) */
@@ -312,7 +312,7 @@ typedef struct set_out_header {
 
 typedef struct set_stats {
     uint64_t submitted, completed, stolen, failed;
-    uint64_t launches_per_worker[64];
+    uint64_t launches_per_worker[64];  /* workers 0..63 (a context may have up to 256) */
     uint64_t host_ns_bind;       /* submitter (or caller) time spent binding parameters */
     uint64_t host_ns_launch;     /* dispatcher time in graph launch + callback registration */
     uint64_t host_ns_callback;   /* time spent inside completion callbacks */
@@ -427,7 +427,13 @@ int set_get_job_times(set_ctx *c, set_job_times *out, uint64_t max, uint64_t *co
  * when it is small).  worker == -1: launch r uses slot r mod (b*d) of the
  * template, all on worker 0's stream, so with enough slots the kernel reads
  * and writes HBM.  The slots' current contents are used as input, so run
- * jobs on them first.  Requires a drained context. */
+ * jobs on them first.  stage == SET_STAGE_INPUT_COPY / SET_STAGE_OUTPUT_COPY
+ * times the template's host-to-device / device-to-host copy of its largest
+ * job (Eq. 1's t_in and t_out) the way a job performs it (copy kernel or DMA)
+ * against a library-owned pinned buffer; 0 us for a pipeline without that
+ * copy.  Requires a drained context. */
+#define SET_STAGE_INPUT_COPY (-1)
+#define SET_STAGE_OUTPUT_COPY (-2)
 int set_time_stage(set_ctx *c, int template_id, int stage, int worker, int reps, double *avg_us);
 
 /* Bucketed persistent batching of vector jobs (template of pipeline

@@ -39,6 +39,7 @@ SET_TF_DEBUG, SET_TF_SCAN_LOW32, SET_TF_CAPTURE = 0x1, 0x2, 0x4
 SET_COPY_KERNELS, SET_COPY_NODES, SET_COPY_ASYNC_IN = 0, 1, 2
 COPY_MODES = {"nodes": SET_COPY_NODES, "kernels": SET_COPY_KERNELS, "async_in": SET_COPY_ASYNC_IN}
 SET_NONBLOCK = 0x1
+SET_STAGE_INPUT_COPY, SET_STAGE_OUTPUT_COPY = -1, -2
 SET_OUT_MAGIC = 0x5E7D0A11
 
 MODES = {"set": SET_MODE_SET, "sync": SET_MODE_SYNC, "graph": SET_MODE_GRAPH, "batch": SET_MODE_BATCH_SYNC,

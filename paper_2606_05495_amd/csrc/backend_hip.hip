@@ -497,15 +497,37 @@ class HipBackend : public Backend {
     // library-call templates list [stage 0, library call, stage 1]
     const bool lib = lib_template(p.t);
     const int nlisted = sl0.nstages + (lib ? 1 : 0);
-    if (stage < 0 || stage >= nlisted) {
+    const bool copy_in = stage == SET_STAGE_INPUT_COPY, copy_out = stage == SET_STAGE_OUTPUT_COPY;
+    if (!copy_in && !copy_out && (stage < 0 || stage >= nlisted)) {
       if (err) *err = "no such stage";
       return SET_EINVAL;
     }
     const bool lib_call = lib && stage == 1;
     const int ks = (lib && stage == 2) ? 1 : stage;
     hipStream_t st = streams_[rotate ? 0 : worker];
+    // The copies as a job performs them (copy kernel, or DMA for memcpy nodes
+    // and async input copies), of the template's largest input / output,
+    // between the slot and the template's own pinned placeholder buffer.
+    const uint64_t in_b = pipeline_in_bytes(p.t, 0), out_b = pipeline_out_bytes(p.t, 0);
     auto once = [&](int r) -> hipError_t {
       Slot& sl = p.slots[first + (size_t)r % nslots];
+      if (copy_in) {
+        if (in_b == 0) return hipSuccess;
+        if (in_by_kernel(p.t)) {
+          CopyArgs ca{p.placeholder, sl.base + p.L.in, in_b};
+          void* av[1] = {&ca};
+          return hipLaunchKernel((const void*)&k_copy_in, dim3(kCopyBlocks), dim3(kBlock), av, 0, st);
+        }
+        return hipMemcpyAsync(sl.base + p.L.in, p.placeholder, in_b, hipMemcpyHostToDevice, st);
+      }
+      if (copy_out) {
+        if (out_by_kernel(p.t)) {
+          CopyArgs ca{sl.base + p.L.out, p.placeholder, out_b};
+          void* av[1] = {&ca};
+          return hipLaunchKernel((const void*)&k_copy_out, dim3(d2h_copy_blocks(p.L.out_cap)), dim3(kBlock), av, 0, st);
+        }
+        return hipMemcpyAsync(p.placeholder, sl.base + p.L.out, out_b, hipMemcpyDeviceToHost, st);
+      }
       if (lib_call) return library_stage(p, sl, st);
       return hipLaunchKernel(sl.func[ks], sl.grid[ks], dim3(kBlock), sl.argv[ks], 0, st);
     };

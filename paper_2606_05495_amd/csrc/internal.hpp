@@ -24,7 +24,9 @@ inline uint64_t now_ns() {
 // that have no context: a failed set_ctx_create, the no-allocation call).
 void set_thread_error(const std::string& msg);
 
-constexpr int kMaxWorkers = 64;
+constexpr int kMaxWorkers = 256;     // b: workers (streams) of a context
+constexpr int kMaxThreads = 64;      // dispatcher threads, input-copy streams
+constexpr int kStatWorkers = 64;     // workers whose launches set_stats lists
 constexpr int kMaxSlots = 64;
 constexpr int kMaxTemplates = 16;
 constexpr int kMaxStages = 40;

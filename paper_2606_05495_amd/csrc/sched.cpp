@@ -1234,7 +1234,7 @@ class Context {
     o->completed = st_completed.load();
     o->stolen = st_stolen.load();
     o->failed = st_failed.load();
-    for (int i = 0; i < kMaxWorkers; ++i) o->launches_per_worker[i] = st_launch[i].load();
+    for (int i = 0; i < kStatWorkers; ++i) o->launches_per_worker[i] = st_launch[i].load();
     o->host_ns_bind = st_ns_bind.load();
     o->host_ns_launch = st_ns_launch.load();
     o->host_ns_callback = st_ns_cb.load();
@@ -1313,8 +1313,8 @@ int set_ctx_create(const set_config* cfg, set_ctx** out) {
       cfg->callback_mode < SET_CB_EVENT_POLL ||
       cfg->callback_mode > SET_CB_EVENT_BLOCKING || cfg->submit_policy < 0 || cfg->submit_policy > SET_SUBMIT_SKEW0 ||
       cfg->inflight_per_worker < 0 || cfg->queue_capacity < 0 || cfg->spin_us < 0 || cfg->staging_capacity < 0 ||
-      cfg->dispatch_threads < 0 || cfg->dispatch_threads > setrt::kMaxWorkers ||
-      cfg->input_copy_streams < 0 || cfg->input_copy_streams > setrt::kMaxWorkers ||
+      cfg->dispatch_threads < 0 || cfg->dispatch_threads > setrt::kMaxThreads ||
+      cfg->input_copy_streams < 0 || cfg->input_copy_streams > setrt::kMaxThreads ||
       (cfg->backend != SET_BACKEND_HIP && cfg->backend != SET_BACKEND_FAKE)) {
     setrt::g_create_error = "invalid configuration";
     return SET_EINVAL;
@@ -1414,7 +1414,9 @@ int set_time_stage(set_ctx* c, int template_id, int stage, int worker, int reps,
   int st = c->impl.check_sticky();
   if (st != SET_OK) return st;
   if (!c->impl.valid_template(template_id)) return SET_EINVAL;
-  if (stage < 0 || stage >= c->impl.tsizes[template_id].num_stages) return SET_EINVAL;
+  if (stage != SET_STAGE_INPUT_COPY && stage != SET_STAGE_OUTPUT_COPY &&
+      (stage < 0 || stage >= c->impl.tsizes[template_id].num_stages))
+    return SET_EINVAL;
   if (worker < -1 || worker >= c->impl.b) return SET_EINVAL;
   std::string err;
   int rc = c->impl.be->time_stage(template_id, stage, worker, reps, avg_us, &err);

@@ -92,6 +92,24 @@ def test_skewed_submission_forces_steals_and_retargets(nd):
         assert sum(st.launches_per_worker[1:4]) > 0
 
 
+def test_256_workers_with_steals():
+    """b up to 256 workers (the largest batch size the SET sweep runs): every job completes once,
+    jobs skewed onto worker 0 are stolen by the others, and b = 257 is refused."""
+    with _fake(workers=256, slots=2, submit_policy=A.SET_SUBMIT_SKEW0, dispatchers=4) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        arr, outs = _vec_jobs(ctx, tid, 600, 2000)
+        ctx.submit_many(tid, arr)
+        ctx.drain()
+        st = ctx.stats()
+        assert st.completed == 600 and st.failed == 0
+        assert st.stolen > 0
+        h = _headers(outs)
+        assert np.array_equal(np.sort(h["job_id"]), np.arange(600))
+        assert len(set(h["worker"].tolist())) > 1
+    with pytest.raises(A.SetError):
+        _fake(workers=257, slots=2)
+
+
 @pytest.mark.parametrize("nd", [1, 3])
 def test_no_stealing_keeps_jobs_local(nd):
     with _fake(workers=4, slots=8, submit_policy=A.SET_SUBMIT_SKEW0, stealing=False, dispatchers=nd) as ctx:
