@@ -228,12 +228,18 @@ def _vec_persistent(args, torch, A, autotune, Context, js, vj, xd, yd, J, total_
     out = {}
     # ---- bucketed persistent batches, dispatched by SET
     ctx = Context(mode="set", workers=args.workers, slots=4, callback=args.callback, dispatchers=args.dispatchers)
-    tid = ctx.define("saxpy_batch", max_n=int(js["n"].max()), x_pool=xd, y_pool=yd, batch_max=args.batch_max,
-                     tiles_max=args.tiles_max, copy=args.copy)
-    tuning = None if args.no_tune else autotune.load()
+
+    def define(block):
+        return ctx.define("saxpy_batch", max_n=int(js["n"].max()), x_pool=xd, y_pool=yd, batch_max=args.batch_max,
+                          tiles_max=args.tiles_max, copy=args.copy, block=block)
+
+    cache = args.tune_cache or autotune.DEFAULT_CACHE
+    tuning = None if (args.no_tune or args.retune) else autotune.load(cache)
+    block = 0 if (args.no_tune or args.retune) else autotune.load_block(cache)
     if tuning is None and not args.no_tune:
-        log("autotuning buckets")
-        tuning = autotune.tune(ctx, tid, vj, calib=512, log=log)
+        log("autotuning block size and buckets")
+        tuning, block = autotune.tune_blocks(ctx, define, vj, calib=512, cache=cache, log=log)
+    tid = define(block)
     res = np.zeros(J, np.float32)
     ctx.run_vector_jobs(tid, vj, res, tuning)  # warm-up
     torch.cuda.synchronize()
@@ -242,7 +248,8 @@ def _vec_persistent(args, torch, A, autotune, Context, js, vj, xd, yd, J, total_
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     out["persistent"] = {"jobs_per_s": round(J / dt, 1), "batches": int(nb), "verified": check(res),
-                         "effective_GBps": round(total_bytes / dt / 1e9, 1), "tuned": tuning is not None}
+                         "effective_GBps": round(total_bytes / dt / 1e9, 1), "tuned": tuning is not None,
+                         "block": block or 256}
     ctx.close()
     return out
 
@@ -734,8 +741,9 @@ def bench_serve(args, torch):
                       input_copy_streams=args.input_copy_streams)
         timg = {s_: ctx.define("gauss_sobel", width=s_, height=s_, copy=args.copy) for s_ in sides}
         tvec = ctx.define("saxpy_batch", max_n=4194303, x_pool=xd, y_pool=yd, batch_max=args.batch_max,
-                          tiles_max=args.tiles_max, copy=args.copy)
-        tuning = None if args.no_tune else autotune.load()
+                          tiles_max=args.tiles_max, copy=args.copy,
+                          block=0 if args.no_tune else autotune.load_block(args.tune_cache or autotune.DEFAULT_CACHE))
+        tuning = None if args.no_tune else autotune.load(args.tune_cache or autotune.DEFAULT_CACHE)
         arr = synth.poisson_arrivals(int(rate), rate, args.serve_seconds)
         n = len(arr)
         mix = synth.serve_mix(int(rate), n)
@@ -836,6 +844,8 @@ def main():
     ap.add_argument("--batch-max", type=int, default=1024)
     ap.add_argument("--tiles-max", type=int, default=16384)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--retune", action="store_true", help="vector workloads: tune block, item sizes and grids afresh")
+    ap.add_argument("--tune-cache", default=None, help="tuning cache file (default: the package's tuning/vec_batch.json)")
     ap.add_argument("--image-pool", type=int, default=61, help="distinct images the jobs cycle through")
     ap.add_argument("--mechanisms", default="event_poll,event_chain,event_blocking",
                     help="SET completion mechanisms the image workload also runs (comma list; empty: none)")
@@ -843,7 +853,9 @@ def main():
     ap.add_argument("--no-sections", action="store_true",
                     help="image workload: skip the vector and scan sections of the default line")
     ap.add_argument("--no-trace", action="store_true", help="image workload: no traced child runs")
-    ap.add_argument("--trace-modes", default="set,batch")
+    ap.add_argument("--trace-modes", default="set,batch,queue")
+    ap.add_argument("--trace-batch-copy", default="kernels", choices=["nodes", "kernels", "async_in"],
+                    help="copy mechanism of the traced batch-sync child (its fastest in every measured run)")
     ap.add_argument("--trace-jobs", type=int, default=2000)
     ap.add_argument("--trace-timeout", type=int, default=240)
     ap.add_argument("--only", choices=["set", "batch", "sync", "queue"], default=None,
@@ -922,9 +934,12 @@ def traced_timelines(args, modes):
     env = dict(os.environ, TMPDIR="/tmp")
     for mode in modes:
         d = tempfile.mkdtemp(prefix="set_trace_%s_" % mode, dir="/tmp")
+        # each mode traced with the copy mechanism it is scored with: SET's own,
+        # the baselines' fastest (copy kernels for batch-sync, DMA for the queue model)
+        copy = args.copy if mode == "set" else {"batch": args.trace_batch_copy, "queue": "async_in"}.get(mode, "kernels")
         child = [sys.executable, os.path.abspath(__file__), "--only", mode, "--steps", "2", "--warmup", "1",
                  "--jobs", str(args.trace_jobs), "--image-pool", "8", "--baseline-steps", "2", "--no-cpu",
-                 "--callback", args.callback, "--copy", args.copy, "--dispatchers", str(args.dispatchers),
+                 "--callback", args.callback, "--copy", copy, "--dispatchers", str(args.dispatchers),
                  "--inflight", str(args.inflight), "--workers", str(args.workers), "--slots", str(args.slots),
                  "--batch", str(args.batch)]
         cmd = [prof, "--kernel-trace", "--memory-copy-trace", "--output-format", "csv", "-d", d, "-o", "trace", "--"] + child
@@ -944,6 +959,7 @@ def traced_timelines(args, modes):
             m = trace.analyze_dir(d, batch=args.batch if mode == "batch" else 0, library_window=True)
             rec = {k: m.get(k) for k in TRACE_KEYS}
             rec["traced_jobs_per_s"] = res.get("jobs_per_s")
+            rec["copy"] = copy
             rec["verified"] = res.get("verified")
             out["modes"][mode] = rec
         except subprocess.TimeoutExpired:
@@ -1117,14 +1133,24 @@ def main_with(args, raw):
             config={"copy": sa.copy, "callback": sa.callback, "dispatchers": sa.dispatchers,
                     "inflight_per_worker": sa.inflight})
 
-    # Scheduling-overhead fraction t_schedule / T_measured (Section 5.3, Eq. 4)
-    # with T_ideal from Eq. 1 per batch of b jobs (b = the workers or the batch
-    # size; 1 for the synchronous model), and the serial reading beside it.
+    log("link probe")
+    link_peak = link_probe(torch)
+    # Scheduling-overhead fraction t_schedule / T_measured (Section 5.3, Eq. 4).
+    # t_in is the input at the link's probed rate (several copies in flight
+    # share the link at that rate; one copy alone on one stream is slower, and
+    # is given beside it).  Two readings of T_ideal: Eq. 1 per batch of b jobs
+    # (b = the workers or the batch size; 1 for the synchronous model), and the
+    # link floor: every job's input back to back over the link, plus one job's
+    # kernels and output copy.
+    eq1["t_in_one_stream_us"] = eq1.pop("t_in_us")
+    eq1["t_in_us"] = round(ib / (link_peak * 1e3), 3) if link_peak else eq1["t_in_one_stream_us"]
+
     def frac(jobs, T_s, b):
-        ideal = (jobs / b) * (b * eq1["t_in_us"] + eq1["t_k_us"] + eq1["t_out_us"])
-        serial = jobs * (eq1["t_in_us"] + eq1["t_k_us"] + eq1["t_out_us"])
+        per = eq1["t_k_us"] + eq1["t_out_us"]
+        ideal = (jobs / b) * (b * eq1["t_in_us"] + per)
+        floor = jobs * eq1["t_in_us"] + per
         T = T_s * 1e6
-        return {"T_measured_ms": round(T / 1e3, 2), "eq1": round(1 - ideal / T, 4), "serial": round(1 - serial / T, 4)}
+        return {"T_measured_ms": round(T / 1e3, 2), "eq1": round(1 - ideal / T, 4), "link_floor": round(1 - floor / T, 4)}
     overhead = {"terms": eq1, "set": frac(n_total, dt, args.workers)}
     for m, b_ in (("batch", args.batch), ("queue", args.workers), ("sync", 1)):
         if m in extra:
@@ -1137,8 +1163,6 @@ def main_with(args, raw):
 
     h2d = ib * set_jps / 1e9
     per_step = [args.jobs / t for t in step_s]
-    log("link probe")
-    link_peak = link_probe(torch)
     tl = traced
     tset = (tl or {}).get("modes", {}).get("set", {})
     line = {

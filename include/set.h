@@ -262,7 +262,10 @@ typedef struct set_job_template {
     const float *dev_x_pool;     /* SAXPY: borrowed device pool of x values */
     const float *dev_y_pool;     /* SAXPY: borrowed device pool of y values */
     uint64_t pool_len;           /* SAXPY: elements in each pool */
-    int32_t block;               /* tuning: threads per block (0 = default) */
+    int32_t block;               /* SET_PIPE_SAXPY_BATCH_F32: threads per block of the persistent work-item
+                                  * kernel, 128 / 256 / 512 / 1024 (0 = 256).  It fixes the order in which a
+                                  * work item's elements are summed, so it is a property of the template: a
+                                  * job's S depends on (n, its item size, this block).  Other pipelines: 0 */
     int32_t grid;                /* tuning: grid cap for streaming kernels (0 = default) */
     uint32_t batch_max;          /* SAXPY batch: most jobs per batch (descriptor table capacity) */
     uint32_t tiles_max;          /* SAXPY batch: most (job, tile) work items per batch */

@@ -21,7 +21,7 @@ TSAN_BIN = os.path.join(OBJ, "sched_tsan_test")
 ARCH = os.environ.get("SET_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HIP_SOURCES = ["kernels.hip", "backend_hip.hip", "noalloc.hip"]
+HIP_SOURCES = ["kernels.hip", "backend_hip.hip", "noalloc.hip", "lib_scan.hip"]
 CPP_SOURCES = ["sched.cpp", "layout.cpp", "backend_fake.cpp"]
 HEADERS = ["internal.hpp", "kernels.hpp", "tiles.hpp"]
 
@@ -102,8 +102,31 @@ def build_tsan(force: bool = False) -> str:
     return TSAN_BIN
 
 
+TSAN_HIP_BIN = os.path.join(OBJ, "hip_backend_tsan_test")
+STUB = os.path.join(CSRC, "hipstub")
+
+
+def build_tsan_hip(force: bool = False) -> str:
+    """The HIP backend's host code (backend_hip.hip compiled as C++) with the
+    scheduler core, over the host-only runtime stand-in in csrc/hipstub, and a
+    stress driver, built with -fsanitize=thread by g++ (no device code)."""
+    os.makedirs(OBJ, exist_ok=True)
+    hip_src = os.path.join(CSRC, "backend_hip.hip")
+    srcs = [os.path.join(STUB, "hip_stub.cpp"), os.path.join(STUB, "tsan_hip_main.cpp")] + [
+        os.path.join(CSRC, s) for s in ("sched.cpp", "layout.cpp", "backend_fake.cpp")]
+    deps = srcs + [hip_src, os.path.join(STUB, "hip", "hip_runtime.h")]
+    if not force and os.path.exists(TSAN_HIP_BIN) and os.path.getmtime(TSAN_HIP_BIN) >= max(
+            max(os.path.getmtime(s) for s in deps), _deps_mtime()):
+        return TSAN_HIP_BIN
+    cmd = ["g++", "-O1", "-g", "-std=c++17", "-fsanitize=thread", "-I" + STUB, "-I" + INCLUDE, "-I" + CSRC,
+           "-pthread", "-Wno-unused-function", "-o", TSAN_HIP_BIN, "-x", "c++", hip_src, "-x", "none"] + srcs
+    _run_all([cmd])
+    return TSAN_HIP_BIN
+
+
 if __name__ == "__main__":
     force = "--force" in sys.argv
     print(build(force=force, verbose=True))
     if "--tsan" in sys.argv:
         print(build_tsan(force=force))
+        print(build_tsan_hip(force=force))

@@ -8,8 +8,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
-#include <rocprim/device/device_scan.hpp>
-#include <rocprim/iterator/transform_iterator.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -75,6 +73,7 @@ struct Slot {
   int nstages = 0;
   const void* func[kMaxStages] = {};
   dim3 grid[kMaxStages];
+  unsigned block[kMaxStages] = {};  // threads per block of each stage
   void* argv[kMaxStages][1] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -131,17 +130,6 @@ inline bool out_by_kernel(const set_job_template& t) { return t.copy_mode != SET
 // graph (between stage kernel 0 and stage kernel 1).
 inline bool lib_template(const set_job_template& t) { return t.pipeline == SET_PIPE_SCAN_LIB_I32_I64; }
 
-struct WidenI32 {
-  __host__ __device__ int64_t operator()(int32_t v) const { return (int64_t)v; }
-};
-
-// The library stage: rocPRIM's device-wide inclusive scan of the slot's
-// int32 input into its int64 output, widening on load.  With ws == nullptr
-// only the workspace size is computed.
-hipError_t lib_scan(void* ws, size_t& ws_bytes, const int32_t* in, int64_t* out, size_t n, hipStream_t st) {
-  auto it = rocprim::make_transform_iterator(in, WidenI32{});
-  return rocprim::inclusive_scan(ws, ws_bytes, it, out, n, rocprim::plus<int64_t>(), st, false);
-}
 
 thread_local int t_dev = -1;
 
@@ -415,7 +403,7 @@ class HipBackend : public Backend {
     }
     for (int i = 0; i < sl.nstages; ++i) {
       if (i == 1) HIPCK(library_stage(p, sl, st));
-      HIPCK(hipLaunchKernel(sl.func[i], sl.grid[i], dim3(kBlock), sl.argv[i], 0, st));
+      HIPCK(hipLaunchKernel(sl.func[i], sl.grid[i], dim3(sl.block[i]), sl.argv[i], 0, st));
     }
     if (out_by_kernel(p.t)) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, sl.host_out, sl.out_bytes};
@@ -529,7 +517,7 @@ class HipBackend : public Backend {
         return hipMemcpyAsync(p.placeholder, sl.base + p.L.out, out_b, hipMemcpyDeviceToHost, st);
       }
       if (lib_call) return library_stage(p, sl, st);
-      return hipLaunchKernel(sl.func[ks], sl.grid[ks], dim3(kBlock), sl.argv[ks], 0, st);
+      return hipLaunchKernel(sl.func[ks], sl.grid[ks], dim3(sl.block[ks]), sl.argv[ks], 0, st);
     };
     hipEvent_t e0, e1;
     HIPCK(hipEventCreate(&e0));
@@ -713,9 +701,10 @@ class HipBackend : public Backend {
     const set_job_template& t = p.t;
     const int h = (int)t.height, w = (int)t.width;
     const int64_t npix = (int64_t)h * w;
-    auto stage = [&](const void* f, dim3 g, void* args) {
+    auto stage = [&](const void* f, dim3 g, void* args, unsigned blk = kBlock) {
       sl.func[sl.nstages] = f;
       sl.grid[sl.nstages] = g;
+      sl.block[sl.nstages] = blk;
       sl.argv[sl.nstages][0] = args;
       ++sl.nstages;
     };
@@ -774,7 +763,12 @@ class HipBackend : public Backend {
                              sc.hdr, JobScalars{}};
         sl.vbf = VecBatchFinalArgs{(const uint8_t*)(b + L.in), (const float*)(b + L.scratch), work,
                                    (float*)(b + L.out + 64), sc};
-        stage((const void*)&k_vec_batch_tiles, dim3(t.grid > 0 ? (unsigned)t.grid : (unsigned)kVecBatchGrid), &sl.vb);
+        const int vbb = vec_batch_block(t);
+        const void* vbk = vbb == 128   ? (const void*)&k_vec_batch_tiles<128>
+                          : vbb == 512 ? (const void*)&k_vec_batch_tiles<512>
+                          : vbb == 1024 ? (const void*)&k_vec_batch_tiles<1024>
+                                        : (const void*)&k_vec_batch_tiles<256>;
+        stage(vbk, dim3(t.grid > 0 ? (unsigned)t.grid : (unsigned)kVecBatchGrid), &sl.vb, (unsigned)vbb);
         stage((const void*)&k_vec_batch_final, dim3((t.batch_max + kBlock - 1) / kBlock), &sl.vbf);
         break;
       }
@@ -869,7 +863,7 @@ class HipBackend : public Backend {
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(sl.func[i]);
     kp.gridDim = sl.grid[i];
-    kp.blockDim = dim3(kBlock);
+    kp.blockDim = dim3(sl.block[i]);
     kp.sharedMemBytes = 0;
     kp.kernelParams = sl.argv[i];
     kp.extra = nullptr;
@@ -989,7 +983,7 @@ class HipBackend : public Backend {
     }
     for (int i = 0; i < sl.nstages; ++i) {
       if (i == 1) HIPCK(library_stage(p, sl, st));
-      HIPCK(hipLaunchKernel(sl.func[i], sl.grid[i], dim3(kBlock), sl.argv[i], 0, st));
+      HIPCK(hipLaunchKernel(sl.func[i], sl.grid[i], dim3(sl.block[i]), sl.argv[i], 0, st));
     }
     if (out_by_kernel(p.t)) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, p.placeholder, p.L.out_cap};

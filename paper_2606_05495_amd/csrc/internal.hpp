@@ -24,6 +24,9 @@ inline uint64_t now_ns() {
 // that have no context: a failed set_ctx_create, the no-allocation call).
 void set_thread_error(const std::string& msg);
 
+// Threads per block of the vector-batch work-item kernel of template t.
+inline int vec_batch_block(const set_job_template& t) { return t.block > 0 ? t.block : kBlock; }
+
 constexpr int kMaxWorkers = 256;     // b: workers (streams) of a context
 constexpr int kMaxThreads = 64;      // dispatcher threads, input-copy streams
 constexpr int kStatWorkers = 64;     // workers whose launches set_stats lists

@@ -699,12 +699,13 @@ __global__ __launch_bounds__(kBlock) void k_vec_final(VecFinalArgs a) {
 // its job by binary search over the descriptors' first-item indices, reduce
 // that item's elements (fixed order within the item) and store the item's
 // partial.  Which block takes which item does not change any result.
+template <int BLOCK>
 __device__ inline float vec_range_sum(const float* __restrict__ x, const float* __restrict__ y, float av,
                                       uint64_t beg, uint64_t end, bool aligned) {
   float acc = 0.f;
   if (aligned) {
     const uint64_t vend = beg + ((end - beg) & ~3ull);
-    for (uint64_t i = beg + 4ull * threadIdx.x; i < vend; i += 4ull * kBlock) {
+    for (uint64_t i = beg + 4ull * threadIdx.x; i < vend; i += 4ull * BLOCK) {
       const float4 xv = *reinterpret_cast<const float4*>(x + i);
       const float4 yv = *reinterpret_cast<const float4*>(y + i);
       acc += tanhf(fmaf(av, xv.x, yv.x));
@@ -715,13 +716,36 @@ __device__ inline float vec_range_sum(const float* __restrict__ x, const float* 
     if (threadIdx.x == 0)
       for (uint64_t i = vend; i < end; ++i) acc += tanhf(fmaf(av, x[i], y[i]));
   } else {
-    for (uint64_t i = beg + threadIdx.x; i < end; i += kBlock) acc += tanhf(fmaf(av, x[i], y[i]));
+    for (uint64_t i = beg + threadIdx.x; i < end; i += BLOCK) acc += tanhf(fmaf(av, x[i], y[i]));
   }
   return acc;
 }
 
-__global__ __launch_bounds__(kBlock) void k_vec_batch_tiles(VecBatchArgs a) {
-  __shared__ float s4f[4];
+// Pairwise sum of W values in a fixed tree ((s0+s1)+(s2+s3)) + ...
+template <int W>
+__device__ inline float tree_sum_f32(const float* s) {
+  if constexpr (W == 1) {
+    return s[0];
+  } else {
+    return tree_sum_f32<W / 2>(s) + tree_sum_f32<W / 2>(s + W / 2);
+  }
+}
+
+// Block sum of a BLOCK-thread block: wave sums, then a fixed pairwise tree
+// over the waves (for 256 threads the same order as block_sum_f32).
+template <int BLOCK>
+__device__ inline float block_sum_f32_w(float v, float* sw) {
+  v = wave_sum_f32(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sw[wave] = v;
+  __syncthreads();
+  return tree_sum_f32<BLOCK / 64>(sw);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_vec_batch_tiles(VecBatchArgs a) {
+  __shared__ float s4f[BLOCK / 64];
   __shared__ uint32_t s_item;
   __shared__ uint32_t s_job;
   if (blockIdx.x == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
@@ -747,12 +771,17 @@ __global__ __launch_bounds__(kBlock) void k_vec_batch_tiles(VecBatchArgs a) {
     const VecBatchDesc d = D[s_job];
     const uint64_t beg = (uint64_t)(t - d.tile_start) * d.tile_elems;
     const uint64_t end = beg + d.tile_elems < d.n ? beg + d.tile_elems : (uint64_t)d.n;
-    const float acc = vec_range_sum(a.x + d.x_off, a.y + d.y_off, d.a, beg, end, ((d.x_off | d.y_off) & 3u) == 0);
-    const float bs = block_sum_f32(acc, s4f);
+    const float acc =
+        vec_range_sum<BLOCK>(a.x + d.x_off, a.y + d.y_off, d.a, beg, end, ((d.x_off | d.y_off) & 3u) == 0);
+    const float bs = block_sum_f32_w<BLOCK>(acc, s4f);
     if (threadIdx.x == 0) a.partials[t] = bs;
     __syncthreads();
   }
 }
+template __global__ void k_vec_batch_tiles<128>(VecBatchArgs);
+template __global__ void k_vec_batch_tiles<256>(VecBatchArgs);
+template __global__ void k_vec_batch_tiles<512>(VecBatchArgs);
+template __global__ void k_vec_batch_tiles<1024>(VecBatchArgs);
 
 // Job j = thread: its items' partials added in item order.  Block 0 also
 // rewinds the work counter for the slot's next batch and publishes the header.

@@ -150,6 +150,11 @@ struct JobEndArgs {
 __global__ void k_job_begin(JobBeginArgs a);
 __global__ void k_job_end(JobEndArgs a);
 
+// The library stage of a library-call template: rocPRIM's device-wide
+// inclusive scan of n int32 values into int64 sums, widening on load, on
+// stream st (lib_scan.hip).  With ws == nullptr only ws_bytes is computed.
+hipError_t lib_scan(void* ws, size_t& ws_bytes, const int32_t* in, int64_t* out, size_t n, hipStream_t st);
+
 // One explicit step of the thermal grid: tout = step(tin, p).  The first
 // step of a job (first != 0) also writes the job's scalars into the slot
 // header.
@@ -187,6 +192,8 @@ __device__ inline float vec_items_total(const float* partials, uint32_t first, u
   return s;
 }
 
+// BLOCK threads per block: 128, 256, 512 or 1024 (the template's block).
+template <int BLOCK>
 __global__ void k_vec_batch_tiles(VecBatchArgs a);
 __global__ void k_vec_batch_final(VecBatchFinalArgs a);
 __global__ void k_scan_reduce_i32(ScanReduceArgs a);

@@ -49,10 +49,14 @@ int pipeline_validate(const set_job_template& t, std::string* why) {
         return bad("vector batch template needs device x/y pools");
       if (t.batch_max < 1 || t.batch_max > (1u << 20)) return bad("vector batch template needs 1 <= batch_max <= 2^20");
       if (t.tiles_max < t.batch_max || t.tiles_max > (1u << 26)) return bad("vector batch needs batch_max <= tiles_max <= 2^26");
+      if (t.block != 0 && t.block != 128 && t.block != 256 && t.block != 512 && t.block != 1024)
+        return bad("vector batch block must be 0, 128, 256, 512 or 1024");
       break;
     default:
       return bad("unknown pipeline");
   }
+  if (t.block != 0 && t.pipeline != SET_PIPE_SAXPY_BATCH_F32)
+    return bad("only the vector batch template takes a block size (block must be 0)");
   if (t.flags & ~(uint32_t)(SET_TF_DEBUG | SET_TF_SCAN_LOW32 | SET_TF_CAPTURE)) return bad("unknown template flags");
   if (t.copy_mode != SET_COPY_KERNELS && t.copy_mode != SET_COPY_NODES && t.copy_mode != SET_COPY_ASYNC_IN)
     return bad("unknown copy mode");

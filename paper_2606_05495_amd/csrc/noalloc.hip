@@ -214,7 +214,7 @@ int run_noalloc(int device, hipStream_t stream, const float* x, const float* y, 
     hipLaunchKernelGGL(k_vec_noalloc_plan, dim3(1), dim3(kNaPlanThreads), 0, stream, pa);
     JobScalars js{};
     VecBatchArgs va{tab, x, y, partials, work, reinterpret_cast<DevSlotHdr*>(base + kNaHdrOff), js};
-    hipLaunchKernelGGL(k_vec_batch_tiles, dim3(grid ? grid : (unsigned)kVecBatchGrid), dim3(kBlock), 0, stream, va);
+    hipLaunchKernelGGL(k_vec_batch_tiles<kBlock>, dim3(grid ? grid : (unsigned)kVecBatchGrid), dim3(kBlock), 0, stream, va);
     NaTotalsArgs ta{tab, partials, results};
     hipLaunchKernelGGL(k_vec_noalloc_totals, dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, stream,
                        ta);

@@ -89,7 +89,7 @@ class Context:
 
     # ------------------------------------------------------------ templates
     def define(self, pipeline, width=0, height=0, max_n=0, flags=0, threshold=0.0, x_pool=None, y_pool=None,
-               borrow_arena=True, pool_ptrs=None, copy="kernels", batch_max=0, tiles_max=0, grid=0):
+               borrow_arena=True, pool_ptrs=None, copy="kernels", batch_max=0, tiles_max=0, grid=0, block=0):
         t = A.set_job_template()
         t.pipeline = PIPELINES[pipeline] if isinstance(pipeline, str) else int(pipeline)
         t.flags = flags
@@ -101,6 +101,7 @@ class Context:
         t.batch_max = batch_max
         t.tiles_max = tiles_max
         t.grid = grid
+        t.block = block
         if x_pool is not None:
             t.dev_x_pool = x_pool.data_ptr()
             t.dev_y_pool = y_pool.data_ptr()

@@ -368,11 +368,12 @@ def test_vector_exact_sums_misaligned(torch_gpu, ternary_pools, mode):
         assert got[i] == np.float32(exact), (mode, int(n), int(xo[i]) % 4, int(yo[i]) % 4, got[i], exact)
 
 
-@pytest.mark.parametrize("tile", [1024, 4096, 65536])
-def test_vector_batching_exact_sums_misaligned(torch_gpu, ternary_pools, tile):
+@pytest.mark.parametrize("tile,block", [(1024, 0), (4096, 0), (65536, 0), (4096, 128), (1024, 512), (65536, 1024)])
+def test_vector_batching_exact_sums_misaligned(torch_gpu, ternary_pools, tile, block):
     """Batched path (persistent kernel over a descriptor table): the same
-    exact sums for every window alignment and work-item size."""
-    _say("vector batching exact sums, tile", tile)
+    exact sums for every window alignment, work-item size and block size of
+    the work-item kernel."""
+    _say("vector batching exact sums, tile", tile, "block", block)
     x, y, xd, yd = ternary_pools
     ns = np.concatenate([EXACT_NS, EXACT_NS])
     xo, yo = _misaligned_windows(ns, len(x), 37)
@@ -384,7 +385,7 @@ def test_vector_batching_exact_sums_misaligned(torch_gpu, ternary_pools, tile):
     for b in range(64):
         tune.tile_elems[b] = tile
     ctx = Context(mode="set", workers=2, slots=4)
-    tid = ctx.define("saxpy_batch", max_n=1 << 22, x_pool=xd, y_pool=yd, batch_max=8, tiles_max=8192)
+    tid = ctx.define("saxpy_batch", max_n=1 << 22, x_pool=xd, y_pool=yd, batch_max=8, tiles_max=8192, block=block)
     res, _ = ctx.run_vector_jobs(tid, jobs, tuning=tune)
     ctx.close()
     for i, n in enumerate(ns):
@@ -582,6 +583,33 @@ def test_vector_batching_parity(torch_gpu, vec_pools, mode, copy):
     assert np.array_equal(res2, res[perm])
     st = ctx.stats()
     assert st.failed == 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("block", [128, 512, 1024])
+def test_vector_batching_block_sizes(torch_gpu, vec_pools, block):
+    """The work-item kernel at each block size: every job within the oracle's
+    tolerance, bit-identical when re-batched in another order (the block is
+    fixed per template), and a bad block size refused."""
+    _say("vector batching block", block)
+    x, y, xd, yd = vec_pools
+    js = synth.vec_jobs(6, 120, pool_len=len(x))
+    jobs = np.zeros(120, dtype=A.VEC_JOB_DTYPE)
+    for f in ("n", "a", "x_off", "y_off"):
+        jobs[f] = js[f]
+    jobs["y_off"][:4] += 3
+    ctx = Context(mode="set", workers=4, slots=4)
+    tid = ctx.define("saxpy_batch", max_n=1 << 22, x_pool=xd, y_pool=yd, batch_max=16, tiles_max=1024, block=block)
+    res, _ = ctx.run_vector_jobs(tid, jobs)
+    for i in range(120):
+        n, xo, yo = int(jobs["n"][i]), int(jobs["x_off"][i]), int(jobs["y_off"][i])
+        S, E = oracle.saxpy_tanh_sum(x[xo:xo + n], y[yo:yo + n], jobs["a"][i])
+        assert abs(float(res[i]) - S) <= oracle.vec_tolerance(S, E), (block, i, n, res[i], S)
+    perm = np.random.default_rng(3).permutation(120)
+    res2, _ = ctx.run_vector_jobs(tid, jobs[perm])
+    assert np.array_equal(res2.view(np.uint32), res[perm].view(np.uint32))
+    with pytest.raises(A.SetError):
+        ctx.define("saxpy_batch", max_n=1 << 22, x_pool=xd, y_pool=yd, batch_max=16, tiles_max=1024, block=96)
     ctx.close()
 
 

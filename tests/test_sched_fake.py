@@ -390,6 +390,24 @@ def test_thread_sanitizer_stress():
     assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
 
 
+def test_thread_sanitizer_hip_backend_on_stub_runtime():
+    """The HIP backend's own host code (backend_hip.hip compiled as C++) over a
+    host-only runtime stand-in (csrc/hipstub: streams as in-order threads, a
+    graph executable's parameters read when its nodes run and when it is
+    launched), with the scheduler core, under ThreadSanitizer: every
+    completion mechanism, up to 4 dispatcher threads, steals, DMA copies
+    issued at bind, captured templates defined while jobs run, the comparison
+    modes and vector batches.  No race report, every output header right, and
+    no executable updated while a launch of it was queued or running."""
+    from paper_2606_05495_amd import build
+    exe = build.build_tsan_hip()
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=600,
+                       env=dict(os.environ, TSAN_OPTIONS="halt_on_error=1"))
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
+    assert "0 executable updates overlapping" in r.stdout, r.stdout[-2000:]
+
+
 # ------------------------------------------------------------------ bucketed persistent batching (host planning)
 def _vec_job_array(ns, offs=0):
     jobs = np.zeros(len(ns), dtype=A.VEC_JOB_DTYPE)
@@ -553,3 +571,16 @@ def test_library_scan_template_rules():
         with pytest.raises(A.SetError) as e:
             ctx.define("scan_lib", max_n=1000)
         assert e.value.code == A.SET_EUNSUPPORTED
+
+
+def test_block_size_only_for_vector_batches():
+    """set_job_template.block: 128/256/512/1024 (or 0) for the vector batch
+    template, and 0 for every other pipeline."""
+    with _fake(workers=2, slots=2) as ctx:
+        for blk in (0, 128, 256, 512, 1024):
+            ctx.define("saxpy_batch", max_n=1 << 20, pool_ptrs=DUMMY_POOL, batch_max=4, tiles_max=64, block=blk)
+        for blk in (64, 100, 2048, -1):
+            with pytest.raises(A.SetError):
+                ctx.define("saxpy_batch", max_n=1 << 20, pool_ptrs=DUMMY_POOL, batch_max=4, tiles_max=64, block=blk)
+        with pytest.raises(A.SetError):
+            ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL, block=256)
