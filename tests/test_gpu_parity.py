@@ -1146,6 +1146,23 @@ def test_hotspot_workload(torch_gpu, mode):
         assert np.array_equal(o, outs[i % 5])
 
 
+@pytest.mark.parametrize("shape", [(256, 256), (97, 130)])
+def test_hotspot_32_steps_within_1e5_relative(torch_gpu, shape):
+    """The longest chain a template allows (32 steps) on seeded random grids,
+    held to the 1e-5 relative bar for float32 stages itself: max |T_gpu -
+    T_ref| <= 1e-5 max |T_ref|, tighter than the derived worst-case bound
+    (33 * 8 * 2^-24 = 1.6e-5 relative) at this length."""
+    _say("hotspot 32 steps, 1e-5 relative", shape)
+    h, w = shape
+    grids = [synth.hotspot_input(3, k, h, w) for k in range(4)]
+    outs = _run_hotspot("set", grids, 32)
+    for (t0, p), o in zip(grids, outs):
+        ref = oracle.hotspot(t0, p, 32)
+        err = float(np.max(np.abs(o.astype(np.float64) - ref)))
+        _say("hotspot 32 steps", shape, "max error relative to max|T|: %.3g" % (err / float(np.max(np.abs(ref)))))
+        assert err <= 1e-5 * float(np.max(np.abs(ref))), (shape, err)
+
+
 def test_hotspot_pins_on_gpu(torch_gpu):
     """Ambient grid without power stays exactly ambient; 32 steps (the most a template allows)."""
     h, w = 40, 72
