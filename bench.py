@@ -13,10 +13,11 @@ synchronous baseline and the queue model, on the same GPU, and through SET
 with each other completion mechanism; every result is checked against the CPU
 oracle after the timed regions.  Before it touches the GPU, the run traces
 short child runs of SET and batch-sync with rocprofv3 for the kernel gap and
-GPU-idle fraction.  The line also carries two more workloads, each verified:
+GPU-idle fraction.  The line also carries three more workloads, each verified:
 100,000 uneven vector jobs (bucketed persistent batches and per-job graphs
-against per-job baselines) and 20,000 copy-bound scan jobs (SET with and
-without stealing against batch-sync).
+against per-job baselines), 20,000 copy-bound scan jobs (SET with and
+without stealing against batch-sync) and the serving loop (open-loop arrivals
+at 2k, 10k and 40k requests/s, p50/p99 latency).
 
 Prints ONE JSON line.
 """
@@ -298,6 +299,22 @@ def vectors_summary(out):
     return r
 
 
+_VEC_POOLS = {}
+
+
+def vector_pools(torch):
+    """The two 2^27-element device pools of the vector jobs (host copies kept
+    for the oracle), generated once per process."""
+    from paper_2606_05495_amd import synth
+    if "p" not in _VEC_POOLS:
+        L = synth.VEC_POOL_LEN
+        log("generating vector pools (2 x %d floats)" % L)
+        x = synth.vec_pool(0, "x", L)
+        y = synth.vec_pool(0, "y", L)
+        _VEC_POOLS["p"] = (x, y, torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda())
+    return _VEC_POOLS["p"]
+
+
 def vectors_section(args, torch, modes=("set", "batch", "sync", "queue")):
     """Runs the uneven vector workload; returns {persistent, per_job_<mode>}."""
     from paper_2606_05495_amd import _abi as A
@@ -305,11 +322,7 @@ def vectors_section(args, torch, modes=("set", "batch", "sync", "queue")):
     from paper_2606_05495_amd.runtime import Context, pinned
     import oracle
     L = synth.VEC_POOL_LEN
-    log("generating vector pools (2 x %d floats)" % L)
-    x = synth.vec_pool(0, "x", L)
-    y = synth.vec_pool(0, "y", L)
-    xd = torch.from_numpy(x).cuda()
-    yd = torch.from_numpy(y).cuda()
+    x, y, xd, yd = vector_pools(torch)
     J = args.vjobs
     js = synth.vec_jobs(0, J, pool_len=L)
     vj = np.zeros(J, dtype=A.VEC_JOB_DTYPE)
@@ -691,6 +704,18 @@ def bench_serve(args, torch):
     image jobs (Gaussian/Sobel at 256^2, 512^2, 1024^2, 2048^2, uniform) and
     half vector jobs (as the uneven vector family), under an 8 GB
     device-memory admission cap.  Latency = arrival -> result in host memory."""
+    results = serve_section(args, torch)
+    line = {"metric": METRIC, "workload": "serving: Poisson arrivals, 50%% images {256,512,1024,2048}^2 + 50%% "
+            "vector jobs, %.0f GB admission cap, %.0f s window" % (args.mem_budget / 1e9, args.serve_seconds),
+            "value": results[0]["throughput_jobs_per_s"], "unit": "jobs/s", "n_gpus": 1, "dtype": "f32",
+            "data": "synthetic", "higher_is_better": True, "vs_baseline": None, "rates": results,
+            "config": {"workers": args.workers, "slots": args.slots, "copy": args.copy, "callback": args.callback,
+                       "dispatchers": args.dispatchers, "image_pool_per_size": args.serve_pool}}
+    print(json.dumps(line), flush=True)
+
+
+def serve_section(args, torch):
+    """Runs the serving workload at each of args.rates; returns one record per rate."""
     from paper_2606_05495_amd import _abi as A
     from paper_2606_05495_amd import autotune, synth
     from paper_2606_05495_amd.runtime import Context, pinned
@@ -707,9 +732,7 @@ def bench_serve(args, torch):
     for s_ in sides:
         nin[offs[s_]:offs[s_] + P * 4 * s_ * s_].view(np.float32)[:] = imgs[s_].ravel()
     L = synth.VEC_POOL_LEN
-    xh, yh = synth.vec_pool(0, "x", L), synth.vec_pool(0, "y", L)
-    xd = torch.from_numpy(xh).cuda()
-    yd = torch.from_numpy(yh).cuda()
+    xh, yh, xd, yd = vector_pools(torch)
     img_refs = {}
 
     def check_sample(req, isimg, side, mix, done, vres, nout, rate, count=200):
@@ -787,13 +810,7 @@ def bench_serve(args, torch):
         log(json.dumps(res))
         results.append(res)
         ctx.close()
-    line = {"metric": METRIC, "workload": "serving: Poisson arrivals, 50%% images {256,512,1024,2048}^2 + 50%% "
-            "vector jobs, %.0f GB admission cap, %.0f s window" % (args.mem_budget / 1e9, args.serve_seconds),
-            "value": results[0]["throughput_jobs_per_s"], "unit": "jobs/s", "n_gpus": 1, "dtype": "f32",
-            "data": "synthetic", "higher_is_better": True, "vs_baseline": None, "rates": results,
-            "config": {"workers": args.workers, "slots": args.slots, "copy": args.copy, "callback": args.callback, "dispatchers": args.dispatchers,
-                       "image_pool_per_size": P}}
-    print(json.dumps(line), flush=True)
+    return results
 
 
 def main():
@@ -838,6 +855,8 @@ def main():
     ap.add_argument("--rates", default="2000,10000,40000")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-pool", type=int, default=16)
+    ap.add_argument("--section-serve-seconds", type=float, default=3.0,
+                    help="image workload: window of each rate in the serving section of the default line")
     ap.add_argument("--mem-budget", type=float, default=8e9)
     ap.add_argument("--vjobs", type=int, default=100000)
     ap.add_argument("--vsample", type=int, default=400)
@@ -1132,6 +1151,15 @@ def main_with(args, raw):
             "%d jobs: 8 MiB int32 H2D -> inclusive int64 scan -> 16 MiB D2H, 8 workers" % sa.scan_jobs),
             config={"copy": sa.copy, "callback": sa.callback, "dispatchers": sa.dispatchers,
                     "inflight_per_worker": sa.inflight})
+        torch.cuda.empty_cache()
+        ga = section_args(raw, "serve", serve_seconds=args.section_serve_seconds, serve_pool=4)
+        log("serving: %s requests/s, %.0f s windows" % (ga.rates, ga.serve_seconds))
+        sres = serve_section(ga, torch)
+        sections["serving"] = {"rates": sres, "verified": all(r["verified"] for r in sres), "workload": (
+            "open-loop Poisson arrivals, 50%% images {256,512,1024,2048}^2 + 50%% vector jobs, %.0f GB admission cap, "
+            "%.0f s window per rate" % (ga.mem_budget / 1e9, ga.serve_seconds)),
+            "config": {"workers": ga.workers, "slots": ga.slots, "copy": ga.copy, "callback": ga.callback,
+                       "dispatchers": ga.dispatchers, "image_pool_per_size": ga.serve_pool}}
 
     log("link probe")
     link_peak = link_probe(torch)
