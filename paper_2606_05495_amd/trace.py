@@ -432,8 +432,38 @@ def summarize(dirpath: str, kernel: str = "", batch: int = 0, library_window: bo
     return out
 
 
+def traffic_file(out_path: str, runs: dict, calib_bytes: int = 64 << 20) -> dict:
+    """Write the counter-traffic record the benchmark reads: runs maps a
+    workload name to (fetch_dir, write_dir, probe_json) of a stage_probe
+    --cold-only pair of counter runs; the skip count (the batch's dispatches
+    and the cold loop's warm-up launches) comes from the probe's slot count."""
+    import hashlib
+    kernels_src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "kernels.hip")
+    rec = {"kernels_sha256": hashlib.sha256(open(kernels_src, "rb").read()).hexdigest(), "unit": "bytes per launch",
+           "method": "rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE (KiB per dispatch), each scaled by the "
+                     "factor that makes the counter read 64 MiB for the run's last plain 64 MiB device copy "
+                     "(__amd_rocclr_copyBuffer); mean over the cold-loop dispatches of stage_probe --cold-only "
+                     "(after the batch's dispatches and the loop's warm-up launches)",
+           "workloads": {}}
+    for name, (fdir, wdir, probe) in runs.items():
+        line = [l for l in open(probe) if l.startswith("{")][-1]
+        slots = json.loads(line)["slots"]
+        r = traffic_record(fdir, wdir, {"gauss5_f32": "k_gauss5", "sobel_thresh_f32": "k_sobel_thresh",
+                                        "sobel_final": "k_sobel_final"}, skip=slots + min(slots, 64),
+                           calib_bytes=calib_bytes)
+        r["slots"] = slots
+        rec["workloads"][name] = r
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
 if __name__ == "__main__":
-    if len(sys.argv) > 1 and sys.argv[1] == "timeline":
+    if len(sys.argv) > 1 and sys.argv[1] == "traffic":
+        # python -m ...trace traffic OUT.json NAME=FETCH_DIR,WRITE_DIR,PROBE_JSON ...
+        runs = {a.split("=", 1)[0]: tuple(a.split("=", 1)[1].split(",")) for a in sys.argv[3:]}
+        print(json.dumps(traffic_file(sys.argv[2], runs), indent=1))
+    elif len(sys.argv) > 1 and sys.argv[1] == "timeline":
         # python -m ...trace timeline OUT.json "COMMAND" mode=summary.json ...
         rec = timeline_record(dict(a.split("=", 1) for a in sys.argv[4:]), sys.argv[3])
         with open(sys.argv[2], "w") as fh:

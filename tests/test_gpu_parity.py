@@ -613,6 +613,29 @@ def test_vector_batching_block_sizes(torch_gpu, vec_pools, block):
     ctx.close()
 
 
+@pytest.mark.parametrize("mode", ["set", "sync", "batch", "queue"])
+def test_empty_inputs_on_gpu(torch_gpu, vec_pools, mode):
+    """Empty submissions and empty vector batches launch nothing and count
+    nothing on the HIP backend; the context then runs real jobs normally."""
+    _say("empty inputs", mode)
+    x, y, xd, yd = vec_pools
+    ctx = Context(mode=mode, workers=2, slots=2)
+    tid = ctx.define("saxpy_tanh_sum", max_n=1 << 16, x_pool=xd, y_pool=yd)
+    tb = ctx.define("saxpy_batch", max_n=1 << 16, x_pool=xd, y_pool=yd, batch_max=4, tiles_max=64)
+    ctx.submit_many(tid, ctx.job_array(0))
+    ctx.drain(timeout_ns=int(5e9))
+    res, nb = ctx.run_vector_jobs(tb, np.zeros(0, dtype=A.VEC_JOB_DTYPE))
+    assert nb == 0 and res.size == 0
+    assert ctx.stats().submitted == 0
+    tout, nout = pinned(128)
+    ctx.submit(tid, host_out=tout.data_ptr(), out_bytes=68, n=77, a=1.5, x_off=64, y_off=128)
+    ctx.drain()
+    S, E = oracle.saxpy_tanh_sum(x[64:64 + 77], y[128:128 + 77], 1.5)
+    assert abs(float(nout[64:68].view(np.float32)[0]) - S) <= oracle.vec_tolerance(S, E)
+    ctx.close()
+    A.set_run_vector_jobs_noalloc(0, 0, xd.data_ptr(), yd.data_ptr(), len(x), 1 << 16, 0, 0, 0)  # count 0: nothing
+
+
 def test_vector_batching_pins(torch_gpu):
     """Saturated tanh gives S = n exactly through the batched path too."""
     _say("vector batching pins")

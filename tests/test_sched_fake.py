@@ -584,3 +584,21 @@ def test_block_size_only_for_vector_batches():
                 ctx.define("saxpy_batch", max_n=1 << 20, pool_ptrs=DUMMY_POOL, batch_max=4, tiles_max=64, block=blk)
         with pytest.raises(A.SetError):
             ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL, block=256)
+
+
+def test_empty_inputs():
+    """Empty submissions and empty vector batches are no-ops: nothing is
+    counted, drain returns at once, and the context stays usable."""
+    with _fake(workers=2, slots=2) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        tb = ctx.define("saxpy_batch", max_n=1 << 20, pool_ptrs=DUMMY_POOL, batch_max=4, tiles_max=64)
+        ctx.submit_many(tid, ctx.job_array(0))
+        ctx.drain(timeout_ns=int(1e9))
+        res, nb = ctx.run_vector_jobs(tb, np.zeros(0, dtype=A.VEC_JOB_DTYPE))
+        assert nb == 0 and res.size == 0
+        st = ctx.stats()
+        assert st.submitted == 0 and st.completed == 0
+        arr, outs = _vec_jobs(ctx, tid, 3, 10)
+        assert ctx.submit_many(tid, arr) == 0
+        ctx.drain()
+        assert ctx.stats().completed == 3
