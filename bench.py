@@ -197,22 +197,6 @@ def traffic_for(kernel_name, workload="gauss_sobel_1024"):
         return None
 
 
-def timeline_from_profile():
-    """Kernel-gap and idle figures per mode from the committed rocprofv3
-    kernel-trace summaries, if they were taken on the current native sources."""
-    path = os.path.join(ROOT, "profiles", "timeline.json")
-    if not os.path.exists(path):
-        return None
-    try:
-        from paper_2606_05495_amd.trace import csrc_digest
-        rec = json.load(open(path))
-        if rec.get("csrc_sha256") != csrc_digest():
-            return None
-        return {"source": "profiles/timeline.json", "command": rec.get("command"), "modes": rec["modes"]}
-    except Exception:
-        return None
-
-
 def copy_reference(torch, nbytes, reps, span=1 << 30):
     """A plain device-to-device copy moving the same bytes (half read, half
     written), rotating over `span` bytes of sources and destinations so that,
