@@ -13,7 +13,8 @@ synchronous baseline and the queue model, on the same GPU, and through SET
 with each other completion mechanism; every result is checked against the CPU
 oracle after the timed regions.  Before it touches the GPU, the run traces
 short child runs of SET and batch-sync with rocprofv3 for the kernel gap and
-GPU-idle fraction.  The line also carries three more workloads, each verified:
+GPU-idle fraction.  The line also carries four more workloads, each verified:
+64 box/histogram jobs (the plain synchronous method against SET, bit-exact),
 100,000 uneven vector jobs (bucketed persistent batches and per-job graphs
 against per-job baselines), 20,000 copy-bound scan jobs (SET with and
 without stealing against batch-sync) and the serving loop (open-loop arrivals
@@ -125,6 +126,23 @@ def cpu_baseline(pool_imgs, passes):
             "sample": "%d jobs = %d passes over the 61 pool images (1024x1024 Gaussian->Sobel->threshold->count/sum, "
                       "float64 C oracle), thread pool of %d" % (len(work), passes, ncores),
             "single_thread_jobs_per_s": round(len(single) / dt1, 2), "cpu_model": cpu_model()}
+
+
+def oracle_pool_rate(fn, items, label):
+    """The oracle over `items` on every host core (thread pool of C calls that
+    release the interpreter lock), and on one thread over a fifth of them."""
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    t0 = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=ncores) as ex:
+        list(ex.map(fn, items))
+    dt = time.perf_counter() - t0
+    few = items[:max(1, len(items) // 5)]
+    t1 = time.perf_counter()
+    for it in few:
+        fn(it)
+    dt1 = time.perf_counter() - t1
+    return {"value": round(len(items) / dt, 2), "unit": "jobs/s", "cores": ncores, "kind": "oracle", "sample": label,
+            "single_thread_jobs_per_s": round(len(few) / dt1, 2)}
 
 
 def cpu_model():
@@ -261,6 +279,58 @@ def bench_vectors(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def box_section(args, torch, reps=20):
+    """The 64-job box/histogram workload: 256x256 uint8 images (seeded by job
+    id) -> 3x3 zero-padded box sum -> floor(/9) -> 256-bin histogram, as the
+    plain method runs it (synchronous launches, stream = job mod 4) and through
+    SET (4 workers x 4 slots, 4 dispatcher threads); `reps` timed passes of the
+    64 jobs each, every histogram of every pass bit-exact against the oracle."""
+    from paper_2606_05495_amd import synth
+    from paper_2606_05495_amd.runtime import Context, pinned
+    import oracle
+    J = 64
+    imgs = [synth.box_image(0, j) for j in range(J)]
+    refs = [oracle.box_hist(im)[2] for im in imgs]
+    tin, nin = pinned(J * 65536)
+    nin[:] = np.concatenate([im.ravel() for im in imgs])
+    out = {}
+    # SET as for the other short-job workloads: completion words, four
+    # dispatcher threads (a job's graph launch costs ~14 us of host time)
+    for mode, slots, cb, nd in (("sync", 1, "event_poll", 1), ("set", 4, "host_flag", 4)):
+        ctx = Context(mode=mode, workers=4, slots=slots, callback=cb, dispatchers=nd)
+        tid = ctx.define("box_hist", width=256, height=256, copy="kernels")
+        ob = ctx.out_bytes(tid)
+        tout, nout = pinned(J * 1152)
+        arr = ctx.job_array(J)
+        j = np.arange(J, dtype=np.uint64)
+        arr["host_in"] = tin.data_ptr() + j * np.uint64(65536)
+        arr["in_bytes"] = 65536
+        arr["host_out"] = tout.data_ptr() + j * np.uint64(1152)
+        arr["out_bytes"] = ob
+        ctx.submit_many(tid, arr)
+        ctx.drain()
+        ok, each = True, []
+        for _ in range(reps):
+            nout[:] = 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.submit_many(tid, arr)
+            ctx.drain()
+            torch.cuda.synchronize()
+            each.append(time.perf_counter() - t0)
+            o = nout.reshape(J, 1152)
+            ok &= all(np.array_equal(o[k, 64:64 + 1024].view(np.uint32), refs[k]) for k in range(J))
+        ctx.close()
+        dt = float(np.median(each))
+        out[mode] = {"jobs_per_s": round(J / dt, 1), "passes": reps, "verified_bit_exact": bool(ok),
+                     "jobs_per_s_min": round(J / max(each), 1), "jobs_per_s_max": round(J / min(each), 1)}
+    out["set_speedup_vs_sync"] = round(out["set"]["jobs_per_s"] / out["sync"]["jobs_per_s"], 3)
+    if not args.no_cpu:
+        out["cpu_oracle"] = oracle_pool_rate(oracle.box_hist, imgs, "all 64 jobs (C oracle)")
+    out["verified"] = out["sync"]["verified_bit_exact"] and out["set"]["verified_bit_exact"]
+    return out
+
+
 def vectors_summary(out):
     """Speedups of the persistent batches and of per-job SET over the per-job baselines."""
     p = out["persistent"]["jobs_per_s"]
@@ -280,6 +350,9 @@ def vectors_summary(out):
     if "per_job_set" in out:
         r["speedup_vs_per_job_set"] = round(p / out["per_job_set"]["jobs_per_s"], 3)
     r["verified"] = all(v.get("verified", True) for v in out.values() if isinstance(v, dict))
+    if "cpu_oracle" in out:
+        r["cpu_oracle_jobs_per_s"] = out["cpu_oracle"]["value"]
+        r["persistent_over_cpu_oracle"] = round(p / out["cpu_oracle"]["value"], 1)
     return r
 
 
@@ -351,6 +424,12 @@ def vectors_section(args, torch, modes=("set", "batch", "sync", "queue")):
         out["per_job_" + mode] = {"jobs_per_s": round(J / dt2, 1), "verified": check(r2)}
         log("vectors per-job %s: %.0f jobs/s" % (mode, J / dt2))
         c.close()
+    if not args.only and not args.no_cpu:
+        K = min(J, 1000)
+        items = [(x[js["x_off"][i]:js["x_off"][i] + js["n"][i]], y[js["y_off"][i]:js["y_off"][i] + js["n"][i]],
+                  float(js["a"][i])) for i in range(K)]
+        out["cpu_oracle"] = oracle_pool_rate(lambda t: oracle.saxpy_tanh_sum(*t), items,
+                                             "the first %d jobs of the workload (float64 C oracle)" % K)
     return out
 
 
@@ -397,8 +476,9 @@ def scan_summary(runs):
     return out
 
 
-def scan_section(args, torch, configs):
-    """Runs (mode, workers, stealing, copy) configurations of the scan workload; returns one record each."""
+def scan_section(args, torch, configs, cpu_out=None):
+    """Runs (mode, workers, stealing, copy) configurations of the scan workload; returns one record each.
+    With cpu_out (a dict), the oracle's rate over the pool's inputs is stored there."""
     from paper_2606_05495_amd import synth
     from paper_2606_05495_amd.runtime import Context, pinned
     import oracle
@@ -456,6 +536,9 @@ def scan_section(args, torch, configs):
                      "stolen": int(st.stolen), "verified": ok})
         log(json.dumps(runs[-1]))
         ctx.close()
+    if cpu_out is not None and not args.no_cpu:
+        cpu_out.update(oracle_pool_rate(oracle.scan, [pool[k] for k in range(P)],
+                                        "the %d pool inputs (2^21 int32 each, C oracle)" % P))
     return runs
 
 
@@ -1119,6 +1202,10 @@ def main_with(args, raw):
 
     sections = {}
     if not args.no_sections:
+        log("box/histogram jobs: 64")
+        sections["box_hist_64"] = dict(box_section(args, torch), workload=(
+            "64 jobs: 256x256 uint8 -> 3x3 box sum (zero-padded) -> floor(/9) -> 256-bin histogram, bit-exact; "
+            "the plain method (sync launches, 4 streams) and SET (4 workers x 4 slots)"))
         va = section_args(raw, "vectors")
         log("uneven vector jobs: %d" % va.vjobs)
         vout = vectors_section(va, torch)
@@ -1129,9 +1216,17 @@ def main_with(args, raw):
         torch.cuda.empty_cache()
         sa = section_args(raw, "scan")
         log("scan jobs: %d" % sa.scan_jobs)
+        scpu = {}
         sruns = scan_section(sa, torch, [("set", 8, True, sa.copy), ("set", 8, False, sa.copy),
-                                         ("batch", 8, False, "kernels"), ("batch", 8, False, "async_in")])
-        sections["scan_jobs"] = dict(scan_summary(sruns), runs=sruns, workload=(
+                                         ("batch", 8, False, "kernels"), ("batch", 8, False, "async_in")], scpu)
+        sbest = max(r["jobs_per_s"] for r in sruns if r["mode"] == "set")
+        sections["scan_jobs"] = dict(scan_summary(sruns), runs=sruns, cpu_oracle=scpu or None,
+                                     pipeline_roofline={
+                                         "bound": "host link, both directions",
+                                         "achieved_GBps": round(sbest * (4 + 8) * (1 << 21) / 1e9, 2),
+                                         "note": "8 MiB in + 16 MiB out per job; the link probe of this run gives "
+                                                 "the host-to-device direction alone"},
+                                     workload=(
             "%d jobs: 8 MiB int32 H2D -> inclusive int64 scan -> 16 MiB D2H, 8 workers" % sa.scan_jobs),
             config={"copy": sa.copy, "callback": sa.callback, "dispatchers": sa.dispatchers,
                     "inflight_per_worker": sa.inflight})
