@@ -11,6 +11,8 @@
 // microseconds when a thousand blocks issue them).  That last kernel combines
 // the per-block partials in block order, checks the slot's canaries and
 // publishes the output header.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace setrt {
@@ -485,36 +487,49 @@ __global__ __launch_bounds__(kBlock) void k_sobel_thresh_win_f32(SobelArgs a) {
   const float thr = a.thr;
   float sum = 0.f;
   uint32_t cnt = 0;
+  // GUARD: test each row against the image (the last row of blocks, and
+  // lanes past a ragged right edge).  Full-width waves whose rows all lie
+  // inside take the unguarded copy: their results are used unconditionally,
+  // so the compiler keeps every load above this point (one memory round trip)
+  // instead of sinking part of a row's load into the row's branch.  Both
+  // copies accumulate in the same order.
+  auto rows = [&](auto guard) {
+    constexpr bool GUARD = decltype(guard)::value;
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int y = L.y0 + r;
-    float vs[4], vd[4];  // vertical smoothing (above + 2*centre + below) and difference (below - above)
+    for (int r = 0; r < R; ++r) {
+      const int y = L.y0 + r;
+      float vs[4], vd[4];  // vertical smoothing (above + 2*centre + below) and difference (below - above)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float t0 = (&v[r].x)[j], t1 = (&v[r + 1].x)[j], t2 = (&v[r + 2].x)[j];
-      vs[j] = (t0 + 2.f * t1) + t2;
-      vd[j] = t2 - t0;
-    }
-    const float es = (e[r] + 2.f * e[r + 1]) + e[r + 2], ed = e[r + 2] - e[r];
-    const float cs[6] = {from_left(vs[3], es), vs[0], vs[1], vs[2], vs[3], from_right(vs[0], es)};
-    const float cd[6] = {from_left(vd[3], ed), vd[0], vd[1], vd[2], vd[3], from_right(vd[0], ed)};
-    uint32_t packed = 0;
-    float rsum;
+      for (int j = 0; j < 4; ++j) {
+        const float t0 = (&v[r].x)[j], t1 = (&v[r + 1].x)[j], t2 = (&v[r + 2].x)[j];
+        vs[j] = (t0 + 2.f * t1) + t2;
+        vd[j] = t2 - t0;
+      }
+      const float es = (e[r] + 2.f * e[r + 1]) + e[r + 2], ed = e[r + 2] - e[r];
+      const float cs[6] = {from_left(vs[3], es), vs[0], vs[1], vs[2], vs[3], from_right(vs[0], es)};
+      const float cd[6] = {from_left(vd[3], ed), vd[0], vd[1], vd[2], vd[3], from_right(vd[0], ed)};
+      uint32_t packed = 0;
+      float rsum;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float gx = cs[j + 2] - cs[j];
-      const float gy = (cd[j] + 2.f * cd[j + 1]) + cd[j + 2];
-      const float mag = sqrt_hw(gx * gx + gy * gy);
-      packed |= (mag > thr ? 1u : 0u) << (8 * j);
-      rsum = (j == 0) ? mag : rsum + mag;
+      for (int j = 0; j < 4; ++j) {
+        const float gx = cs[j + 2] - cs[j];
+        const float gy = (cd[j] + 2.f * cd[j + 1]) + cd[j + 2];
+        const float mag = sqrt_hw(gx * gx + gy * gy);
+        packed |= (mag > thr ? 1u : 0u) << (8 * j);
+        rsum = (j == 0) ? mag : rsum + mag;
+      }
+      if (!GUARD || (y < h && !L.past)) {
+        uint8_t* mrow = a.mask + (size_t)y * w;  // wave-uniform row base
+        *reinterpret_cast<uint32_t*>(mrow + L.x) = packed;
+        cnt += __builtin_popcount(packed);
+        sum += rsum;
+      }
     }
-    if (y < h && !L.past) {
-      uint8_t* mrow = a.mask + (size_t)y * w;  // wave-uniform row base
-      *reinterpret_cast<uint32_t*>(mrow + L.x) = packed;
-      cnt += __builtin_popcount(packed);
-      sum += rsum;
-    }
-  }
+  };
+  if (FULL && L.y0 + R <= h)
+    rows(std::false_type{});
+  else
+    rows(std::true_type{});
   const float ws = wave_total_f32(sum);
   const uint32_t wc = wave_total_u32(cnt);
   if (L.lane == 0) {
@@ -563,20 +578,29 @@ __global__ __launch_bounds__(kBlock) void k_hotspot_win_f32(HotspotArgs a) {
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) pv[r] = L.load4(a.p + (size_t)clampi(L.y0 + r, 0, hm) * w);
+  // Full-width waves whose rows all lie inside store unguarded, which keeps
+  // every load (P's rows included) above this point: one memory round trip.
+  auto rows = [&](auto guard) {
+    constexpr bool GUARD = decltype(guard)::value;
 #pragma unroll
-  for (int r = 1; r <= R; ++r) {
-    const int y = L.y0 + r - 1;
-    const float c[6] = {from_left(v[r].w, e[r]), v[r].x, v[r].y, v[r].z, v[r].w, from_right(v[r].x, e[r])};
-    const float n4[4] = {v[r - 1].x, v[r - 1].y, v[r - 1].z, v[r - 1].w};
-    const float s4[4] = {v[r + 1].x, v[r + 1].y, v[r + 1].z, v[r + 1].w};
-    const float p4[4] = {pv[r - 1].x, pv[r - 1].y, pv[r - 1].z, pv[r - 1].w};
-    float o[4];
+    for (int r = 1; r <= R; ++r) {
+      const int y = L.y0 + r - 1;
+      const float c[6] = {from_left(v[r].w, e[r]), v[r].x, v[r].y, v[r].z, v[r].w, from_right(v[r].x, e[r])};
+      const float n4[4] = {v[r - 1].x, v[r - 1].y, v[r - 1].z, v[r - 1].w};
+      const float s4[4] = {v[r + 1].x, v[r + 1].y, v[r + 1].z, v[r + 1].w};
+      const float p4[4] = {pv[r - 1].x, pv[r - 1].y, pv[r - 1].z, pv[r - 1].w};
+      float o[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) o[j] = hotspot::step(c[j + 1], p4[j], n4[j], s4[j], c[j], c[j + 2]);
-    if (y < h && !L.past)
-      *reinterpret_cast<float4*>(reinterpret_cast<char*>(a.tout + (size_t)y * w) + L.x * 4u) =
-          make_float4(o[0], o[1], o[2], o[3]);
-  }
+      for (int j = 0; j < 4; ++j) o[j] = hotspot::step(c[j + 1], p4[j], n4[j], s4[j], c[j], c[j + 2]);
+      if (!GUARD || (y < h && !L.past))
+        *reinterpret_cast<float4*>(reinterpret_cast<char*>(a.tout + (size_t)y * w) + L.x * 4u) =
+            make_float4(o[0], o[1], o[2], o[3]);
+    }
+  };
+  if (FULL && L.y0 + R <= h)
+    rows(std::false_type{});
+  else
+    rows(std::true_type{});
 }
 template __global__ void k_hotspot_win_f32<true>(HotspotArgs a);
 template __global__ void k_hotspot_win_f32<false>(HotspotArgs a);
@@ -908,12 +932,27 @@ __global__ __launch_bounds__(kBlock) void k_scan_down_i32_i64(ScanDownArgs a) {
   constexpr int kPitch = kScanItems + 2;  // LDS row of a thread (padding spreads the banks, keeps 16-byte alignment)
   __shared__ int64_t s_wave[4];
   __shared__ __align__(16) int64_t s_out[kBlock * kPitch];
-  const uint64_t n = a.hdr->n;
+  const uint64_t n = a.n;
   const unsigned t = blockIdx.x;
   if ((uint64_t)t * kScanTile >= n) return;
-  const int64_t tile_off = a.tile_excl[t];  // issued before the block barriers, not after them
-  int64_t v[kScanItems];
-  scan_load(a.in, n, t, threadIdx.x, v);
+  // The thread's 8 values as two 16-byte loads with no branch around them,
+  // then the tile's prefix, held at this point by the empty asm statement
+  // (the compiler would otherwise load it after the block scan, or after
+  // waiting for the data behind a branch: a second memory round trip).  So
+  // one memory latency covers both.  A thread past the end reads the last
+  // 8-value group instead and zeroes what lies beyond n: the slot's input
+  // region is padded to 256 bytes, so a 32-byte group that starts below n
+  // lies inside it.
+  const uint64_t base = (uint64_t)t * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+  const uint64_t last = (n - 1) & ~(uint64_t)(kScanItems - 1);
+  const uint64_t ld = base < last ? base : last;
+  const int4 q0 = *reinterpret_cast<const int4*>(a.in + ld);
+  const int4 q1 = *reinterpret_cast<const int4*>(a.in + ld + 4);
+  const int64_t tile_off = a.tile_excl[t];
+  asm volatile("" ::"s"(tile_off) : "memory");
+  int64_t v[kScanItems] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? v[k] : 0;
 #pragma unroll
   for (int k = 1; k < kScanItems; ++k) v[k] += v[k - 1];
   int64_t total;

@@ -97,8 +97,9 @@ struct VecBatchFinalArgs {
   SlotConst sc;
 };
 // Scan as reduce -> spine -> downsweep; all three are launched with the grid
-// of the template's largest n and read the job's n from the slot header, so a
-// job of any length needs no grid update.
+// of the template's largest n, so a job of any length needs no grid update.
+// The reduce and the downsweep take the job's n in their argument blocks; the
+// one-block spine reads it from the slot header.
 struct ScanReduceArgs {
   const int32_t* in;
   int64_t* tile_sum;   // [tiles]
@@ -111,12 +112,15 @@ struct ScanSpineArgs {
   int64_t* tile_excl;  // [tiles] exclusive prefix of tile sums
   SlotConst sc;
 };
+// The downsweep carries the job's n in its own argument block (rebound with
+// the first kernel's), so its data loads need no dependent load of the slot
+// header first: one memory round trip instead of two.
 struct ScanDownArgs {
   const int32_t* in;
   const int64_t* tile_excl;
   void* out;           // int64[n], or uint32[n] low words
   int low32;
-  const DevSlotHdr* hdr;
+  uint64_t n;          // the job's length
 };
 
 // Host<->device copy as a kernel: a small grid of 16-byte loads/stores that
