@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SET_ABI_VERSION 2u
+#define SET_ABI_VERSION 3u
 
 /* ---------------------------------------------------------------- status codes */
 enum set_status {
@@ -204,6 +204,11 @@ enum set_copy_mode {
 #define SET_TF_SCAN_LOW32 0x2u  /* scan: copy back only the low 32 bits of each sum */
 #define SET_TF_CAPTURE 0x4u     /* build each slot's graph by stream capture of the job's launch sequence
                                    (Section 4.1's capture path) instead of explicit node construction */
+#define SET_TF_POISON 0x8u      /* memory-safety stress of Section 4.1's rule that no job writes into a slot
+                                   another job still uses: every job's graph ends, after its output copy, with
+                                   a kernel that fills the slot's device buffers (header and canaries excepted)
+                                   with 0xFF bytes, so a job that read what the slot's previous job left there
+                                   would read NaN / all-ones values instead of plausible data */
 
 /* submit flags */
 #define SET_NONBLOCK 0x1  /* return SET_EAGAIN instead of waiting for staging room */
@@ -269,6 +274,11 @@ typedef struct set_job_template {
     int32_t grid;                /* tuning: grid cap for streaming kernels (0 = default) */
     uint32_t batch_max;          /* SAXPY batch: most jobs per batch (descriptor table capacity) */
     uint32_t tiles_max;          /* SAXPY batch: most (job, tile) work items per batch */
+    uint32_t stress_delay_us;    /* memory-safety stress: > 0 puts a one-wave kernel that waits about this many
+                                  * microseconds (device clock) before the first stage of every job, widening
+                                  * the window in which a slot released before its job ended would be
+                                  * overwritten by the next job's input copy; 0..100000, 0 = none */
+    uint32_t reserved;           /* must be 0 */
 } set_job_template;
 
 typedef struct set_job_args {

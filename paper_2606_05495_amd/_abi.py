@@ -20,7 +20,7 @@ except Exception:  # pragma: no cover - torch is part of the image
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libset.so")
 
-SET_ABI_VERSION = 2
+SET_ABI_VERSION = 3
 
 # status codes
 SET_OK, SET_EINVAL, SET_ENOMEM, SET_EDEVICE, SET_EAGAIN, SET_ETIMEOUT, SET_ECLOSED, SET_EUNSUPPORTED = (
@@ -35,7 +35,7 @@ SET_PIPE_BOX_HIST_U8, SET_PIPE_GAUSS_SOBEL_F32, SET_PIPE_SAXPY_TANH_SUM_F32, SET
 SET_PIPE_SAXPY_BATCH_F32 = 4
 SET_PIPE_SCAN_LIB_I32_I64 = 5
 SET_PIPE_HOTSPOT_F32 = 6
-SET_TF_DEBUG, SET_TF_SCAN_LOW32, SET_TF_CAPTURE = 0x1, 0x2, 0x4
+SET_TF_DEBUG, SET_TF_SCAN_LOW32, SET_TF_CAPTURE, SET_TF_POISON = 0x1, 0x2, 0x4, 0x8
 SET_COPY_KERNELS, SET_COPY_NODES, SET_COPY_ASYNC_IN = 0, 1, 2
 COPY_MODES = {"nodes": SET_COPY_NODES, "kernels": SET_COPY_KERNELS, "async_in": SET_COPY_ASYNC_IN}
 SET_NONBLOCK = 0x1
@@ -92,6 +92,8 @@ class set_job_template(ctypes.Structure):
         ("grid", ctypes.c_int32),
         ("batch_max", ctypes.c_uint32),
         ("tiles_max", ctypes.c_uint32),
+        ("stress_delay_us", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 

@@ -149,9 +149,11 @@ class FakeBackend : public Backend {
     std::thread th;
   };
 
+  // A job's simulated run time, plus the template's stress delay.
   uint64_t duration_us(const JobRec* j) const {
-    if (templates_[j->tmpl].pipeline == SET_PIPE_SAXPY_TANH_SUM_F32) return j->args.n % 1000000ull;
-    return 20;
+    const set_job_template& t = templates_[j->tmpl];
+    if (t.pipeline == SET_PIPE_SAXPY_TANH_SUM_F32) return j->args.n % 1000000ull + t.stress_delay_us;
+    return 20 + t.stress_delay_us;
   }
   static void sleep_us(uint64_t us) {
     if (us) std::this_thread::sleep_for(std::chrono::microseconds(us));

@@ -39,6 +39,7 @@ struct CbCtx {
 
 struct ChainNodes {
   hipGraphNode_t h2d = nullptr, d2h = nullptr, flag = nullptr;
+  hipGraphNode_t delay = nullptr, poison = nullptr;  // memory-safety stress nodes (template options)
   hipGraphNode_t k[kMaxStages] = {};
 };
 
@@ -64,6 +65,10 @@ struct Slot {
   void* d2h_argv[1] = {&d2h_copy};
   DoneFlagArgs flag{};
   void* flag_argv[1] = {&flag};
+  PoisonArgs poison{};
+  void* poison_argv[1] = {&poison};
+  DelayArgs delay{};
+  void* delay_argv[1] = {&delay};
   JobBeginArgs jb{};
   JobEndArgs je{};
   HotspotArgs hot[kMaxHotspotSteps] = {};
@@ -148,6 +153,9 @@ class HipBackend : public Backend {
       return SET_EDEVICE;
     }
     dev_ = cfg.device;
+    int khz = 0;
+    HIPCK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev_));
+    clock_khz_ = khz > 0 ? (uint64_t)khz : 100000;
     pipes_.reserve(kMaxTemplates);  // entries never move while jobs of other templates run
     HIPCK(hipSetDevice(dev_));
     t_dev = dev_;
@@ -242,6 +250,10 @@ class HipBackend : public Backend {
         sl.s = s;
         sl.base = p.arena + p.L.total * ((uint64_t)w * d_ + s);
         setup_slot(p, sl, taps);
+        if (poisons(p)) {  // a slot's first job finds poison too (after the arena's zero fill)
+          if (w == 0 && s == 0) HIPCK(hipDeviceSynchronize());
+          HIPCK(launch_stress(p, sl, true, define_stream_));
+        }
         if (p.lib_ws) {
           sl.lib_ws = (char*)p.lib_ws + lib_ws_bytes * ((size_t)w * d_ + s);
           sl.lib_ws_bytes = lib_ws_bytes;
@@ -401,6 +413,7 @@ class HipBackend : public Backend {
         HIPCK(hipMemcpyAsync(sl.base + p.L.in, sl.host_in, sl.in_bytes, hipMemcpyHostToDevice, st));
       }
     }
+    if (delays(p)) HIPCK(launch_stress(p, sl, false, st));
     for (int i = 0; i < sl.nstages; ++i) {
       if (i == 1) HIPCK(library_stage(p, sl, st));
       HIPCK(hipLaunchKernel(sl.func[i], sl.grid[i], dim3(sl.block[i]), sl.argv[i], 0, st));
@@ -411,6 +424,7 @@ class HipBackend : public Backend {
     } else {
       HIPCK(hipMemcpyAsync(sl.host_out, sl.base + p.L.out, sl.out_bytes, hipMemcpyDeviceToHost, st));
     }
+    if (poisons(p)) HIPCK(launch_stress(p, sl, true, st));
     const uint64_t t0 = now_ns();
     HIPCK(hipStreamSynchronize(st));
     sync_ns_ += now_ns() - t0;
@@ -811,6 +825,35 @@ class HipBackend : public Backend {
         break;
       }
     }
+    // Memory-safety stress: the poisoned range runs from the first buffer
+    // after the header to the tail canary (both 256-byte aligned).
+    const uint64_t zero_word = t.pipeline == SET_PIPE_SAXPY_BATCH_F32
+                                   ? (L.scratch + ((uint64_t)t.tiles_max * 4 + 255) / 256 * 256 - L.in) / 4
+                                   : ~0ull;
+    sl.poison = PoisonArgs{b + L.in, (L.tail - L.in) / 16, zero_word};
+    const uint64_t us = t.stress_delay_us;
+    sl.delay = DelayArgs{us * clock_khz_ / 1000, 8 * us + 64};
+  }
+
+  static bool poisons(const Pipe& p) { return (p.t.flags & SET_TF_POISON) != 0; }
+  static bool delays(const Pipe& p) { return p.t.stress_delay_us > 0; }
+  static unsigned poison_blocks(const Pipe& p) {
+    const uint64_t nvec = (p.L.tail - p.L.in) / 16;
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(1024, (nvec + kBlock - 1) / kBlock));
+  }
+  hipKernelNodeParams stress_params(Pipe& p, Slot& sl, bool poison) {
+    hipKernelNodeParams kp{};
+    kp.func = poison ? (void*)&k_poison : (void*)&k_stress_delay;
+    kp.gridDim = dim3(poison ? poison_blocks(p) : 1);
+    kp.blockDim = dim3(poison ? kBlock : 64);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = poison ? sl.poison_argv : sl.delay_argv;
+    kp.extra = nullptr;
+    return kp;
+  }
+  hipError_t launch_stress(Pipe& p, Slot& sl, bool poison, hipStream_t st) {
+    const hipKernelNodeParams kp = stress_params(p, sl, poison);
+    return hipLaunchKernel(kp.func, kp.gridDim, kp.blockDim, kp.kernelParams, 0, st);
   }
 
   // Write the job's scalars into the slot's first-stage argument block and
@@ -936,6 +979,11 @@ class HipBackend : public Backend {
       }
       prev = cn->h2d;
     }
+    if (delays(p)) {
+      hipKernelNodeParams kp = stress_params(p, sl, false);
+      HIPCK(hipGraphAddKernelNode(&cn->delay, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+      prev = cn->delay;
+    }
     for (int i = 0; i < sl.nstages; ++i) {
       hipKernelNodeParams kp = kparams(sl, i);
       HIPCK(hipGraphAddKernelNode(&cn->k[i], g, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
@@ -949,9 +997,15 @@ class HipBackend : public Backend {
       HIPCK(hipGraphAddMemcpyNode1D(&cn->d2h, g, &prev, 1, p.placeholder, sl.base + p.L.out, p.L.out_cap,
                                     hipMemcpyDeviceToHost));
     }
+    prev = cn->d2h;
+    if (poisons(p)) {
+      hipKernelNodeParams kp = stress_params(p, sl, true);
+      HIPCK(hipGraphAddKernelNode(&cn->poison, g, &prev, 1, &kp));
+      prev = cn->poison;
+    }
     if (p.words && g == sl.graph) {
       hipKernelNodeParams kf = flag_params(sl);
-      HIPCK(hipGraphAddKernelNode(&cn->flag, g, &cn->d2h, 1, &kf));
+      HIPCK(hipGraphAddKernelNode(&cn->flag, g, &prev, 1, &kf));
     }
     return SET_OK;
   }
@@ -982,6 +1036,7 @@ class HipBackend : public Backend {
         HIPCK(hipMemcpyAsync(sl.base + p.L.in, p.placeholder, p.L.in_cap, hipMemcpyHostToDevice, st));
       }
     }
+    if (delays(p)) HIPCK(launch_stress(p, sl, false, st));
     for (int i = 0; i < sl.nstages; ++i) {
       if (i == 1) HIPCK(library_stage(p, sl, st));
       HIPCK(hipLaunchKernel(sl.func[i], sl.grid[i], dim3(sl.block[i]), sl.argv[i], 0, st));
@@ -992,13 +1047,15 @@ class HipBackend : public Backend {
     } else {
       HIPCK(hipMemcpyAsync(p.placeholder, sl.base + p.L.out, p.L.out_cap, hipMemcpyDeviceToHost, st));
     }
+    if (poisons(p)) HIPCK(launch_stress(p, sl, true, st));
     if (p.words) HIPCK(hipLaunchKernel((const void*)&k_done_flag, dim3(1), dim3(64), sl.flag_argv, 0, st));
     HIPCK(hipStreamEndCapture(st, out));
     size_t n = 0;
     HIPCK(hipGraphGetNodes(*out, nullptr, &n));
     std::vector<hipGraphNode_t> nodes(n);
     HIPCK(hipGraphGetNodes(*out, nodes.data(), &n));
-    const size_t fixed = (in_node ? 1 : 0) + sl.nstages + 1 + (p.words ? 1 : 0);
+    const size_t fixed =
+        (in_node ? 1 : 0) + (delays(p) ? 1 : 0) + sl.nstages + 1 + (poisons(p) ? 1 : 0) + (p.words ? 1 : 0);
     const size_t lib_nodes = n - std::min(n, fixed);  // captured library kernels between stages 0 and 1
     if (n < fixed || (lib_template(p.t) ? lib_nodes < 1 : lib_nodes != 0)) {
       if (err) *err = "captured graph has an unexpected number of nodes";
@@ -1029,6 +1086,7 @@ class HipBackend : public Backend {
     }
     size_t k = 0;
     if (in_node) cn->h2d = order[k++];
+    if (delays(p)) cn->delay = order[k++];
     for (int i = 0; i < sl.nstages; ++i) {
       if (i == 1) {
         // the library's nodes: kernels only (no memset or memcpy nodes in a replayed graph)
@@ -1051,6 +1109,7 @@ class HipBackend : public Backend {
       cn->k[i] = order[k++];
     }
     cn->d2h = order[k++];
+    if (poisons(p)) cn->poison = order[k++];
     if (p.words) cn->flag = order[k];
     return SET_OK;
   }
@@ -1112,6 +1171,7 @@ class HipBackend : public Backend {
   std::atomic<bool> poll_new_{false};          // poll_in_ holds entries
   bool poll_stop_ = false;
   bool flag_mode_ = false;
+  uint64_t clock_khz_ = 100000;  // rate of the device's constant clock (stress delay)
 };
 
 }  // namespace

@@ -87,7 +87,9 @@ struct hipKernelNodeParams {
 #define hipHostMallocDefault 0x0
 
 const char* hipGetErrorString(hipError_t e);
+typedef enum hipDeviceAttribute_t { hipDeviceAttributeWallClockRate = 1 } hipDeviceAttribute_t;
 hipError_t hipGetDeviceCount(int* n);
+hipError_t hipDeviceGetAttribute(int* value, hipDeviceAttribute_t attr, int dev);
 hipError_t hipSetDevice(int dev);
 hipError_t hipGetDevice(int* dev);
 hipError_t hipDeviceSynchronize();

@@ -167,6 +167,11 @@ hipError_t hipGetDeviceCount(int* n) {
   *n = 1;
   return hipSuccess;
 }
+hipError_t hipDeviceGetAttribute(int* value, hipDeviceAttribute_t attr, int dev) {
+  if (dev != 0 || attr != hipDeviceAttributeWallClockRate) return hipErrorInvalidValue;
+  *value = 100000;  // kHz
+  return hipSuccess;
+}
 hipError_t hipSetDevice(int dev) { return dev == 0 ? hipSuccess : hipErrorInvalidValue; }
 hipError_t hipGetDevice(int* dev) {
   *dev = 0;
@@ -496,6 +501,13 @@ void publish(const SlotConst& sc) {
 void k_copy_in(CopyArgs a) { std::memcpy(a.dst, a.src, a.bytes); }
 void k_copy_out(CopyArgs a) { std::memcpy(a.dst, a.src, a.bytes); }
 void k_done_flag(DoneFlagArgs a) { __atomic_store_n(a.word, a.hdr->seq, __ATOMIC_RELEASE); }
+void k_poison(PoisonArgs a) {
+  std::memset(a.p, 0xFF, a.nvec * 16);
+  if (a.zero_word != ~0ull) reinterpret_cast<uint32_t*>(a.p)[a.zero_word] = 0;
+}
+void k_stress_delay(DelayArgs a) {  // the stand-in clock runs at 100 MHz
+  std::this_thread::sleep_for(std::chrono::nanoseconds(a.ticks * 10));
+}
 void k_job_begin(JobBeginArgs a) { stamp(a.hdr, a.js); }
 void k_job_end(JobEndArgs a) { publish(a.sc); }
 template <bool FULL>
@@ -554,6 +566,8 @@ struct Register {
     register_kernel(&k_copy_in);
     register_kernel(&k_copy_out);
     register_kernel(&k_done_flag);
+    register_kernel(&k_poison);
+    register_kernel(&k_stress_delay);
     register_kernel(&k_job_begin);
     register_kernel(&k_job_end);
     register_kernel(&k_hotspot_win_f32<true>);

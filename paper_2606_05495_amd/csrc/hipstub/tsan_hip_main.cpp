@@ -22,6 +22,7 @@ struct Run {
   const char* name;
   int mode, workers, slots, callback, dispatchers, policy, copy, copy_streams, inflight;
   int define_while_running;  // define captured templates while the jobs run
+  int stress;                // 1: poison-fill slots after each job and delay each job's first stage
 };
 
 int run_images(const Run& r, int producers, int per_producer) {
@@ -51,6 +52,10 @@ int run_images(const Run& r, int producers, int per_producer) {
   t.width = 32;
   t.height = 24;
   t.copy_mode = (uint32_t)r.copy;
+  if (r.stress) {
+    t.flags |= SET_TF_POISON;
+    t.stress_delay_us = 20;
+  }
   int tid = -1;
   if (set_template_define(c, &t, &tid) != SET_OK) {
     std::printf("%s: define failed: %s\n", r.name, set_last_error(c));
@@ -194,9 +199,14 @@ int main() {
        SET_COPY_KERNELS, 0, 0, 3},
       {"set, event chain, define while running", SET_MODE_SET, 4, 4, SET_CB_EVENT_CHAIN, 2, SET_SUBMIT_SKEW0,
        SET_COPY_KERNELS, 0, 0, 3},
+      {"set, poison + delay, DMA at bind", SET_MODE_SET, 8, 2, SET_CB_EVENT_POLL, 4, SET_SUBMIT_SKEW0,
+       SET_COPY_ASYNC_IN, 2, 1, 0, 1},
+      {"set, poison + delay, host flag", SET_MODE_SET, 4, 1, SET_CB_HOST_FLAG, 2, SET_SUBMIT_SKEW0,
+       SET_COPY_KERNELS, 0, 0, 0, 1},
       {"sync", SET_MODE_SYNC, 4, 1, 0, 1, 0, SET_COPY_ASYNC_IN, 2, 0, 0},
       {"graph", SET_MODE_GRAPH, 4, 1, 0, 1, 0, SET_COPY_KERNELS, 0, 0, 0},
       {"batch-sync", SET_MODE_BATCH_SYNC, 4, 2, 0, 1, 0, SET_COPY_NODES, 0, 0, 0},
+      {"batch-sync, poison + delay", SET_MODE_BATCH_SYNC, 4, 2, 0, 1, 0, SET_COPY_KERNELS, 0, 0, 0, 1},
       {"queue model", SET_MODE_QUEUE, 4, 1, 0, 1, 0, SET_COPY_KERNELS, 0, 0, 0},
   };
   int rc = 0, i = 0;

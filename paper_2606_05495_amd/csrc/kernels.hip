@@ -139,6 +139,33 @@ __global__ __launch_bounds__(64) void k_done_flag(DoneFlagArgs a) {
   if (threadIdx.x == 0) __hip_atomic_store(a.word, a.hdr->seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// ------------------------------------------------------------------ memory-safety stress
+__global__ __launch_bounds__(kBlock) void k_poison(PoisonArgs a) {
+  const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  const uint64_t zv = a.zero_word >> 2;  // the 16-byte word that holds the zero word, if any
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < a.nvec; i += stride) {
+    uint4 v = ones;
+    if (i == zv) {
+      const unsigned c = (unsigned)(a.zero_word & 3);
+      v.x = c == 0 ? 0u : v.x;
+      v.y = c == 1 ? 0u : v.y;
+      v.z = c == 2 ? 0u : v.z;
+      v.w = c == 3 ? 0u : v.w;
+    }
+    reinterpret_cast<uint4*>(a.p)[i] = v;
+  }
+}
+
+// One wave; s_sleep 8 is 512 clocks, so the loop ends within max_sleeps
+// iterations even if the clock does not advance.
+__global__ __launch_bounds__(64) void k_stress_delay(DelayArgs a) {
+  if (threadIdx.x != 0) return;
+  const uint64_t t0 = (uint64_t)wall_clock64();
+  for (uint64_t k = 0; k < a.max_sleeps && (uint64_t)wall_clock64() - t0 < a.ticks; ++k)
+    __builtin_amdgcn_s_sleep(8);
+}
+
 // ------------------------------------------------------------------ bracket kernels of library-call jobs
 __global__ __launch_bounds__(kBlock) void k_job_begin(JobBeginArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);

@@ -141,6 +141,27 @@ struct DoneFlagArgs {
 };
 __global__ void k_done_flag(DoneFlagArgs a);
 
+// Memory-safety stress (template options).  k_poison runs after a job's
+// output copy and fills the slot's buffers (everything between the header
+// and the tail canary) with 0xFF bytes, so a job that read anything a
+// previous job left in its slot would read NaN / all-ones values; the one
+// word the slot carries from job to job on purpose (the work counter of
+// batched vector templates, rewound to zero by the job's last stage) is
+// written as zero.  k_stress_delay runs before the first stage and sleeps
+// until the device's constant-rate clock has advanced by `ticks`, stretching
+// the window in which a slot released too early would be overwritten.
+struct PoisonArgs {
+  void* p;              // 16-byte aligned start of the poisoned range
+  uint64_t nvec;        // 16-byte words in the range
+  uint64_t zero_word;   // index (uint32 units from p) of the word written as 0, or ~0 for none
+};
+__global__ void k_poison(PoisonArgs a);
+struct DelayArgs {
+  uint64_t ticks;       // constant-clock ticks to wait
+  uint64_t max_sleeps;  // bound on the sleep loop, so the wait ends whatever the clock reads
+};
+__global__ void k_stress_delay(DelayArgs a);
+
 // Bracket kernels of a job whose middle stages are library code captured
 // into the job graph: the first writes the job's scalars into the slot
 // header, the last checks the canaries and publishes the output header.

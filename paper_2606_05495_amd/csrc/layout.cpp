@@ -57,7 +57,10 @@ int pipeline_validate(const set_job_template& t, std::string* why) {
   }
   if (t.block != 0 && t.pipeline != SET_PIPE_SAXPY_BATCH_F32)
     return bad("only the vector batch template takes a block size (block must be 0)");
-  if (t.flags & ~(uint32_t)(SET_TF_DEBUG | SET_TF_SCAN_LOW32 | SET_TF_CAPTURE)) return bad("unknown template flags");
+  if (t.flags & ~(uint32_t)(SET_TF_DEBUG | SET_TF_SCAN_LOW32 | SET_TF_CAPTURE | SET_TF_POISON))
+    return bad("unknown template flags");
+  if (t.stress_delay_us > 100000) return bad("stress_delay_us above 100000");
+  if (t.reserved != 0) return bad("reserved template field must be 0");
   if (t.copy_mode != SET_COPY_KERNELS && t.copy_mode != SET_COPY_NODES && t.copy_mode != SET_COPY_ASYNC_IN)
     return bad("unknown copy mode");
   return SET_OK;

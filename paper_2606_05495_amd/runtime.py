@@ -86,10 +86,12 @@ class Context:
         self.cfg = cfg
         self.h = A.set_ctx_create(cfg)
         self.templates = {}
+        self.arenas = {}
 
     # ------------------------------------------------------------ templates
     def define(self, pipeline, width=0, height=0, max_n=0, flags=0, threshold=0.0, x_pool=None, y_pool=None,
-               borrow_arena=True, pool_ptrs=None, copy="kernels", batch_max=0, tiles_max=0, grid=0, block=0):
+               borrow_arena=True, pool_ptrs=None, copy="kernels", batch_max=0, tiles_max=0, grid=0, block=0,
+               stress_delay_us=0):
         t = A.set_job_template()
         t.pipeline = PIPELINES[pipeline] if isinstance(pipeline, str) else int(pipeline)
         t.flags = flags
@@ -102,6 +104,7 @@ class Context:
         t.tiles_max = tiles_max
         t.grid = grid
         t.block = block
+        t.stress_delay_us = stress_delay_us
         if x_pool is not None:
             t.dev_x_pool = x_pool.data_ptr()
             t.dev_y_pool = y_pool.data_ptr()
@@ -110,6 +113,7 @@ class Context:
         elif pool_ptrs is not None:  # raw device addresses (x, y, length)
             t.dev_x_pool, t.dev_y_pool, t.pool_len = pool_ptrs
         slot_bytes, total = A.set_template_footprint(self.cfg, t)
+        arena = None
         if self.backend == "hip" and borrow_arena:
             torch = _torch()
             arena = torch.empty(total, dtype=torch.uint8, device=torch.device("cuda", self.cfg.device))
@@ -118,6 +122,8 @@ class Context:
             t.arena_bytes = total
         tid = A.set_template_define(self.h, t)
         self.templates[tid] = t
+        if arena is not None:  # the device buffer that holds every slot of the template
+            self.arenas[tid] = arena
         return tid
 
     def in_bytes(self, tid, n=0):

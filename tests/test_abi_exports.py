@@ -28,7 +28,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(A.set_config) == 96
     assert ctypes.sizeof(A.set_job_args) == 80 == A.JOB_ARGS_DTYPE.itemsize
     assert ctypes.sizeof(A.set_out_header) == 64 == A.OUT_HEADER_DTYPE.itemsize
-    assert ctypes.sizeof(A.set_job_template) == 88
+    assert ctypes.sizeof(A.set_job_template) == 96
     assert A.VEC_JOB_DTYPE.itemsize == 32 and ctypes.sizeof(A.set_vec_tuning) == 512
     assert A.REQUEST_DTYPE.itemsize == 96 and ctypes.sizeof(A.set_serve_config) == 24
     for f, off in (("a", 40), ("worker_hint", 44), ("x_off", 48), ("user_tag", 64)):

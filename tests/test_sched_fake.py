@@ -586,6 +586,37 @@ def test_block_size_only_for_vector_batches():
             ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL, block=256)
 
 
+def test_stress_template_options():
+    """The memory-safety stress options: the poison flag and a delay of
+    0..100000 us are accepted, a larger delay or a nonzero reserved field is
+    refused.  On the fake backend the delay lengthens every job, and with one
+    slot per worker under skewed submission no job runs in a slot another job
+    still holds (the fake backend's clash check, reported per job as the
+    canary flag)."""
+    with _fake(workers=4, slots=1, submit_policy=A.SET_SUBMIT_SKEW0, dispatchers=2) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL, flags=A.SET_TF_POISON,
+                         stress_delay_us=2000)
+        ctx.define("gauss_sobel", width=8, height=8, flags=A.SET_TF_POISON, stress_delay_us=100000)
+        with pytest.raises(A.SetError):
+            ctx.define("gauss_sobel", width=8, height=8, stress_delay_us=100001)
+        t = A.set_job_template()
+        t.pipeline = A.SET_PIPE_GAUSS_SOBEL_F32
+        t.width = t.height = 8
+        t.reserved = 1
+        with pytest.raises(A.SetError):
+            A.set_template_define(ctx.h, t)
+        arr, outs = _vec_jobs(ctx, tid, 16, 10)
+        t0 = time.perf_counter()
+        first = ctx.submit_many(tid, arr)
+        ctx.drain(timeout_ns=int(10e9))
+        dt = time.perf_counter() - t0
+        hs = _headers(outs)
+        assert np.all(hs["canary_ok"] == 1)
+        assert np.array_equal(hs["job_id"], first + np.arange(16))
+        assert dt >= 16 * 2010e-6 / 4  # four workers, each job at least 2 ms
+        assert ctx.stats().stolen > 0
+
+
 def test_empty_inputs():
     """Empty submissions and empty vector batches are no-ops: nothing is
     counted, drain returns at once, and the context stays usable."""
