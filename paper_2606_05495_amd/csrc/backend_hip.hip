@@ -242,6 +242,7 @@ class HipBackend : public Backend {
       HIPCK(hipMalloc(&p.lib_ws, lib_ws_bytes * (size_t)b_ * d_));
     }
     p.slots.resize((size_t)b_ * d_);
+    if (poisons(p)) HIPCK(hipDeviceSynchronize());  // the zero fill above, before the poison fill
     for (int w = 0; w < b_; ++w) {
       for (int s = 0; s < d_; ++s) {
         Slot& sl = p.slots[(size_t)w * d_ + s];
@@ -250,10 +251,7 @@ class HipBackend : public Backend {
         sl.s = s;
         sl.base = p.arena + p.L.total * ((uint64_t)w * d_ + s);
         setup_slot(p, sl, taps);
-        if (poisons(p)) {  // a slot's first job finds poison too (after the arena's zero fill)
-          if (w == 0 && s == 0) HIPCK(hipDeviceSynchronize());
-          HIPCK(launch_stress(p, sl, true, define_stream_));
-        }
+        if (poisons(p)) HIPCK(launch_stress(p, sl, true, define_stream_));  // a slot's first job finds poison too
         if (p.lib_ws) {
           sl.lib_ws = (char*)p.lib_ws + lib_ws_bytes * ((size_t)w * d_ + s);
           sl.lib_ws_bytes = lib_ws_bytes;
@@ -827,8 +825,9 @@ class HipBackend : public Backend {
     }
     // Memory-safety stress: the poisoned range runs from the first buffer
     // after the header to the tail canary (both 256-byte aligned).
+    // The batched-vector work counter is the one word kept as zero.
     const uint64_t zero_word = t.pipeline == SET_PIPE_SAXPY_BATCH_F32
-                                   ? (L.scratch + ((uint64_t)t.tiles_max * 4 + 255) / 256 * 256 - L.in) / 4
+                                   ? (uint64_t)(reinterpret_cast<char*>(sl.vb.work) - (b + L.in)) / 4
                                    : ~0ull;
     sl.poison = PoisonArgs{b + L.in, (L.tail - L.in) / 16, zero_word};
     const uint64_t us = t.stress_delay_us;

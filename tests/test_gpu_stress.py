@@ -219,6 +219,22 @@ def test_poison_scan_ragged_tails(torch_gpu):
     ctx.close()
 
 
+def test_poison_library_scan_template(torch_gpu):
+    """The captured library call (rocPRIM's scan between the bracket kernels)
+    with poisoned slots: bit-exact sums, job after job in the same slots."""
+    _say("poison library scan")
+    n = 100003
+    rng = np.random.default_rng(22)
+    inputs = [rng.integers(-(1 << 20), (1 << 20) + 1, n).astype(np.int32) for _ in range(6)]
+    ctx = _ctx("set", 1, workers=2)
+    tid = ctx.define("scan_lib", max_n=n, flags=A.SET_TF_POISON, copy="kernels", stress_delay_us=20)
+    ob = ctx.out_bytes(tid, n)
+    outs, _, _ = _submit(ctx, tid, [v.view(np.uint8) for v in inputs], [ob] * len(inputs))
+    for v, o in zip(inputs, outs):
+        assert np.array_equal(o[64:64 + 8 * n].view(np.int64), oracle.scan(v))
+    ctx.close()
+
+
 def test_poison_thermal_grid(torch_gpu):
     """Every step reads the previous step's buffer: none may see poison."""
     _say("poison hotspot")
