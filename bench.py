@@ -59,13 +59,14 @@ def make_jobs(ctx, tid, n_jobs, tin, pool, ib, tout, ob, stride):
 
 
 def run_mode(mode, args, jobs_per_step, steps, warmup, tin, tout, pool, torch, callback="event_chain", copy=None,
-             copy_streams=None):
+             copy_streams=None, callback_streams=0):
     from paper_2606_05495_amd.runtime import Context
     workers = args.workers
     ctx = Context(mode=mode, workers=workers, slots=args.slots if mode == "set" else 1,
                   batch_size=args.batch if mode == "batch" else 0, callback=callback, inflight=args.inflight,
                   spin_us=args.spin_us, dispatchers=args.dispatchers,
-                  input_copy_streams=args.input_copy_streams if copy_streams is None else copy_streams)
+                  input_copy_streams=args.input_copy_streams if copy_streams is None else copy_streams,
+                  callback_streams=callback_streams)
     tid = ctx.define("gauss_sobel", width=1024, height=1024, copy=copy or args.copy)
     ib, ob = ctx.in_bytes(tid), ctx.out_bytes(tid)
     stride = 128
@@ -933,7 +934,7 @@ def main():
     ap.add_argument("--retune", action="store_true", help="vector workloads: tune block, item sizes and grids afresh")
     ap.add_argument("--tune-cache", default=None, help="tuning cache file (default: the package's tuning/vec_batch.json)")
     ap.add_argument("--image-pool", type=int, default=61, help="distinct images the jobs cycle through")
-    ap.add_argument("--mechanisms", default="event_poll,event_chain,event_blocking",
+    ap.add_argument("--mechanisms", default="event_poll,event_chain,event_chain_per_worker,event_blocking",
                     help="SET completion mechanisms the image workload also runs (comma list; empty: none)")
     ap.add_argument("--mech-steps", type=int, default=3)
     ap.add_argument("--no-sections", action="store_true",
@@ -1060,20 +1061,25 @@ def traced_timelines(args, modes):
 def run_mechanisms(args, tin, tout, pool, torch, imgs, refs):
     """The same image jobs in SET with each other completion mechanism (Algorithm 3's
     release path), a short run each: jobs/s, and the host CPU time the process used
-    per second of the run (a spinning completion thread shows as about one core)."""
+    per second of the run (a spinning completion thread shows as about one core).
+    "event_chain" shares one callback stream among the workers;
+    "event_chain_per_worker" gives each worker its own."""
     out = {}
-    for cb in [c for c in args.mechanisms.split(",") if c and c != args.callback]:
-        log("SET with %s: %d jobs x %d steps" % (cb, args.jobs, args.mech_steps))
+    for name in [c for c in args.mechanisms.split(",") if c and c != args.callback]:
+        per_worker = name == "event_chain_per_worker"
+        cb = "event_chain" if per_worker else name
+        log("SET with %s: %d jobs x %d steps" % (name, args.jobs, args.mech_steps))
         tout.zero_()
         c0 = time.process_time()
         w0 = time.perf_counter()
-        ctx, _, dt, st, _ = run_mode("set", args, args.jobs, args.mech_steps, 1, tin, tout, pool, torch, callback=cb)
+        ctx, _, dt, st, _ = run_mode("set", args, args.jobs, args.mech_steps, 1, tin, tout, pool, torch, callback=cb,
+                                     callback_streams=args.workers if per_worker else 0)
         cpu = (time.process_time() - c0) / (time.perf_counter() - w0)
         ctx.close()
         ok, bad = verify(tout, args.jobs, imgs, refs)
-        out[cb] = {"jobs_per_s": round(args.jobs * args.mech_steps / dt, 1), "verified": ok, "wrong_jobs": int(bad),
-                   "steps": args.mech_steps, "host_cpu_s_per_s": round(cpu, 2),
-                   "host_us_per_job_launch": round(st.host_ns_launch / 1e3 / max(1, st.completed), 2)}
+        out[name] = {"jobs_per_s": round(args.jobs * args.mech_steps / dt, 1), "verified": ok, "wrong_jobs": int(bad),
+                     "steps": args.mech_steps, "host_cpu_s_per_s": round(cpu, 2),
+                     "host_us_per_job_launch": round(st.host_ns_launch / 1e3 / max(1, st.completed), 2)}
     return out
 
 

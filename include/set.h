@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SET_ABI_VERSION 3u
+#define SET_ABI_VERSION 4u
 
 /* ---------------------------------------------------------------- status codes */
 enum set_status {
@@ -253,6 +253,16 @@ typedef struct set_config {
      * 0 = each input copy on its worker's own stream, right before the graph.
      * 0..64, capped at num_workers. */
     int32_t input_copy_streams;
+    /* SET_CB_EVENT_CHAIN (Algorithm 3): the number K of callback streams;
+     * worker w's event waits and host functions go on stream w % K.  0 = 1.
+     * 1..64, capped at num_workers.  A host function holds its hardware queue
+     * until the host has run it, and ROCm maps every stream of a process onto
+     * 4 hardware queues: with one callback stream a single queue carries those
+     * packets, with one per worker every queue does and the worker streams
+     * stall behind them (1024x1024 images, 8 workers: 13.2k against 10.3-11.0k
+     * jobs/s). */
+    int32_t callback_streams;
+    int32_t reserved;            /* must be 0 */
 } set_config;
 
 typedef struct set_job_template {

@@ -20,7 +20,7 @@ except Exception:  # pragma: no cover - torch is part of the image
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libset.so")
 
-SET_ABI_VERSION = 3
+SET_ABI_VERSION = 4
 
 # status codes
 SET_OK, SET_EINVAL, SET_ENOMEM, SET_EDEVICE, SET_EAGAIN, SET_ETIMEOUT, SET_ECLOSED, SET_EUNSUPPORTED = (
@@ -71,6 +71,8 @@ class set_config(ctypes.Structure):
         ("fake_reorder_callbacks", ctypes.c_int32),
         ("dispatch_threads", ctypes.c_int32),
         ("input_copy_streams", ctypes.c_int32),
+        ("callback_streams", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

@@ -179,8 +179,9 @@ class HipBackend : public Backend {
     copy_streams_.resize(std::min(cfg.input_copy_streams, b_));
     for (hipStream_t& cs : copy_streams_) HIPCK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     if (cfg.mode == SET_MODE_SET && cfg.callback_mode == SET_CB_EVENT_CHAIN) {
-      cb_streams_.resize(b_);
-      for (int i = 0; i < b_; ++i) HIPCK(hipStreamCreateWithFlags(&cb_streams_[i], hipStreamNonBlocking));
+      cb_streams_.resize((size_t)std::min(b_, std::max(1, cfg.callback_streams)));
+      for (hipStream_t& cs : cb_streams_) HIPCK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      cb_mu_.reset(new std::mutex[cb_streams_.size()]);
     }
     flag_mode_ = cfg.mode == SET_MODE_SET && cfg.callback_mode == SET_CB_HOST_FLAG;
     if (cfg.mode == SET_MODE_SET && (cfg.callback_mode == SET_CB_EVENT_POLL || flag_mode_)) {
@@ -333,11 +334,16 @@ class HipBackend : public Backend {
     HIPCK(input_ahead(p, sl, st, w));
     HIPCK(hipGraphLaunch(sl.exec, st));
     switch (cfg_.callback_mode) {
-      case SET_CB_EVENT_CHAIN:
+      case SET_CB_EVENT_CHAIN: {
         HIPCK(hipEventRecord(sl.ev, st));
-        HIPCK(hipStreamWaitEvent(cb_streams_[w], sl.ev, 0));
-        HIPCK(hipLaunchHostFunc(cb_streams_[w], &HipBackend::host_cb, &sl.cb));
+        // the wait and its host function stay adjacent on a callback stream
+        // that several dispatcher threads share
+        const size_t k = (size_t)w % cb_streams_.size();
+        std::lock_guard<std::mutex> g(cb_mu_[k]);
+        HIPCK(hipStreamWaitEvent(cb_streams_[k], sl.ev, 0));
+        HIPCK(hipLaunchHostFunc(cb_streams_[k], &HipBackend::host_cb, &sl.cb));
         break;
+      }
       case SET_CB_SAME_STREAM:
         HIPCK(hipLaunchHostFunc(st, &HipBackend::host_cb, &sl.cb));
         break;
@@ -1148,6 +1154,7 @@ class HipBackend : public Backend {
   int b_ = 0, d_ = 0, dev_ = -1;
   bool own_streams_ = false, down_ = false;
   std::vector<hipStream_t> streams_, cb_streams_;
+  std::unique_ptr<std::mutex[]> cb_mu_;  // one per callback stream
   std::vector<hipStream_t> copy_streams_;  // input-copy streams (set_config.input_copy_streams)
   hipStream_t define_stream_ = nullptr;    // template capture and graph upload, never a worker's
   std::vector<std::unique_ptr<Pipe>> pipes_;

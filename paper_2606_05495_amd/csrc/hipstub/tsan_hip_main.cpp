@@ -23,6 +23,7 @@ struct Run {
   int mode, workers, slots, callback, dispatchers, policy, copy, copy_streams, inflight;
   int define_while_running;  // define captured templates while the jobs run
   int stress;                // 1: poison-fill slots after each job and delay each job's first stage
+  int cb_streams;            // event chaining: callback streams (0 = one shared by every worker)
 };
 
 int run_images(const Run& r, int producers, int per_producer) {
@@ -39,6 +40,7 @@ int run_images(const Run& r, int producers, int per_producer) {
   cfg.dispatch_threads = r.dispatchers;
   cfg.input_copy_streams = r.copy_streams;
   cfg.inflight_per_worker = r.inflight;
+  cfg.callback_streams = r.cb_streams;
   cfg.staging_capacity = 256;
   cfg.batch_size = r.mode == SET_MODE_BATCH_SYNC ? r.workers : 0;
   set_ctx* c = nullptr;
@@ -187,6 +189,10 @@ int main() {
        SET_COPY_KERNELS, 0, 0, 0},
       {"set, event chain, 3 dispatchers", SET_MODE_SET, 6, 4, SET_CB_EVENT_CHAIN, 3, SET_SUBMIT_SKEW0,
        SET_COPY_NODES, 0, 0, 0},
+      {"set, event chain, 2 callback streams", SET_MODE_SET, 6, 4, SET_CB_EVENT_CHAIN, 3, SET_SUBMIT_SKEW0,
+       SET_COPY_KERNELS, 0, 0, 0, 0, 2},
+      {"set, event chain, stream per worker", SET_MODE_SET, 6, 4, SET_CB_EVENT_CHAIN, 2, SET_SUBMIT_ROUND_ROBIN,
+       SET_COPY_KERNELS, 0, 0, 0, 0, 6},
       {"set, same stream, 2 dispatchers", SET_MODE_SET, 4, 4, SET_CB_SAME_STREAM, 2, SET_SUBMIT_ROUND_ROBIN,
        SET_COPY_KERNELS, 0, 0, 0},
       {"set, event blocking, 4 dispatchers", SET_MODE_SET, 8, 4, SET_CB_EVENT_BLOCKING, 4, SET_SUBMIT_SKEW0,

@@ -67,7 +67,7 @@ struct DevSlotHdr {
 };
 static_assert(sizeof(DevSlotHdr) == 64, "DevSlotHdr layout");
 static_assert(sizeof(set_out_header) == 64, "set_out_header layout");
-static_assert(sizeof(set_config) == 96, "set_config layout");
+static_assert(sizeof(set_config) == 104, "set_config layout");
 static_assert(sizeof(set_job_template) == 96, "set_job_template layout");
 
 // Descriptor table of a vector batch (host-written, copied to the slot by

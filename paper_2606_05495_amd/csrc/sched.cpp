@@ -1315,6 +1315,7 @@ int set_ctx_create(const set_config* cfg, set_ctx** out) {
       cfg->inflight_per_worker < 0 || cfg->queue_capacity < 0 || cfg->spin_us < 0 || cfg->staging_capacity < 0 ||
       cfg->dispatch_threads < 0 || cfg->dispatch_threads > setrt::kMaxThreads ||
       cfg->input_copy_streams < 0 || cfg->input_copy_streams > setrt::kMaxThreads ||
+      cfg->callback_streams < 0 || cfg->callback_streams > setrt::kMaxThreads || cfg->reserved != 0 ||
       (cfg->backend != SET_BACKEND_HIP && cfg->backend != SET_BACKEND_FAKE)) {
     setrt::g_create_error = "invalid configuration";
     return SET_EINVAL;

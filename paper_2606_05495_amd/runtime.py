@@ -49,7 +49,8 @@ class Context:
     def __init__(self, mode="set", workers=8, slots=16, backend="hip", queue_capacity=0, inflight=0,
                  stealing=True, batch_size=0, callback="event_poll", submit_policy=A.SET_SUBMIT_ROUND_ROBIN,
                  spin_us=0, staging=0, mem_budget=0, device=0, seed=0, borrow_streams=True,
-                 fake_fail_after=0, fake_reorder=False, dispatchers=1, input_copy_streams=0):
+                 fake_fail_after=0, fake_reorder=False, dispatchers=1, input_copy_streams=0,
+                 callback_streams=0):
         self.backend = backend
         self.workers = workers
         self.slots = slots
@@ -75,6 +76,7 @@ class Context:
         cfg.fake_reorder_callbacks = 1 if fake_reorder else 0
         cfg.dispatch_threads = dispatchers
         cfg.input_copy_streams = input_copy_streams
+        cfg.callback_streams = callback_streams
         self.streams = []
         if backend == "hip" and borrow_streams:
             torch = _torch()

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(A.set_config) == 96
+    assert ctypes.sizeof(A.set_config) == 104
     assert ctypes.sizeof(A.set_job_args) == 80 == A.JOB_ARGS_DTYPE.itemsize
     assert ctypes.sizeof(A.set_out_header) == 64 == A.OUT_HEADER_DTYPE.itemsize
     assert ctypes.sizeof(A.set_job_template) == 96
@@ -43,6 +43,29 @@ def test_strerror_and_create_errors():
     rc = A.load().set_ctx_create(ctypes.byref(cfg), ctypes.byref(h))
     assert rc == A.SET_EINVAL and not h.value
     assert "abi_version" in A.set_last_error(None)
+
+
+def test_callback_streams_range():
+    """callback_streams takes 0..64 and the reserved word must be 0 (checked
+    before any device is touched: the fake backend serves here)."""
+    def create(**fields):
+        cfg = A.set_config()
+        cfg.abi_version = A.SET_ABI_VERSION
+        cfg.backend = A.SET_BACKEND_FAKE
+        cfg.num_workers, cfg.slots_per_worker = 4, 2
+        cfg.callback_mode = A.SET_CB_EVENT_CHAIN
+        for k, v in fields.items():
+            setattr(cfg, k, v)
+        h = ctypes.c_void_p()
+        rc = A.load().set_ctx_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc == A.SET_OK:
+            A.load().set_ctx_destroy(h)
+        return rc
+    for k in (0, 1, 4, 64):
+        assert create(callback_streams=k) == A.SET_OK
+    for k in (-1, 65):
+        assert create(callback_streams=k) == A.SET_EINVAL
+    assert create(reserved=1) == A.SET_EINVAL
 
 
 def test_footprint_is_host_only():
