@@ -1157,6 +1157,20 @@ def test_hotspot_parity(torch_gpu, mode, shape):
             assert np.max(np.abs(o - ref)) <= oracle.hotspot_tolerance(ref, steps), (shape, steps)
 
 
+@pytest.mark.parametrize("shape", [(1024, 1024), (1030, 1028)])
+def test_hotspot_parity_large_grids(torch_gpu, shape):
+    """Grids of a million cells and more: full width, and a width with lanes
+    past the edge and a ragged last row group."""
+    _say("hotspot large", shape)
+    h, w = shape
+    grids = [synth.hotspot_input(1, k, h, w) for k in range(2)]
+    for steps in (1, 3):
+        outs = _run_hotspot("set", grids, steps, workers=2, slots=2)
+        for (t0, p), o in zip(grids, outs):
+            ref = oracle.hotspot(t0, p, steps)
+            assert np.max(np.abs(o - ref)) <= oracle.hotspot_tolerance(ref, steps), (shape, steps)
+
+
 @pytest.mark.parametrize("mode", ["sync", "graph", "batch", "queue", "set"])
 def test_hotspot_workload(torch_gpu, mode):
     """256x256 grids, 16 steps per job, 8 workers: every mode, identical results for identical inputs."""
