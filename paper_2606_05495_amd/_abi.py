@@ -30,6 +30,7 @@ SET_MODE_SET, SET_MODE_SYNC, SET_MODE_GRAPH, SET_MODE_BATCH_SYNC, SET_MODE_QUEUE
 SET_BACKEND_HIP, SET_BACKEND_FAKE = 0, 1
 SET_CB_EVENT_POLL, SET_CB_EVENT_CHAIN, SET_CB_SAME_STREAM, SET_CB_HOST_FLAG, SET_CB_EVENT_BLOCKING = 0, 1, 2, 3, 4
 SET_SUBMIT_ROUND_ROBIN, SET_SUBMIT_SHORTEST, SET_SUBMIT_SKEW0 = 0, 1, 2
+SET_STEAL_ANY, SET_STEAL_BUSY = 0, 1
 # pipelines
 SET_PIPE_BOX_HIST_U8, SET_PIPE_GAUSS_SOBEL_F32, SET_PIPE_SAXPY_TANH_SUM_F32, SET_PIPE_SCAN_I32_I64 = 0, 1, 2, 3
 SET_PIPE_SAXPY_BATCH_F32 = 4
@@ -72,7 +73,7 @@ class set_config(ctypes.Structure):
         ("dispatch_threads", ctypes.c_int32),
         ("input_copy_streams", ctypes.c_int32),
         ("callback_streams", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("steal_policy", ctypes.c_int32),
     ]
 
 

@@ -175,6 +175,7 @@ class Context {
   // ---- stats
   std::atomic<uint64_t> st_completed{0}, st_stolen{0}, st_failed{0};
   std::atomic<uint64_t> st_launch[kMaxWorkers];
+  std::atomic<int> free_permits[kMaxWorkers];  // launch permits of each worker sitting in a pool
   std::atomic<uint64_t> st_ns_bind{0}, st_ns_launch{0}, st_ns_cb{0}, st_ns_sync{0};
   std::atomic<uint32_t> st_q_hw{0}, st_inflight_hw{0};
   std::atomic<int64_t> inflight{0};
@@ -315,7 +316,10 @@ class Context {
     tsizes.reserve(kMaxTemplates);
     free_mask.reserve(kMaxTemplates);
     slot_seq.reserve(kMaxTemplates);
-    for (int i = 0; i < kMaxWorkers; ++i) st_launch[i] = 0;
+    for (int i = 0; i < kMaxWorkers; ++i) {
+      st_launch[i] = 0;
+      free_permits[i] = 0;
+    }
     // A thief steals only into a FREE slot of its own; with an empty queue and a
     // permit in hand it has at most kperm - 1 slots in flight, so kperm <= d
     // guarantees progress (q + k <= d additionally guarantees every steal finds a slot).
@@ -337,6 +341,7 @@ class Context {
       // permits interleaved across workers so the first launches spread out
       for (int r = 0; r < kperm; ++r)
         for (int w = 0; w < b; ++w) disp[w % ndisp]->pool.push_back(w);
+      for (int w = 0; w < b; ++w) free_permits[w] = kperm;
       submitter = std::thread([this] { submitter_loop(); });
       for (int t = 0; t < ndisp; ++t) dispatchers.emplace_back([this, t] { dispatcher_loop(t); });
     }
@@ -466,6 +471,7 @@ class Context {
       {
         std::lock_guard<std::mutex> g(ds.mu);
         ds.pool.push_back(w);  // W_pool.push(w)
+        ++free_permits[w];
         ++ds.pool_gen;
       }
       ds.cv.notify_one();  // notify_one()
@@ -613,6 +619,8 @@ class Context {
     if (!cfg.work_stealing) return nullptr;
     for (int k = 1; k < b; ++k) {
       const int v = (w + k) % b;
+      // SET_STEAL_BUSY: a victim holding a free permit launches the job itself
+      if (cfg.steal_policy == SET_STEAL_BUSY && free_permits[v].load(std::memory_order_relaxed) > 0) continue;
       int new_slot = -1;
       JobRec* s = queues[v]->try_steal_if([&](JobRec* cand) {
         new_slot = acquire_slot(cand->tmpl, w);
@@ -724,6 +732,7 @@ class Context {
       {
         std::lock_guard<std::mutex> g(ds.mu);
         ds.pool.erase(std::find(ds.pool.begin(), ds.pool.end(), chosen));
+        --free_permits[chosen];
       }
       --queued;
       launch_job(job, chosen);  // LaunchJob
@@ -1315,7 +1324,8 @@ int set_ctx_create(const set_config* cfg, set_ctx** out) {
       cfg->inflight_per_worker < 0 || cfg->queue_capacity < 0 || cfg->spin_us < 0 || cfg->staging_capacity < 0 ||
       cfg->dispatch_threads < 0 || cfg->dispatch_threads > setrt::kMaxThreads ||
       cfg->input_copy_streams < 0 || cfg->input_copy_streams > setrt::kMaxThreads ||
-      cfg->callback_streams < 0 || cfg->callback_streams > setrt::kMaxThreads || cfg->reserved != 0 ||
+      cfg->callback_streams < 0 || cfg->callback_streams > setrt::kMaxThreads ||
+      (cfg->steal_policy != SET_STEAL_ANY && cfg->steal_policy != SET_STEAL_BUSY) ||
       (cfg->backend != SET_BACKEND_HIP && cfg->backend != SET_BACKEND_FAKE)) {
     setrt::g_create_error = "invalid configuration";
     return SET_EINVAL;

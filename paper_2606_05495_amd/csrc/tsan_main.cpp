@@ -10,7 +10,7 @@
 #include "set.h"
 
 static int run(int mode, int b, int d, int policy, int stealing, int reorder, int producers, int per_producer,
-               int dispatchers = 1, int extra_templates = 0) {
+               int dispatchers = 1, int extra_templates = 0, int steal_policy = SET_STEAL_ANY) {
   set_config cfg;
   std::memset(&cfg, 0, sizeof(cfg));
   cfg.abi_version = SET_ABI_VERSION;
@@ -23,6 +23,7 @@ static int run(int mode, int b, int d, int policy, int stealing, int reorder, in
   cfg.fake_reorder_callbacks = reorder;
   cfg.staging_capacity = 64;
   cfg.dispatch_threads = dispatchers;
+  cfg.steal_policy = steal_policy;
   set_ctx* c = nullptr;
   if (set_ctx_create(&cfg, &c) != SET_OK) {
     std::printf("create failed: %s\n", set_last_error(nullptr));
@@ -94,6 +95,8 @@ int main() {
   rc |= run(SET_MODE_SET, 6, 8, SET_SUBMIT_SKEW0, 1, 1, 3, 300, 3) << 7;
   rc |= run(SET_MODE_SET, 4, 4, SET_SUBMIT_ROUND_ROBIN, 0, 1, 2, 200, 2) << 8;
   rc |= run(SET_MODE_SET, 4, 4, SET_SUBMIT_SKEW0, 1, 1, 2, 300, 2, 5) << 9;
+  rc |= run(SET_MODE_SET, 8, 4, SET_SUBMIT_SKEW0, 1, 1, 3, 300, 8, 0, SET_STEAL_BUSY) << 10;
+  rc |= run(SET_MODE_SET, 8, 4, SET_SUBMIT_ROUND_ROBIN, 1, 1, 3, 300, 8, 0, SET_STEAL_BUSY) << 11;
   std::printf("tsan stress rc=%d\n", rc);
   return rc;
 }

@@ -50,7 +50,7 @@ class Context:
                  stealing=True, batch_size=0, callback="event_poll", submit_policy=A.SET_SUBMIT_ROUND_ROBIN,
                  spin_us=0, staging=0, mem_budget=0, device=0, seed=0, borrow_streams=True,
                  fake_fail_after=0, fake_reorder=False, dispatchers=1, input_copy_streams=0,
-                 callback_streams=0):
+                 callback_streams=0, steal_policy=0):
         self.backend = backend
         self.workers = workers
         self.slots = slots
@@ -77,6 +77,7 @@ class Context:
         cfg.dispatch_threads = dispatchers
         cfg.input_copy_streams = input_copy_streams
         cfg.callback_streams = callback_streams
+        cfg.steal_policy = steal_policy
         self.streams = []
         if backend == "hip" and borrow_streams:
             torch = _torch()

@@ -46,8 +46,9 @@ def test_strerror_and_create_errors():
 
 
 def test_callback_streams_range():
-    """callback_streams takes 0..64 and the reserved word must be 0 (checked
-    before any device is touched: the fake backend serves here)."""
+    """callback_streams takes 0..64 and steal_policy SET_STEAL_ANY or
+    SET_STEAL_BUSY (checked before any device is touched: the fake backend
+    serves here)."""
     def create(**fields):
         cfg = A.set_config()
         cfg.abi_version = A.SET_ABI_VERSION
@@ -65,7 +66,10 @@ def test_callback_streams_range():
         assert create(callback_streams=k) == A.SET_OK
     for k in (-1, 65):
         assert create(callback_streams=k) == A.SET_EINVAL
-    assert create(reserved=1) == A.SET_EINVAL
+    for p in (A.SET_STEAL_ANY, A.SET_STEAL_BUSY):
+        assert create(steal_policy=p) == A.SET_OK
+    for p in (-1, 2):
+        assert create(steal_policy=p) == A.SET_EINVAL
 
 
 def test_footprint_is_host_only():

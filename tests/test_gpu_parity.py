@@ -481,18 +481,22 @@ def test_scan_full_size_and_low32(torch_gpu):
 
 
 # ------------------------------------------------------------------ scheduling on the device
-@pytest.mark.parametrize("callback,nd,ncb", [("event_chain", 1, 0), ("event_chain", 3, 0), ("event_chain", 3, 2),
-                                             ("event_chain", 1, 4), ("same_stream", 1, 0), ("event_poll", 1, 0),
-                                             ("host_flag", 1, 0), ("event_poll", 4, 0), ("host_flag", 3, 0),
-                                             ("event_blocking", 1, 0), ("event_blocking", 4, 0)])
-def test_set_mode_callbacks_and_steals(torch_gpu, callback, nd, ncb):
+@pytest.mark.parametrize("callback,nd,ncb,sp", [("event_chain", 1, 0, 0), ("event_chain", 3, 0, 0),
+                                                ("event_chain", 3, 2, 0), ("event_chain", 1, 4, 0),
+                                                ("same_stream", 1, 0, 0), ("event_poll", 1, 0, 0),
+                                                ("host_flag", 1, 0, 0), ("event_poll", 4, 0, 0),
+                                                ("host_flag", 3, 0, 0), ("event_blocking", 1, 0, 0),
+                                                ("event_blocking", 4, 0, 0), ("event_poll", 4, 0, 1),
+                                                ("host_flag", 1, 0, 1)])
+def test_set_mode_callbacks_and_steals(torch_gpu, callback, nd, ncb, sp):
     """Skewed submission on the GPU: steals retarget jobs to thieves' slots; results stay exact
     (one dispatcher thread, or several each owning a share of the workers; event chaining on
-    one callback stream shared by the workers, on two, or on one per worker)."""
-    _say("set callbacks", callback, nd, ncb)
+    one callback stream shared by the workers, on two, or on one per worker; victims taken as
+    printed, or only busy ones)."""
+    _say("set callbacks", callback, nd, ncb, sp)
     imgs = [synth.box_image(0, j) for j in range(96)]
     ctx = Context(mode="set", workers=4, slots=4, callback=callback, submit_policy=A.SET_SUBMIT_SKEW0,
-                  dispatchers=nd, callback_streams=ncb)
+                  dispatchers=nd, callback_streams=ncb, steal_policy=sp)
     tid = ctx.define("box_hist", width=256, height=256)
     ib, ob = ctx.in_bytes(tid), ctx.out_bytes(tid)
     tin, nin = pinned(ib * 96)

@@ -194,6 +194,46 @@ def test_findjob_pops_local_then_probes_victims_in_order(thief, filled):
         assert np.all(h["canary_ok"] == 1) and np.all(h["magic"] == A.SET_OUT_MAGIC)
 
 
+@pytest.mark.parametrize("policy", ["any", "busy"])
+def test_steal_policy_idle_victim(policy):
+    """A fresh context: four workers, one permit each, all free, held by one
+    dispatcher in worker order.  One job is submitted to worker 1.  The
+    dispatcher's first permit is worker 0's; FindJob(0) finds Q_0 empty and
+    probes Q_1.  As printed (SET_STEAL_ANY) it takes the job, though worker 1
+    is idle; SET_STEAL_BUSY skips a victim holding a free permit, and worker 1
+    runs its own job."""
+    sp = A.SET_STEAL_ANY if policy == "any" else A.SET_STEAL_BUSY
+    with _fake(workers=4, slots=2, inflight=1, dispatchers=1, steal_policy=sp) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        outs = np.zeros((1, 128), np.uint8)
+        jid = ctx.submit(tid, host_out=outs[0].ctypes.data, out_bytes=68, n=1000, a=1.0, worker_hint=1)
+        ctx.drain()
+        r = [r for r in ctx.job_times() if int(r["job_id"]) == jid][0]
+        if policy == "any":
+            assert int(r["worker"]) == 0 and int(r["stolen"]) == 1 and ctx.stats().stolen == 1
+        else:
+            assert int(r["worker"]) == 1 and int(r["stolen"]) == 0 and ctx.stats().stolen == 0
+
+
+@pytest.mark.parametrize("policy", ["any", "busy"])
+def test_skewed_submission_steals_under_both_policies(policy):
+    """Everything submitted to Q_0 with eight workers and eight dispatcher
+    threads: both policies steal (worker 0 is busy), every job completes once
+    with its own header."""
+    sp = A.SET_STEAL_ANY if policy == "any" else A.SET_STEAL_BUSY
+    with _fake(workers=8, slots=4, inflight=2, dispatchers=8, steal_policy=sp,
+               submit_policy=A.SET_SUBMIT_SKEW0) as ctx:
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        arr, outs = _vec_jobs(ctx, tid, 400, 200)
+        first = ctx.submit_many(tid, arr)
+        ctx.drain(timeout_ns=int(30e9))
+        hs = _headers(outs)
+        assert np.array_equal(hs["job_id"], first + np.arange(400))
+        assert np.all(hs["canary_ok"] == 1)
+        st = ctx.stats()
+        assert st.completed == 400 and st.stolen > 0
+
+
 def test_findjob_without_stealing_leaves_other_queues():
     """With stealing off the thief's returned permit finds its own queue empty
     and takes nothing: the queued jobs wait for their own workers."""
