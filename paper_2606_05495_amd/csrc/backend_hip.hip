@@ -820,7 +820,7 @@ class HipBackend : public Backend {
         char* sb = b + L.scratch;
         sl.scan_r = ScanReduceArgs{(const int32_t*)(b + L.in), (int64_t*)sb, T, sc.hdr, JobScalars{}};
         sl.scan_r.js.n = t.max_n;
-        sl.scan_s = ScanSpineArgs{(const int64_t*)sb, (int64_t*)(sb + q8), sc};
+        sl.scan_s = ScanSpineArgs{(const int64_t*)sb, (int64_t*)(sb + q8), sc, t.max_n};
         sl.scan_d = ScanDownArgs{(const int32_t*)(b + L.in), (const int64_t*)(sb + q8), (void*)(b + L.out + 64),
                                  (t.flags & SET_TF_SCAN_LOW32) ? 1 : 0, t.max_n};
         stage((const void*)&k_scan_reduce_i32, dim3(T), &sl.scan_r);
@@ -888,6 +888,7 @@ class HipBackend : public Backend {
       case SET_PIPE_SCAN_I32_I64:
         if (js.n == 0) js.n = p.t.max_n;
         sl.scan_r.js = js;
+        sl.scan_s.n = js.n;
         sl.scan_d.n = js.n;
         break;
       case SET_PIPE_SCAN_LIB_I32_I64:
@@ -1135,9 +1136,11 @@ class HipBackend : public Backend {
     }
     hipKernelNodeParams kp = kparams(sl, 0);
     HIPCK(hipGraphExecKernelNodeSetParams(ex, cn.k[0], &kp));
-    if (p.t.pipeline == SET_PIPE_SCAN_I32_I64) {  // the downsweep carries n too
-      hipKernelNodeParams kd = kparams(sl, 2);
-      HIPCK(hipGraphExecKernelNodeSetParams(ex, cn.k[2], &kd));
+    if (p.t.pipeline == SET_PIPE_SCAN_I32_I64) {  // the spine and the downsweep carry n too
+      for (int i = 1; i <= 2; ++i) {
+        hipKernelNodeParams kd = kparams(sl, i);
+        HIPCK(hipGraphExecKernelNodeSetParams(ex, cn.k[i], &kd));
+      }
     }
     if (out_by_kernel(p.t)) {
       sl.d2h_copy = CopyArgs{sl.base + p.L.out, sl.host_out, sl.out_bytes};

@@ -27,11 +27,13 @@ __device__ inline void write_slot_hdr(DevSlotHdr* hdr, const JobScalars& js) {
   hdr->n = js.n;
 }
 
-// One thread; the caller has acquired everything the job wrote.
+// One thread; the caller has acquired everything the job wrote.  The two
+// canary tests are combined without short-circuit, so every load of the
+// header and the tail goes out at once: one memory round trip.
 __device__ inline void publish_out(const SlotConst& sc, bool extra_ok) {
   const DevSlotHdr* h = sc.hdr;
   set_out_header* o = sc.outh;
-  const bool canaries = (h->canary_head == sc.canary_head) && (*sc.tail == sc.canary_tail);
+  const bool canaries = (h->canary_head == sc.canary_head) & (*sc.tail == sc.canary_tail);
   o->job_id = h->job_id;
   o->seq = h->seq;
   o->worker = h->worker;
@@ -244,11 +246,24 @@ __global__ __launch_bounds__(kBlock) void k_hist256_u8(HistArgs a) {
   a.partials[(size_t)blockIdx.x * 256 + tid] = wh[0][tid] + wh[1][tid] + wh[2][tid] + wh[3][tid];
 }
 
-// One block: bin tid = sum over blocks in block order (integer, exact).
+// One block: bin tid = sum of the blocks' partial counts (integer, exact in
+// any order).  The loads go out 16 blocks at a time with no branch between
+// them (past the last block the index is clamped and the value dropped), so
+// one memory latency covers 16 blocks instead of one.
 __global__ __launch_bounds__(kBlock) void k_hist256_final(HistFinalArgs a) {
   const int tid = threadIdx.x;
+  const unsigned nb = a.nblocks;
   uint32_t s = 0;
-  for (unsigned b = 0; b < a.nblocks; ++b) s += a.partials[(size_t)b * 256 + tid];
+  for (unsigned b0 = 0; b0 < nb; b0 += 16) {
+    uint32_t v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const unsigned b = b0 + k < nb ? b0 + k : nb - 1;
+      v[k] = a.partials[(size_t)b * 256 + tid];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += b0 + k < nb ? v[k] : 0u;
+  }
   a.H[tid] = s;
   if (tid == 0) publish_out(a.sc, true);
 }
@@ -733,11 +748,22 @@ __global__ __launch_bounds__(kBlock) void k_saxpy_tanh_sum_f32(VecArgs a) {
 }
 
 // One block: the job's partials (vec_blocks(n) of them) in a fixed order.
+// The job's block count comes from n in the slot header.  Every thread loads
+// its kVecGridCap / kBlock possible partials beside that load (the scratch
+// holds kVecGridCap of them) and adds those below the count, in the order of
+// the one-partial-per-step loop: one memory round trip instead of two.
 __global__ __launch_bounds__(kBlock) void k_vec_final(VecFinalArgs a) {
   __shared__ float s4f[4];
+  static_assert(kVecGridCap % kBlock == 0, "whole partials per thread");
+  constexpr int PER = kVecGridCap / kBlock;
+  float v[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) v[i] = a.partials[threadIdx.x + i * kBlock];
   const unsigned G = vec_blocks(a.sc.hdr->n);
   float s = 0.f;
-  for (unsigned k = threadIdx.x; k < G; k += kBlock) s += a.partials[k];
+#pragma unroll
+  for (int i = 0; i < PER; ++i)
+    if (threadIdx.x + i * kBlock < G) s += v[i];
   s = block_sum_f32(s, s4f);
   if (threadIdx.x == 0) {
     *a.out_sum = s;
@@ -926,15 +952,26 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce_i32(ScanReduceArgs a) {
   if (threadIdx.x == 0) a.tile_sum[t] = total;
 }
 
+// A thread's 8 tile sums are four 16-byte loads with no branch around them:
+// past the last tile it re-reads the last 8-sum group (inside the scratch,
+// which is padded to 256 bytes) and drops what lies beyond.
 __global__ __launch_bounds__(kBlock) void k_scan_spine_i64(ScanSpineArgs a) {
   __shared__ int64_t s_wave[4];
-  const unsigned T = scan_tiles(a.sc.hdr->n);
+  const unsigned T = scan_tiles(a.n);
+  const unsigned last = (T - 1) & ~(unsigned)(kScanItems - 1);
   int64_t carry = 0;
   for (unsigned base = 0; base < T; base += kScanTile) {
     int64_t v[kScanItems];
     const unsigned i0 = base + threadIdx.x * kScanItems;
+    const longlong2* g = reinterpret_cast<const longlong2*>(a.tile_sum + (i0 < last ? i0 : last));
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) v[k] = (i0 + k < T) ? a.tile_sum[i0 + k] : 0;
+    for (int q = 0; q < kScanItems / 2; ++q) {
+      const longlong2 t = g[q];
+      v[2 * q] = t.x;
+      v[2 * q + 1] = t.y;
+    }
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) v[k] = (i0 + k < T) ? v[k] : 0;
     int64_t s = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) s += v[k];

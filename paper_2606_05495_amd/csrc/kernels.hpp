@@ -111,6 +111,7 @@ struct ScanSpineArgs {
   const int64_t* tile_sum;
   int64_t* tile_excl;  // [tiles] exclusive prefix of tile sums
   SlotConst sc;
+  uint64_t n;          // the job's length, rebound per job like the downsweep's
 };
 // The downsweep carries the job's n in its own argument block (rebound with
 // the first kernel's), so its data loads need no dependent load of the slot
