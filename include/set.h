@@ -474,6 +474,17 @@ int set_get_job_times(set_ctx *c, set_job_times *out, uint64_t max, uint64_t *co
 #define SET_STAGE_OUTPUT_COPY (-2)
 int set_time_stage(set_ctx *c, int template_id, int stage, int worker, int reps, double *avg_us);
 
+/* Measurement helper: the bandwidth reference the stage kernels are held to.
+ * A plain device copy kernel (one 16-byte word per thread, every word in
+ * flight at once) moving `bytes` in all (half read, half written) is launched
+ * `reps` times back to back on a library-owned stream between two HIP events;
+ * launch r copies slice r' of two buffers of about 512 MiB each (r' strides
+ * through the slices), so it reads and writes HBM.  *avg_us receives the mean
+ * duration per launch.  The buffers are allocated for the call and freed
+ * after it.  bytes: 32 .. 2^30; reps >= 1.  SET_EUNSUPPORTED on the fake
+ * backend. */
+int set_time_device_copy(set_ctx *c, uint64_t bytes, int reps, double *avg_us);
+
 /* Bucketed persistent batching of vector jobs (template of pipeline
  * SET_PIPE_SAXPY_BATCH_F32): jobs are grouped by size bucket floor(log2 n),
  * each bucket in input order into batches of at most batch_max jobs and

@@ -211,7 +211,7 @@ set_completion_fn = ctypes.CFUNCTYPE(None, ctypes.c_uint64, ctypes.c_int, ctypes
 EXPORTS = [
     "set_ctx_create", "set_ctx_destroy", "set_template_footprint", "set_template_define", "set_submit",
     "set_submit_many", "set_set_completion_cb", "set_drain", "set_get_stats", "set_reset_stats",
-    "set_get_job_times", "set_time_stage", "set_stage_info", "set_last_error", "set_strerror",
+    "set_get_job_times", "set_time_stage", "set_time_device_copy", "set_stage_info", "set_last_error", "set_strerror",
     "set_run_vector_jobs", "set_serve", "set_job_io_bytes", "set_run_vector_jobs_noalloc",
 ]
 SET_NOALLOC_MAX_JOBS = 16384
@@ -246,6 +246,7 @@ def load():
         "set_reset_stats": (I, [P]),
         "set_get_job_times": (I, [P, P, U64, ctypes.POINTER(U64)]),
         "set_time_stage": (I, [P, I, I, I, I, ctypes.POINTER(ctypes.c_double)]),
+        "set_time_device_copy": (I, [P, U64, I, ctypes.POINTER(ctypes.c_double)]),
         "set_stage_info": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(U64), I, ctypes.c_char_p, I]),
         "set_job_io_bytes": (I, [P, I, U64, ctypes.POINTER(U64), ctypes.POINTER(U64)]),
         "set_run_vector_jobs": (I, [P, I, P, U64, P, ctypes.POINTER(set_vec_tuning), ctypes.POINTER(U64)]),
@@ -339,6 +340,12 @@ def set_get_job_times(ctx, max_records: int = 1 << 22) -> np.ndarray:
     n = ctypes.c_uint64()
     check(load().set_get_job_times(ctx, out.ctypes.data, max_records, ctypes.byref(n)), ctx)
     return out[:n.value]
+
+
+def set_time_device_copy(ctx, nbytes: int, reps: int) -> float:
+    us = ctypes.c_double()
+    check(load().set_time_device_copy(ctx, nbytes, reps, ctypes.byref(us)), ctx)
+    return us.value
 
 
 def set_time_stage(ctx, template_id: int, stage: int, worker: int, reps: int) -> float:

@@ -124,6 +124,10 @@ class FakeBackend : public Backend {
     *avg_us = 0.0;
     return SET_OK;
   }
+  int time_device_copy(uint64_t, int, double*, std::string* err) override {
+    if (err) *err = "the fake backend has no device";
+    return SET_EUNSUPPORTED;
+  }
 
   void shutdown() override {
     if (stop_.exchange(true)) return;

@@ -490,6 +490,44 @@ class HipBackend : public Backend {
     return SET_OK;
   }
 
+  int time_device_copy(uint64_t bytes, int reps, double* avg_us, std::string* err) override {
+    ensure_dev();
+    const uint64_t half = (bytes / 2 + 15) / 16 * 16, nvec = half / 16;
+    const uint64_t k = std::max<uint64_t>(2, (512ull << 20) / half);  // slices per buffer
+    void* buf = nullptr;
+    HIPCK(hipMalloc(&buf, 2 * k * half));
+    char* a = static_cast<char*>(buf);
+    char* b = a + k * half;
+    const unsigned grid = (unsigned)((nvec + kBlock - 1) / kBlock);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto once = [&](uint64_t r) {
+      const uint64_t i = (r * 7 + 3) % k;  // stride through the slices so neighbours are not reused
+      RefCopyArgs ra{a + i * half, b + i * half, nvec};
+      void* argv[1] = {&ra};
+      return hipLaunchKernel((const void*)&k_ref_copy, dim3(grid), dim3(kBlock), argv, 0, define_stream_);
+    };
+    hipError_t e = hipSuccess;  // the contents do not matter to a copy's timing
+    for (uint64_t r = 0; e == hipSuccess && r < std::min<uint64_t>(k, 16); ++r) e = once(r + 1000);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, define_stream_);
+    for (int r = 0; e == hipSuccess && r < reps; ++r) e = once((uint64_t)r);
+    if (e == hipSuccess) e = hipEventRecord(e1, define_stream_);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(define_stream_);
+    (void)hipFree(buf);
+    if (e != hipSuccess) {
+      if (err) *err = std::string("device copy: ") + hipGetErrorString(e);
+      return SET_EDEVICE;
+    }
+    *avg_us = (double)ms * 1000.0 / reps;
+    return SET_OK;
+  }
+
   int time_stage(int tmpl, int stage, int worker, int reps, double* avg_us, std::string* err) override {
     ensure_dev();
     Pipe& p = *pipes_[tmpl];

@@ -500,6 +500,7 @@ void publish(const SlotConst& sc) {
 
 void k_copy_in(CopyArgs a) { std::memcpy(a.dst, a.src, a.bytes); }
 void k_copy_out(CopyArgs a) { std::memcpy(a.dst, a.src, a.bytes); }
+void k_ref_copy(RefCopyArgs a) { std::memcpy(a.dst, a.src, a.nvec * 16); }
 void k_done_flag(DoneFlagArgs a) { __atomic_store_n(a.word, a.hdr->seq, __ATOMIC_RELEASE); }
 void k_poison(PoisonArgs a) {
   std::memset(a.p, 0xFF, a.nvec * 16);
@@ -565,6 +566,7 @@ struct Register {
     using hipstub::register_kernel;
     register_kernel(&k_copy_in);
     register_kernel(&k_copy_out);
+    register_kernel(&k_ref_copy);
     register_kernel(&k_done_flag);
     register_kernel(&k_poison);
     register_kernel(&k_stress_delay);

@@ -155,6 +155,8 @@ class Backend {
   virtual int run_graph(JobRec* job, int stream_index, std::string* err) = 0;
   virtual int run_batch(JobRec** jobs, int count, std::string* err) = 0;
   virtual int time_stage(int tmpl, int stage, int worker, int reps, double* avg_us, std::string* err) = 0;
+  // A plain device copy of `bytes` (half read, half written), cold; see set_time_device_copy.
+  virtual int time_device_copy(uint64_t bytes, int reps, double* avg_us, std::string* err) = 0;
   virtual uint64_t host_ns_sync() const { return 0; }
   // Pinned host staging owned by the library (descriptor tables, results).
   virtual void* alloc_host(uint64_t bytes) = 0;

@@ -152,6 +152,10 @@ __device__ __forceinline__ void copy_bytes(const CopyArgs& a) {
   if (t < a.bytes) reinterpret_cast<uint8_t*>(a.dst)[t] = reinterpret_cast<const uint8_t*>(a.src)[t];
 }
 __global__ __launch_bounds__(kBlock) void k_copy_in(CopyArgs a) { copy_bytes(a); }
+__global__ __launch_bounds__(kBlock) void k_ref_copy(RefCopyArgs a) {
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < a.nvec) static_cast<uint4*>(a.dst)[i] = static_cast<const uint4*>(a.src)[i];
+}
 __global__ __launch_bounds__(kBlock) void k_copy_out(CopyArgs a) { copy_bytes(a); }
 
 // ------------------------------------------------------------------ completion word

@@ -132,6 +132,13 @@ struct CopyArgs {
   uint64_t bytes;
 };
 __global__ void k_copy_in(CopyArgs a);   // host-to-device
+// Bandwidth reference: word i of `nvec` 16-byte words copied by thread i.
+struct RefCopyArgs {
+  const void* src;
+  void* dst;
+  uint64_t nvec;
+};
+__global__ void k_ref_copy(RefCopyArgs a);
 __global__ void k_copy_out(CopyArgs a);  // device-to-host
 
 // Completion word: one thread stores the job's binding sequence number (from

@@ -1435,6 +1435,16 @@ int set_time_stage(set_ctx* c, int template_id, int stage, int worker, int reps,
   return SET_OK;
 }
 
+int set_time_device_copy(set_ctx* c, uint64_t bytes, int reps, double* avg_us) {
+  if (!c || !avg_us || reps < 1 || bytes < 32 || bytes > (1ull << 30)) return SET_EINVAL;
+  int st = c->impl.check_sticky();
+  if (st != SET_OK) return st;
+  std::string err;
+  int rc = c->impl.be->time_device_copy(bytes, reps, avg_us, &err);
+  if (rc != SET_OK) return c->impl.fail(rc, "time_device_copy: " + err);
+  return SET_OK;
+}
+
 int set_job_io_bytes(set_ctx* c, int template_id, uint64_t n, uint64_t* in_bytes, uint64_t* out_bytes) {
   if (!c) return SET_EINVAL;
   if (!c->impl.valid_template(template_id)) return SET_EINVAL;

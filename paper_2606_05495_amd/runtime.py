@@ -175,6 +175,10 @@ class Context:
     def time_stage(self, tid, stage, worker=0, reps=100):
         return A.set_time_stage(self.h, tid, stage, worker, reps)
 
+    def time_device_copy(self, nbytes, reps=100):
+        """Mean time of a plain device copy kernel moving nbytes (half read, half written), cold."""
+        return A.set_time_device_copy(self.h, nbytes, reps)
+
     def stage_info(self, tid):
         return A.set_stage_info(self.h, tid)
 

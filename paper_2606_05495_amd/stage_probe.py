@@ -11,10 +11,12 @@ timed with HIP events around `reps` back-to-back launches, two ways:
 * warm: every launch on one slot, whose operands stay cached when they fit
   (the figure the first measurements reported).
 
-Beside each stage: a plain device-to-device copy moving the same bytes (half
-read, half written), cold (rotating over 1 GiB) and warm (one buffer pair):
-the bandwidth the memory system gives at that transfer size.  A last plain
-copy of known size calibrates the byte counters of counter runs.
+Beside each stage: a plain device copy moving the same bytes (half read, half
+written), cold (rotating over 1 GiB): the library's reference copy kernel (one
+16-byte word per thread), the bandwidth the memory system gives at that
+transfer size; and the runtime's device-to-device copy (hipMemcpy's blit
+kernel), cold and warm (one buffer pair).  A last plain copy of known size
+calibrates the byte counters of counter runs.
 
     python -m paper_2606_05495_amd.stage_probe --side 1024 --reps 100
 """
@@ -142,9 +144,10 @@ def main():
         if args.cold_only:
             continue
         warm = ctx.time_stage(tid, i, 0, args.reps)
-        half = max(16, int(nbytes) // 2)
+        half = max(16, (int(nbytes) // 2 + 15) // 16 * 16)
         out[name].update({"warm_us": round(warm, 3), "warm_GBps": round(nbytes / warm / 1e3, 1),
-                          "copy_cold_us": round(cold_copy_us(torch, half, args.reps), 3),
+                          "copy_cold_us": round(ctx.time_device_copy(2 * half, args.reps), 3),
+                          "runtime_copy_cold_us": round(cold_copy_us(torch, half, args.reps), 3),
                           "copy_warm_us": round(warm_copy_us(torch, half, args.reps), 3)})
     ctx.close()
     # calibration: a plain device-to-device copy of known size

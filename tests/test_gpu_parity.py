@@ -623,6 +623,16 @@ def test_vector_batching_block_sizes(torch_gpu, vec_pools, block):
     ctx.close()
 
 
+def test_device_copy_reference(torch_gpu):
+    """The bandwidth reference of the stage tables: a cold copy of 8 MiB takes a
+    plausible time (within 1 to 1000 us, and no faster than 8 TB/s allows)."""
+    _say("device copy reference")
+    ctx = Context(mode="set", workers=2, slots=2)
+    us = ctx.time_device_copy(8 << 20, 50)
+    assert 8 * 2 ** 20 / (us * 1e-6) <= 8.0e12 and 1.0 <= us <= 1000.0, us
+    ctx.close()
+
+
 @pytest.mark.parametrize("mode", ["set", "sync", "batch", "queue"])
 def test_empty_inputs_on_gpu(torch_gpu, vec_pools, mode):
     """Empty submissions and empty vector batches launch nothing and count

@@ -657,6 +657,23 @@ def test_stress_template_options():
         assert ctx.stats().stolen > 0
 
 
+def test_device_copy_reference_needs_a_device():
+    """set_time_device_copy: the fake backend has no device (SET_EUNSUPPORTED,
+    the context stays usable); sizes outside 32 .. 2^30 bytes are refused."""
+    with _fake(workers=2, slots=2) as ctx:
+        with pytest.raises(A.SetError) as e:
+            ctx.time_device_copy(1 << 20, 10)
+        assert e.value.code == A.SET_EUNSUPPORTED
+        for nbytes, reps in ((16, 10), ((1 << 30) + 1, 10), (1 << 20, 0)):
+            with pytest.raises(A.SetError):
+                ctx.time_device_copy(nbytes, reps)
+        tid = ctx.define("saxpy_tanh_sum", max_n=1 << 20, pool_ptrs=DUMMY_POOL)
+        arr, outs = _vec_jobs(ctx, tid, 4, 10)
+        ctx.submit_many(tid, arr)
+        ctx.drain(timeout_ns=int(5e9))
+        assert ctx.stats().completed == 4
+
+
 def test_empty_inputs():
     """Empty submissions and empty vector batches are no-ops: nothing is
     counted, drain returns at once, and the context stays usable."""
