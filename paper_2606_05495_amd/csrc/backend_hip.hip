@@ -494,8 +494,17 @@ class HipBackend : public Backend {
     ensure_dev();
     const uint64_t half = (bytes / 2 + 15) / 16 * 16, nvec = half / 16;
     const uint64_t k = std::max<uint64_t>(2, (512ull << 20) / half);  // slices per buffer
+    // a stream of its own: a template capture on the definition stream must
+    // not record these launches
+    hipStream_t st = nullptr;
+    HIPCK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     void* buf = nullptr;
-    HIPCK(hipMalloc(&buf, 2 * k * half));
+    const hipError_t ea = hipMalloc(&buf, 2 * k * half);
+    if (ea != hipSuccess) {
+      (void)hipStreamDestroy(st);
+      if (err) *err = std::string("hipMalloc: ") + hipGetErrorString(ea);
+      return SET_ENOMEM;
+    }
     char* a = static_cast<char*>(buf);
     char* b = a + k * half;
     const unsigned grid = (unsigned)((nvec + kBlock - 1) / kBlock);
@@ -504,22 +513,23 @@ class HipBackend : public Backend {
       const uint64_t i = (r * 7 + 3) % k;  // stride through the slices so neighbours are not reused
       RefCopyArgs ra{a + i * half, b + i * half, nvec};
       void* argv[1] = {&ra};
-      return hipLaunchKernel((const void*)&k_ref_copy, dim3(grid), dim3(kBlock), argv, 0, define_stream_);
+      return hipLaunchKernel((const void*)&k_ref_copy, dim3(grid), dim3(kBlock), argv, 0, st);
     };
     hipError_t e = hipSuccess;  // the contents do not matter to a copy's timing
     for (uint64_t r = 0; e == hipSuccess && r < std::min<uint64_t>(k, 16); ++r) e = once(r + 1000);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    if (e == hipSuccess) e = hipEventRecord(e0, define_stream_);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
     for (int r = 0; e == hipSuccess && r < reps; ++r) e = once((uint64_t)r);
-    if (e == hipSuccess) e = hipEventRecord(e1, define_stream_);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    (void)hipStreamSynchronize(define_stream_);
+    (void)hipStreamSynchronize(st);
     (void)hipFree(buf);
+    (void)hipStreamDestroy(st);
     if (e != hipSuccess) {
       if (err) *err = std::string("device copy: ") + hipGetErrorString(e);
       return SET_EDEVICE;
