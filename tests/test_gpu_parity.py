@@ -968,6 +968,42 @@ def test_host_flag_completion_all_pipelines(torch_gpu, vec_pools, capture):
         assert np.array_equal(r, oracle.scan(v))
 
 
+@pytest.mark.parametrize("copy", ["kernels", "async_in", "nodes"])
+def test_captured_thermal_and_vector_batch_templates(torch_gpu, vec_pools, copy):
+    """Stream-captured templates of the two pipelines the capture tests above
+    leave out: the thermal grid (a chain of 5 step kernels) matches the explicit
+    template bit for bit and the oracle within its bound; batched vector jobs
+    through a captured template match the explicit one bit for bit."""
+    _say("captured thermal / vector batch", copy)
+    grids = [synth.hotspot_input(4, k, 97, 132) for k in range(6)]
+    a = _run_hotspot("set", grids, 5, copy=copy, flags=A.SET_TF_CAPTURE)
+    b = _run_hotspot("set", grids, 5, copy=copy)
+    for (t0, p), x, y in zip(grids, a, b):
+        assert np.array_equal(x, y)
+        ref = oracle.hotspot(t0, p, 5)
+        assert np.max(np.abs(x - ref)) <= oracle.hotspot_tolerance(ref, 5)
+    if copy == "nodes":
+        return
+    x, y, xd, yd = vec_pools
+    js = synth.vec_jobs(8, 150, pool_len=len(x))
+    jobs = np.zeros(150, dtype=A.VEC_JOB_DTYPE)
+    for f in ("n", "a", "x_off", "y_off"):
+        jobs[f] = js[f]
+    res = []
+    for flags in (A.SET_TF_CAPTURE, 0):
+        ctx = Context(mode="set", workers=4, slots=2)
+        tid = ctx.define("saxpy_batch", max_n=1 << 22, x_pool=xd, y_pool=yd, batch_max=16, tiles_max=1024,
+                         flags=flags, copy=copy)
+        r, _ = ctx.run_vector_jobs(tid, jobs)
+        res.append(r)
+        ctx.close()
+    assert np.array_equal(res[0].view(np.uint32), res[1].view(np.uint32))
+    for i in range(0, 150, 25):
+        n, xo, yo = int(jobs["n"][i]), int(jobs["x_off"][i]), int(jobs["y_off"][i])
+        S, E = oracle.saxpy_tanh_sum(x[xo:xo + n], y[yo:yo + n], jobs["a"][i])
+        assert abs(float(res[0][i]) - S) <= oracle.vec_tolerance(S, E)
+
+
 # ------------------------------------------------------------------ input copied ahead of the graph
 @pytest.mark.parametrize("mode", ["sync", "graph", "batch", "queue", "set"])
 def test_async_input_copy_all_modes(torch_gpu, vec_pools, mode):
@@ -1132,10 +1168,10 @@ def test_library_scan_stage_timing(torch_gpu):
 
 
 # ------------------------------------------------------------------ thermal grid (iterative stencil)
-def _run_hotspot(mode, grids, steps, workers=4, slots=4, copy="kernels", **kw):
+def _run_hotspot(mode, grids, steps, workers=4, slots=4, copy="kernels", flags=0, **kw):
     h, w = grids[0][0].shape
     ctx = Context(mode=mode, workers=workers, slots=slots, **kw)
-    tid = ctx.define("hotspot", width=w, height=h, max_n=steps, copy=copy)
+    tid = ctx.define("hotspot", width=w, height=h, max_n=steps, copy=copy, flags=flags)
     ib, ob = ctx.in_bytes(tid), ctx.out_bytes(tid)
     assert ib == 8 * h * w and ob == 64 + 4 * h * w
     istride, ostride = _up64(ib), _up64(ob)
