@@ -1201,14 +1201,19 @@ def main_with(args, raw):
                 key = cp if cs == 0 else "%s+%d_copy_streams" % (cp, cs)
                 log("%s baseline, copy %s: %d jobs x %d steps" % (mode, key, args.jobs, args.baseline_steps))
                 tout.zero_()
-                c2, _, dt2, st2, _ = run_mode(mode, args, args.jobs, args.baseline_steps, 1, tin, tout, pool, torch,
-                                              copy=cp, copy_streams=cs)
+                c2, _, dt2, st2, (t2, _) = run_mode(mode, args, args.jobs, args.baseline_steps, 1, tin, tout, pool,
+                                                    torch, copy=cp, copy_streams=cs)
                 c2.close()
                 ok2, bad2 = verify(tout, args.jobs, imgs, refs)
+                lat2 = (t2["t_done"] - t2["t_launch"]) / 1e3  # launch (of the job, or of its batch) to completion
                 per[key] = {"jobs_per_s": round(args.jobs * args.baseline_steps / dt2, 1), "verified": ok2,
-                            "wrong_jobs": int(bad2), "host_sync_ms": round(st2.host_ns_sync / 1e6, 2)}
+                            "wrong_jobs": int(bad2), "host_sync_ms": round(st2.host_ns_sync / 1e6, 2),
+                            "launch_to_done_p50_us": round(nearest_rank(lat2, 50), 1),
+                            "launch_to_done_p99_us": round(nearest_rank(lat2, 99), 1)}
             best = max(per, key=lambda c: per[c]["jobs_per_s"])
             extra[mode] = {"jobs_per_s": per[best]["jobs_per_s"], "copy": best,
+                           "launch_to_done_p50_us": per[best]["launch_to_done_p50_us"],
+                           "launch_to_done_p99_us": per[best]["launch_to_done_p99_us"],
                            "verified": all(v["verified"] for v in per.values()), "by_copy": per}
 
     sections = {}
