@@ -289,8 +289,10 @@ def box_section(args, torch, reps=20):
     """The 64-job box/histogram workload: 256x256 uint8 images (seeded by job
     id) -> 3x3 zero-padded box sum -> floor(/9) -> 256-bin histogram, as the
     plain method runs it (synchronous launches, stream = job mod 4) and through
-    SET (4 workers x 4 slots, 4 dispatcher threads); `reps` timed passes of the
-    64 jobs each, every histogram of every pass bit-exact against the oracle."""
+    SET (4 workers x 4 slots, 4 dispatcher threads), beside the batch-synchronised
+    graph baseline (batch 8 over 4 workers x 2 slots) and the queue model; `reps`
+    timed passes of the 64 jobs each, every histogram of every pass bit-exact
+    against the oracle."""
     from paper_2606_05495_amd import synth
     from paper_2606_05495_amd.runtime import Context, pinned
     import oracle
@@ -302,8 +304,10 @@ def box_section(args, torch, reps=20):
     out = {}
     # SET as for the other short-job workloads: completion words, four
     # dispatcher threads (a job's graph launch costs ~14 us of host time)
-    for mode, slots, cb, nd in (("sync", 1, "event_poll", 1), ("set", 4, "host_flag", 4)):
-        ctx = Context(mode=mode, workers=4, slots=slots, callback=cb, dispatchers=nd)
+    for mode, slots, cb, nd in (("sync", 1, "event_poll", 1), ("set", 4, "host_flag", 4), ("batch", 2, "event_poll", 1),
+                                ("queue", 1, "event_poll", 1)):
+        ctx = Context(mode=mode, workers=4, slots=slots, callback=cb, dispatchers=nd,
+                      batch_size=8 if mode == "batch" else 0)
         tid = ctx.define("box_hist", width=256, height=256, copy="kernels")
         ob = ctx.out_bytes(tid)
         tout, nout = pinned(J * 1152)
@@ -331,9 +335,11 @@ def box_section(args, torch, reps=20):
         out[mode] = {"jobs_per_s": round(J / dt, 1), "passes": reps, "verified_bit_exact": bool(ok),
                      "jobs_per_s_min": round(J / max(each), 1), "jobs_per_s_max": round(J / min(each), 1)}
     out["set_speedup_vs_sync"] = round(out["set"]["jobs_per_s"] / out["sync"]["jobs_per_s"], 3)
+    out["set_speedup_vs_batch_sync"] = round(out["set"]["jobs_per_s"] / out["batch"]["jobs_per_s"], 3)
+    out["set_speedup_vs_queue"] = round(out["set"]["jobs_per_s"] / out["queue"]["jobs_per_s"], 3)
     if not args.no_cpu:
         out["cpu_oracle"] = oracle_pool_rate(oracle.box_hist, imgs, "all 64 jobs (C oracle)")
-    out["verified"] = out["sync"]["verified_bit_exact"] and out["set"]["verified_bit_exact"]
+    out["verified"] = all(out[m]["verified_bit_exact"] for m in ("sync", "set", "batch", "queue"))
     return out
 
 
@@ -1221,7 +1227,8 @@ def main_with(args, raw):
         log("box/histogram jobs: 64")
         sections["box_hist_64"] = dict(box_section(args, torch), workload=(
             "64 jobs: 256x256 uint8 -> 3x3 box sum (zero-padded) -> floor(/9) -> 256-bin histogram, bit-exact; "
-            "the plain method (sync launches, 4 streams) and SET (4 workers x 4 slots)"))
+            "the plain method (sync launches, 4 streams), batch-sync (batch 8), the queue model and SET "
+            "(4 workers x 4 slots)"))
         va = section_args(raw, "vectors")
         log("uneven vector jobs: %d" % va.vjobs)
         vout = vectors_section(va, torch)
