@@ -1241,7 +1241,8 @@ def main_with(args, raw):
         log("scan jobs: %d" % sa.scan_jobs)
         scpu = {}
         sruns = scan_section(sa, torch, [("set", 8, True, sa.copy), ("set", 8, False, sa.copy),
-                                         ("batch", 8, False, "kernels"), ("batch", 8, False, "async_in")], scpu)
+                                         ("batch", 8, False, "kernels"), ("batch", 8, False, "async_in"),
+                                         ("queue", 8, False, "async_in")], scpu)
         sbest = max(r["jobs_per_s"] for r in sruns if r["mode"] == "set")
         sections["scan_jobs"] = dict(scan_summary(sruns), runs=sruns, cpu_oracle=scpu or None,
                                      pipeline_roofline={
