@@ -808,7 +808,10 @@ class HipBackend : public Backend {
             {(const void*)&k_sobel_thresh_win_f32<2, false>, (const void*)&k_sobel_thresh_win_f32<2, true>},
             {(const void*)&k_sobel_thresh_win_f32<4, false>, (const void*)&k_sobel_thresh_win_f32<4, true>}};
         const void* gk = win ? gks[gr == 2 ? 0 : 1][full ? 1 : 0] : (const void*)&k_gauss5_f32;
-        stage(gk, to_dim3(gauss_grid(h, w)), &sl.gauss);
+        if (gauss_band_path(w))
+          stage((const void*)&k_gauss5_band_f32, to_dim3(gauss_grid(h, w)), &sl.gauss, (unsigned)kBandCols / 4);
+        else
+          stage(gk, to_dim3(gauss_grid(h, w)), &sl.gauss);
         const void* sk = win ? sks[sr == 2 ? 0 : 1][full ? 1 : 0] : (const void*)&k_sobel_thresh_f32;
         stage(sk, to_dim3(sg), &sl.sobel);
         stage((const void*)&k_sobel_final, dim3(1), &sl.sobelf);

@@ -97,6 +97,13 @@ __device__ inline void store_nt(uint32_t* p, uint32_t x, uint32_t y, uint32_t z,
   __builtin_nontemporal_store(v4u_t{x, y, z, w}, reinterpret_cast<v4u_t*>(p));
 }
 __device__ inline void store_nt(uint32_t* p, uint32_t x) { __builtin_nontemporal_store(x, p); }
+// Global-memory (address space 1) views of an integer address.  A row base
+// held in scalar registers as an integer, plus a lane's 32-bit byte offset,
+// then loads and stores as global_load/store with a scalar base, where the
+// compiler would otherwise form one 64-bit vector address per row.
+typedef v4f_t __attribute__((address_space(1))) GlobalV4f;
+typedef const float __attribute__((address_space(1))) GlobalF32;
+__device__ inline v4f_t make_v4f(float x, float y, float z, float w) { return v4f_t{x, y, z, w}; }
 
 // The hardware square root (v_sqrt_f32, within 1 ulp for normal inputs)
 // instead of the correctly rounded library sequence, which costs about 15
@@ -520,6 +527,120 @@ __global__ __launch_bounds__(kBlock) void k_gauss5_win_f32(GaussArgs a) {
                o[3]);
   }
 }
+// Row bands, for widths that are a multiple of kBandCols: a block of
+// kBandCols / 256 waves lies side by side across kGaussBandRows whole rows,
+// each wave 256 columns as in the window kernel.  A wave's halo columns are
+// its neighbours' outermost columns, whose vertical-pass results the
+// neighbours already hold: each wave's lane 0 publishes its first two columns
+// and lane 63 its last two in LDS, and after one barrier lanes 0 and 63 read
+// the neighbouring waves' pairs.  Only the block's outer edges, where they lie
+// inside the image, load their two halo columns (the first wave on the left,
+// the last on the right); at the image border the clamped columns are the
+// border column itself, whose vertical result the border lane already holds.
+// Against the window kernel, which loads both halo pairs in every wave, a wave
+// issues R + 4 vector loads instead of 3 (R + 4) and skips two columns'
+// vertical passes; the barrier makes a wave wait for its block's slowest
+// load, which costs more than that saves on images of a million pixels or
+// fewer, where each SIMD holds one wave.  The arithmetic is the window
+// kernel's, operation for operation.
+__global__ __launch_bounds__(kBandCols / 4) void k_gauss5_band_f32(GaussArgs a) {
+  constexpr int R = kGaussBandRows, nw = kBandCols / kWinCols;
+  unsigned bx, band;
+  xcd_tile(bx, band);  // grid (column blocks, bands)
+  if (bx == 0 && band == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
+  // lo[k + 1][r]: wave k's two first columns; hi[k + 1][r]: its two last.
+  // hi[0] holds the pair left of the block, lo[nw + 1] the pair right of it.
+  __shared__ float2 lo[nw + 2][R], hi[nw + 2][R];
+  const int w = a.w, h = a.h, hm = h - 1;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int y0 = (int)band * R;
+  const unsigned xb = bx * (unsigned)kBandCols;  // first column of the block
+  const unsigned x = xb + (unsigned)wave * kWinCols + 4u * (unsigned)lane;
+  const uint32_t pitch = (uint32_t)w * 4u;  // row bytes
+  const bool left_out = wave == 0 && bx > 0;                    // halo left of the block inside the image
+  const bool right_out = wave == nw - 1 && bx + 1 < gridDim.x;  // halo right of the block inside the image
+  auto row_base = [&](const float* img, int r) {
+    uint64_t row = reinterpret_cast<uint64_t>(img) + (uint64_t)(uint32_t)clampi(y0 + r - 2, 0, hm) * pitch;
+    asm("" : "+s"(row));  // keeps the row base scalar: scalar base + 32-bit lane offset per load
+    return row;
+  };
+  float e0[R + 4], e1[R + 4];
+  if (left_out || right_out) {  // wave-uniform (same address in every lane), issued before the window rows
+    const unsigned hc = (left_out ? xb - 2u : xb + (unsigned)kBandCols) * 4u;
+#pragma unroll
+    for (int r = 0; r < R + 4; ++r) {
+      const uint64_t row = row_base(a.in, r);
+      e0[r] = *reinterpret_cast<const GlobalF32*>(row + hc);
+      e1[r] = *reinterpret_cast<const GlobalF32*>(row + hc + 4u);
+    }
+  }
+  float4 v[R + 4];
+#pragma unroll
+  for (int r = 0; r < R + 4; ++r) {
+    const v4f_t t = *reinterpret_cast<const GlobalV4f*>(row_base(a.in, r) + x * 4u);
+    v[r] = make_float4(t.x, t.y, t.z, t.w);
+  }
+  const float g0 = a.g0, g1 = a.g1, g2 = a.g2;
+  auto vert = [&](float t0, float t1, float t2, float t3, float t4) {
+    float acc = g0 * t0;
+    acc = fmaf(g1, t1, acc);
+    acc = fmaf(g2, t2, acc);
+    acc = fmaf(g1, t3, acc);
+    return fmaf(g0, t4, acc);
+  };
+  float4 c[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    c[r] = make_float4(vert(v[r].x, v[r + 1].x, v[r + 2].x, v[r + 3].x, v[r + 4].x),
+                       vert(v[r].y, v[r + 1].y, v[r + 2].y, v[r + 3].y, v[r + 4].y),
+                       vert(v[r].z, v[r + 1].z, v[r + 2].z, v[r + 3].z, v[r + 4].z),
+                       vert(v[r].w, v[r + 1].w, v[r + 2].w, v[r + 3].w, v[r + 4].w));
+  if (left_out || right_out) {
+    // the outer pair, vertical pass, published by the lane that borders it
+    float2* dst = left_out ? &hi[0][0] : &lo[nw + 1][0];
+    if (lane == (left_out ? 0 : 63))
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        dst[r] = make_float2(vert(e0[r], e0[r + 1], e0[r + 2], e0[r + 3], e0[r + 4]),
+                             vert(e1[r], e1[r + 1], e1[r + 2], e1[r + 3], e1[r + 4]));
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) lo[wave + 1][r] = make_float2(c[r].x, c[r].y);
+    if (wave == 0 && bx == 0)  // image border: the clamped columns repeat column 0
+#pragma unroll
+      for (int r = 0; r < R; ++r) hi[0][r] = make_float2(c[r].x, c[r].x);
+  } else if (lane == 63) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) hi[wave + 1][r] = make_float2(c[r].z, c[r].w);
+    if (wave == nw - 1 && bx + 1 == gridDim.x)  // image border: column w - 1 repeated
+#pragma unroll
+      for (int r = 0; r < R; ++r) lo[nw + 1][r] = make_float2(c[r].w, c[r].w);
+  }
+  __syncthreads();
+  // lane 0 takes the left neighbour's last pair, every other lane the right
+  // neighbour's first pair (only lane 63 uses it)
+  const float2* halo = lane == 0 ? &hi[wave][0] : &lo[wave + 2][0];
+  float2 f[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) f[r] = halo[r];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float cc[8] = {from_left(c[r].z, f[r].x), from_left(c[r].w, f[r].y), c[r].x, c[r].y,
+                         c[r].z, c[r].w, from_right(c[r].x, f[r].x), from_right(c[r].y, f[r].y)};
+    float o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = vert(cc[j], cc[j + 1], cc[j + 2], cc[j + 3], cc[j + 4]);
+    const int y = y0 + r;
+    if (y < h) {
+      uint64_t orow = reinterpret_cast<uint64_t>(a.out) + (uint64_t)(uint32_t)y * pitch;
+      asm("" : "+s"(orow));
+      __builtin_nontemporal_store(make_v4f(o[0], o[1], o[2], o[3]), reinterpret_cast<GlobalV4f*>(orow + x * 4u));
+    }
+  }
+}
+
 template __global__ void k_gauss5_win_f32<2, true>(GaussArgs a);
 template __global__ void k_gauss5_win_f32<4, true>(GaussArgs a);
 template __global__ void k_gauss5_win_f32<2, false>(GaussArgs a);

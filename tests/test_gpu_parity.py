@@ -227,6 +227,50 @@ def test_gauss_sobel_full_width_four_rows_per_pixel(torch_gpu):
     _check_gauss(imgs[0], outs[0])
 
 
+# Widths that are multiples of 2048 take the Gaussian's row-band kernel:
+# blocks of 8 waves across 4 rows, halo columns passed between waves in LDS
+# and loaded only at a block's outer edges.  Heights ragged against the 4 rows;
+# 1, 2, 3 and 4 blocks per band.
+BAND_SHAPES = [(1, 2048), (3, 2048), (6, 4096), (37, 2048), (37, 4096), (9, 6144), (2, 8192)]
+
+
+@pytest.mark.parametrize("shape", BAND_SHAPES)
+def test_gauss_sobel_row_bands_per_pixel(torch_gpu, shape):
+    _say("gauss_sobel row bands", shape)
+    h, w = shape
+    imgs = [synth.normal_image(6, k, h, w) for k in range(2)]
+    outs, _ = _run_images("set", "gauss_sobel", imgs, np.float32, workers=2, slots=1)
+    for img, o in zip(imgs, outs):
+        _check_gauss(img, o)
+
+
+def test_gauss_row_band_impulses_at_wave_and_block_edges(torch_gpu):
+    """Impulses on the columns either side of every wave boundary (256k) and
+    block boundary (2048) of a 4096-wide image: each blur is exactly the
+    float32 product g_i*g_j in its 5x5 neighbourhood and exactly zero
+    elsewhere, so a halo pair taken from the wrong wave, block or row shows."""
+    _say("gauss row-band impulses")
+    h, w = 24, 4096
+    cols = [[255, 767, 1279, 2047, 2559, 3071, 3839], [256, 768, 1280, 2048, 2560, 3072, 3840]]
+    imgs = []
+    for cs in cols:
+        im = np.zeros((h, w), np.float32)
+        for k, c in enumerate(cs):
+            im[4 + 2 * (k % 3) + 4 * (k % 2), c] = 1.0
+        imgs.append(im)
+    outs, _ = _run_images("set", "gauss_sobel", imgs, np.float32, workers=1, slots=2)
+    g = oracle.gauss_taps().astype(np.float32)
+    b_off = _up64(128 + h * w)
+    for im, o in zip(imgs, outs):
+        blur = o[b_off:b_off + 4 * h * w].view(np.float32).reshape(h, w)
+        want = np.zeros((h, w), np.float32)
+        for y, x in zip(*np.nonzero(im)):
+            for i in range(5):
+                for j in range(5):
+                    want[y + i - 2, x + j - 2] = np.float32(g[i]) * np.float32(g[j])
+        assert np.array_equal(blur, want)
+
+
 # ------------------------------------------------------------------ vector jobs
 @pytest.fixture(scope="module")
 def vec_pools(torch_gpu):
