@@ -283,7 +283,10 @@ typedef struct set_config {
 typedef struct set_job_template {
     int32_t pipeline;            /* enum set_pipeline */
     uint32_t flags;              /* SET_TF_* */
-    uint32_t width, height;      /* image pipelines: image size (each >= 1) */
+    uint32_t width, height;      /* image and thermal-grid pipelines: size; 1 <= width <= 2^20,
+                                    1 <= height <= 2^19, width * height <= 2^28 (the height bound
+                                    keeps every launch grid within 65,536 blocks in its second
+                                    dimension); SET_EINVAL otherwise */
     uint64_t max_n;              /* vector / scan pipelines: largest n any job may use (>= 1) */
     float threshold;             /* Gaussian/Sobel mask threshold; 0 means 1.0 */
     uint32_t copy_mode;          /* enum set_copy_mode */

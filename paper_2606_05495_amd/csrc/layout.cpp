@@ -23,7 +23,12 @@ int pipeline_validate(const set_job_template& t, std::string* why) {
     case SET_PIPE_GAUSS_SOBEL_F32:
       if (t.width < 1 || t.height < 1) return bad("image templates need width >= 1 and height >= 1");
       if ((uint64_t)t.width * t.height > (1ull << 28)) return bad("image larger than 2^28 pixels");
-      if (t.width > (1u << 20) || t.height > (1u << 20)) return bad("image side larger than 2^20");
+      if (t.width > (1u << 20)) return bad("image width larger than 2^20");
+      // keeps every image grid within the launch limit of 65,536 blocks in
+      // its second dimension: 8 or more rows per block, except the
+      // Gaussian's 4-row bands, whose widths of 2048 or more leave at most
+      // 2^17 rows
+      if (t.height > (1u << 19)) return bad("image height larger than 2^19");
       break;
     case SET_PIPE_SAXPY_TANH_SUM_F32:
       if (t.max_n < 1 || t.max_n > (1ull << 32)) return bad("vector template needs 1 <= max_n <= 2^32");
@@ -36,7 +41,8 @@ int pipeline_validate(const set_job_template& t, std::string* why) {
     case SET_PIPE_HOTSPOT_F32:
       if (t.width < 1 || t.height < 1) return bad("thermal-grid templates need width >= 1 and height >= 1");
       if ((uint64_t)t.width * t.height > (1ull << 28)) return bad("grid larger than 2^28 cells");
-      if (t.width > (1u << 20) || t.height > (1u << 20)) return bad("grid side larger than 2^20");
+      if (t.width > (1u << 20)) return bad("grid width larger than 2^20");
+      if (t.height > (1u << 19)) return bad("grid height larger than 2^19");  // 8 rows per block, as above
       if (t.max_n < 1 || t.max_n > (uint64_t)kMaxHotspotSteps) return bad("thermal-grid template needs 1 <= max_n (steps) <= 32");
       break;
     case SET_PIPE_SCAN_LIB_I32_I64:

@@ -104,3 +104,30 @@ def test_noalloc_limits_refused_on_the_host():
                                            0) == A.SET_EINVAL
     assert lib.set_run_vector_jobs_noalloc(0, None, None, 16, 1 << 23, 4096, 16, 1, 16, None, 0) == A.SET_EINVAL
     assert lib.set_run_vector_jobs_noalloc(0, None, 16, 16, 1 << 23, 0, 16, 1, 16, None, 0) == A.SET_EINVAL
+
+
+def test_image_and_grid_size_limits():
+    """Widths up to 2^20, heights up to 2^19 (so that no launch grid passes
+    65,536 blocks in its second dimension) and at most 2^28 pixels, checked
+    on the host."""
+    cfg = A.set_config()
+    cfg.abi_version = A.SET_ABI_VERSION
+    cfg.num_workers, cfg.slots_per_worker = 1, 1
+
+    def fits(pipeline, w, h):
+        t = A.set_job_template()
+        t.pipeline = pipeline
+        t.width, t.height = w, h
+        if pipeline == A.SET_PIPE_HOTSPOT_F32:
+            t.max_n = 2
+        try:
+            A.set_template_footprint(cfg, t)
+            return True
+        except A.SetError as e:
+            assert e.code == A.SET_EINVAL
+            return False
+    for p in (A.SET_PIPE_GAUSS_SOBEL_F32, A.SET_PIPE_BOX_HIST_U8, A.SET_PIPE_HOTSPOT_F32):
+        assert fits(p, 4, 1 << 19) and fits(p, 1 << 20, 256) and fits(p, 512, 1 << 19)
+        assert not fits(p, 4, (1 << 19) + 1)
+        assert not fits(p, (1 << 20) + 1, 1)
+        assert not fits(p, 1024, 1 << 19)  # 2^29 pixels

@@ -791,18 +791,23 @@ def test_serve_alone_vs_mix(torch_gpu, vec_pools):
     ctx.close()
 
 
-def test_serve_alone_vs_mix_full_sizes(torch_gpu, vec_pools):
+@pytest.mark.parametrize("callback,inflight,dispatchers,vec_copy",
+                         [("event_poll", 0, 1, "kernels"), ("host_flag", 1, 4, "async_in")])
+def test_serve_alone_vs_mix_full_sizes(torch_gpu, vec_pools, callback, inflight, dispatchers, vec_copy):
     """The serving mix at its own image sizes (256^2, 512^2, 1024^2, 2048^2 beside vector jobs) under a
     device-memory budget that binds: at most a few 2048^2 slots fit at once, so later arrivals wait for
     memory, and admission must still never exceed the budget.  Each image request gives the same bits
-    alone as in the mix and matches the oracle; each vector request likewise."""
-    _say("serve alone vs mix, full sizes")
+    alone as in the mix and matches the oracle; each vector request likewise.  Second case: the serving
+    benchmark's settings (completion words, one job in flight per worker, 4 dispatcher threads, DMA
+    input copies for the vector batches' tables too)."""
+    _say("serve alone vs mix, full sizes", callback, inflight, dispatchers, vec_copy)
     x, y, xd, yd = vec_pools
     sides = synth.SERVE_SIDES
     budget = 96 << 20
-    ctx = Context(mode="set", workers=8, slots=4, mem_budget=budget, callback="event_poll")
+    ctx = Context(mode="set", workers=8, slots=4, mem_budget=budget, callback=callback, inflight=inflight,
+                  dispatchers=dispatchers)
     timg = {s: ctx.define("gauss_sobel", width=s, height=s, copy="async_in") for s in sides}
-    tvec = ctx.define("saxpy_batch", max_n=1 << 20, x_pool=xd, y_pool=yd, batch_max=64, tiles_max=4096, copy="kernels")
+    tvec = ctx.define("saxpy_batch", max_n=1 << 20, x_pool=xd, y_pool=yd, batch_max=64, tiles_max=4096, copy=vec_copy)
     fp = {s: A.set_template_footprint(ctx.cfg, ctx.templates[timg[s]])[0] for s in sides}
     assert 2 * fp[2048] < budget < 4 * fp[2048]
     P = 3
@@ -1267,6 +1272,23 @@ def test_hotspot_parity_large_grids(torch_gpu, shape):
         for (t0, p), o in zip(grids, outs):
             ref = oracle.hotspot(t0, p, steps)
             assert np.max(np.abs(o - ref)) <= oracle.hotspot_tolerance(ref, steps), (shape, steps)
+
+
+def test_tallest_image_and_grid(torch_gpu):
+    """The tallest templates allowed, 2^19 rows of 4 columns: the second
+    launch-grid dimension reaches 32,768 blocks for the image stages and
+    65,536, its limit, for the thermal step (8 rows per block).  Every pixel
+    of blur and mask, and every cell after 2 steps."""
+    h, w = 1 << 19, 4
+    _say("tallest image", h, w)
+    img = synth.normal_image(7, 0, h, w)
+    outs, _ = _run_images("set", "gauss_sobel", [img], np.float32, workers=1, slots=1)
+    _check_gauss(img, outs[0])
+    _say("tallest thermal grid", h, w)
+    grids = [synth.hotspot_input(7, 0, h, w)]
+    o = _run_hotspot("set", grids, 2, workers=1, slots=1)[0]
+    ref = oracle.hotspot(grids[0][0], grids[0][1], 2)
+    assert np.max(np.abs(o - ref)) <= oracle.hotspot_tolerance(ref, 2)
 
 
 @pytest.mark.parametrize("mode", ["sync", "graph", "batch", "queue", "set"])
