@@ -813,7 +813,8 @@ class HipBackend : public Backend {
             {(const void*)&k_sobel_thresh_win_f32<4, false>, (const void*)&k_sobel_thresh_win_f32<4, true>}};
         const void* gk = win ? gks[gr == 2 ? 0 : 1][full ? 1 : 0] : (const void*)&k_gauss5_f32;
         if (gauss_band_path(w))
-          stage((const void*)&k_gauss5_band_f32, to_dim3(gauss_grid(h, w)), &sl.gauss, (unsigned)kBandCols / 4);
+          stage(gauss_band_rows(h, w) == 8 ? (const void*)&k_gauss5_band_f32<8> : (const void*)&k_gauss5_band_f32<4>,
+                to_dim3(gauss_grid(h, w)), &sl.gauss, (unsigned)kBandCols / 4);
         else
           stage(gk, to_dim3(gauss_grid(h, w)), &sl.gauss);
         const void* sk = win ? sks[sr == 2 ? 0 : 1][full ? 1 : 0] : (const void*)&k_sobel_thresh_f32;

@@ -533,7 +533,12 @@ template void k_gauss5_win_f32<2, true>(GaussArgs);
 template void k_gauss5_win_f32<2, false>(GaussArgs);
 template void k_gauss5_win_f32<4, true>(GaussArgs);
 template void k_gauss5_win_f32<4, false>(GaussArgs);
-void k_gauss5_band_f32(GaussArgs a) { stamp(a.hdr, a.js); }
+template <int R>
+void k_gauss5_band_f32(GaussArgs a) {
+  stamp(a.hdr, a.js);
+}
+template void k_gauss5_band_f32<4>(GaussArgs);
+template void k_gauss5_band_f32<8>(GaussArgs);
 void k_sobel_thresh_f32(SobelArgs) {}
 template <int R, bool FULL>
 void k_sobel_thresh_win_f32(SobelArgs) {}
@@ -585,7 +590,8 @@ struct Register {
     register_kernel(&k_gauss5_win_f32<2, false>);
     register_kernel(&k_gauss5_win_f32<4, true>);
     register_kernel(&k_gauss5_win_f32<4, false>);
-    register_kernel(&k_gauss5_band_f32);
+    register_kernel(&k_gauss5_band_f32<4>);
+    register_kernel(&k_gauss5_band_f32<8>);
     register_kernel(&k_sobel_thresh_f32);
     register_kernel(&k_sobel_thresh_win_f32<2, true>);
     register_kernel(&k_sobel_thresh_win_f32<2, false>);

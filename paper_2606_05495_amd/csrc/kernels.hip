@@ -528,8 +528,8 @@ __global__ __launch_bounds__(kBlock) void k_gauss5_win_f32(GaussArgs a) {
   }
 }
 // Row bands, for widths that are a multiple of kBandCols: a block of
-// kBandCols / 256 waves lies side by side across kGaussBandRows whole rows,
-// each wave 256 columns as in the window kernel.  A wave's halo columns are
+// kBandCols / 256 waves lies side by side across R whole rows (8, or 4 above
+// 4096^2 pixels), each wave 256 columns as in the window kernel.  A wave's halo columns are
 // its neighbours' outermost columns, whose vertical-pass results the
 // neighbours already hold: each wave's lane 0 publishes its first two columns
 // and lane 63 its last two in LDS, and after one barrier lanes 0 and 63 read
@@ -537,14 +537,16 @@ __global__ __launch_bounds__(kBlock) void k_gauss5_win_f32(GaussArgs a) {
 // inside the image, load their two halo columns (the first wave on the left,
 // the last on the right); at the image border the clamped columns are the
 // border column itself, whose vertical result the border lane already holds.
-// Against the window kernel, which loads both halo pairs in every wave, a wave
-// issues R + 4 vector loads instead of 3 (R + 4) and skips two columns'
-// vertical passes; the barrier makes a wave wait for its block's slowest
-// load, which costs more than that saves on images of a million pixels or
-// fewer, where each SIMD holds one wave.  The arithmetic is the window
-// kernel's, operation for operation.
+// Against the window kernel at 4 rows, which loads both halo pairs in every
+// wave, a wave issues R + 4 vector loads instead of 3 (R + 4) and skips two
+// columns' vertical passes, and at 8 rows it re-reads 1.5x its rows from L2
+// instead of 2x; the barrier makes a wave wait for its block's slowest load,
+// which costs more than that saves on images of a million pixels or fewer,
+// where each SIMD holds one wave.  The arithmetic is the window kernel's,
+// operation for operation.
+template <int R>
 __global__ __launch_bounds__(kBandCols / 4) void k_gauss5_band_f32(GaussArgs a) {
-  constexpr int R = kGaussBandRows, nw = kBandCols / kWinCols;
+  constexpr int nw = kBandCols / kWinCols;
   unsigned bx, band;
   xcd_tile(bx, band);  // grid (column blocks, bands)
   if (bx == 0 && band == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
@@ -641,6 +643,8 @@ __global__ __launch_bounds__(kBandCols / 4) void k_gauss5_band_f32(GaussArgs a) 
   }
 }
 
+template __global__ void k_gauss5_band_f32<4>(GaussArgs a);
+template __global__ void k_gauss5_band_f32<8>(GaussArgs a);
 template __global__ void k_gauss5_win_f32<2, true>(GaussArgs a);
 template __global__ void k_gauss5_win_f32<4, true>(GaussArgs a);
 template __global__ void k_gauss5_win_f32<2, false>(GaussArgs a);

@@ -211,6 +211,7 @@ __global__ void k_hist256_final(HistFinalArgs a);
 __global__ void k_gauss5_f32(GaussArgs a);
 template <int R, bool FULL>
 __global__ void k_gauss5_win_f32(GaussArgs a);
+template <int R>
 __global__ void k_gauss5_band_f32(GaussArgs a);
 __global__ void k_sobel_thresh_f32(SobelArgs a);
 template <int R, bool FULL>

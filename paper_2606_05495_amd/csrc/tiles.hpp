@@ -61,14 +61,15 @@ inline unsigned hist_blocks(int64_t npix) {
 // widths that are multiples of kBandCols takes the row-band kernel instead.
 constexpr int kWinCols = 256;                 // columns per wave (and per block)
 // Gaussian row bands for widths that are a multiple of kBandCols: blocks of
-// 8 waves side by side (2048 columns) across kGaussBandRows rows.  Measured
-// on cold buffers against the window kernel: 7.9 against 8.6 us at 2048^2,
-// 28.6 against 29.1 us at 4096^2; at 1024^2 (blocks of 4 waves across the
-// width) the band kernel was the slower, 3.7 against 3.6 us, and 16-wave
-// blocks across 4096 columns took 31 us.
+// 8 waves side by side (2048 columns) across R rows, R = 8 up to 4096^2
+// pixels and 4 above.  Measured on cold buffers (window kernel / band R = 4 /
+// band R = 8): 8.6 / 8.1 / 7.2 us at 2048^2, 29.2 / 28.3 / 28.0 us at 4096^2,
+// 99.7 / 92.4 / 94.3 us at 8192^2.  At 1024^2 (blocks of 4 waves across the
+// width) a 4-row band was the slower, 3.7 against 3.6 us, and 16-wave blocks
+// across 4096 columns took 31 us.
 constexpr int kBandCols = 2048;
-constexpr int kGaussBandRows = 4;
 inline bool gauss_band_path(int w) { return w > 0 && (w % kBandCols) == 0; }
+inline int gauss_band_rows(int h, int w) { return (int64_t)h * w <= (int64_t)4096 * 4096 ? 8 : 4; }
 inline bool image_window_path(int w) { return w > 0 && (w % 4) == 0; }
 // Every tile of the window path full width: no lane lies past the right edge.
 inline bool window_full_width(int w) { return w > 0 && (w % kWinCols) == 0; }
@@ -79,8 +80,10 @@ inline Grid3 window_grid(int h, int w, int rows_per_wave) {
   return {(unsigned)((w + kWinCols - 1) / kWinCols), (unsigned)((h + rows - 1) / rows), 1u};
 }
 inline Grid3 gauss_grid(int h, int w) {
-  if (gauss_band_path(w))
-    return {(unsigned)(w / kBandCols), (unsigned)((h + kGaussBandRows - 1) / kGaussBandRows), 1u};
+  if (gauss_band_path(w)) {
+    const int r = gauss_band_rows(h, w);
+    return {(unsigned)(w / kBandCols), (unsigned)((h + r - 1) / r), 1u};
+  }
   if (image_window_path(w)) return window_grid(h, w, gauss_win_rows(h, w));
   return {(unsigned)((w + kGaussTW - 1) / kGaussTW), (unsigned)((h + kGaussTH - 1) / kGaussTH), 1u};
 }

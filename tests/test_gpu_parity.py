@@ -228,10 +228,11 @@ def test_gauss_sobel_full_width_four_rows_per_pixel(torch_gpu):
 
 
 # Widths that are multiples of 2048 take the Gaussian's row-band kernel:
-# blocks of 8 waves across 4 rows, halo columns passed between waves in LDS
-# and loaded only at a block's outer edges.  Heights ragged against the 4 rows;
-# 1, 2, 3 and 4 blocks per band.
-BAND_SHAPES = [(1, 2048), (3, 2048), (6, 4096), (37, 2048), (37, 4096), (9, 6144), (2, 8192)]
+# blocks of 8 waves across 8 rows (4 above 4096^2 pixels), halo columns
+# passed between waves in LDS and loaded only at a block's outer edges.
+# Heights ragged against the rows of a band; 1, 2, 3 and 4 blocks per band;
+# 4097x4096 takes the 4-row bands.
+BAND_SHAPES = [(1, 2048), (3, 2048), (6, 4096), (37, 2048), (37, 4096), (9, 6144), (2, 8192), (4097, 4096)]
 
 
 @pytest.mark.parametrize("shape", BAND_SHAPES)
