@@ -858,7 +858,12 @@ class HipBackend : public Backend {
           const float* src = (k == 0) ? (const float*)(b + L.in) : sl.hot[k - 1].tout;
           float* dst = (k == K - 1) ? (float*)(b + L.out + 64) : (float*)(b + ((k % 2 == 0) ? L.b1 : L.b2));
           sl.hot[k] = HotspotArgs{src, P, dst, h, w, k == 0 ? 1 : 0, sc.hdr, JobScalars{}};
-          stage(hk, to_dim3(hotspot_grid(h, w)), &sl.hot[k]);
+          const int hr = hotspot_band_rows(h, w);
+          if (hr)
+            stage(hr == 16 ? (const void*)&k_hotspot_band_f32<16> : (const void*)&k_hotspot_band_f32<8>,
+                  to_dim3(hotspot_grid(h, w)), &sl.hot[k], (unsigned)kBandCols / 4);
+          else
+            stage(hk, to_dim3(hotspot_grid(h, w)), &sl.hot[k]);
         }
         sl.je = JobEndArgs{sc};
         stage((const void*)&k_job_end, dim3(1), &sl.je);

@@ -517,6 +517,12 @@ void k_hotspot_win_f32(HotspotArgs a) {
 }
 template void k_hotspot_win_f32<true>(HotspotArgs);
 template void k_hotspot_win_f32<false>(HotspotArgs);
+template <int R>
+void k_hotspot_band_f32(HotspotArgs a) {
+  if (a.first) stamp(a.hdr, a.js);
+}
+template void k_hotspot_band_f32<8>(HotspotArgs);
+template void k_hotspot_band_f32<16>(HotspotArgs);
 void k_hotspot_f32(HotspotArgs a) {
   if (a.first) stamp(a.hdr, a.js);
 }
@@ -581,6 +587,8 @@ struct Register {
     register_kernel(&k_hotspot_win_f32<true>);
     register_kernel(&k_hotspot_win_f32<false>);
     register_kernel(&k_hotspot_f32);
+    register_kernel(&k_hotspot_band_f32<8>);
+    register_kernel(&k_hotspot_band_f32<16>);
     register_kernel(&k_box3_u8_u16);
     register_kernel(&k_div9_u16_u8);
     register_kernel(&k_hist256_u8);

@@ -793,6 +793,95 @@ __global__ __launch_bounds__(kBlock) void k_hotspot_win_f32(HotspotArgs a) {
   else
     rows(std::true_type{});
 }
+// Thermal step on row bands, for widths that are a multiple of kBandCols
+// and grids of 2^22 to 2^24 cells: 8 waves side by side across R rows (8 up
+// to 2^22 cells, 16 above), as the Gaussian's bands.  The halo is
+// one raw column each side: lane 0 publishes its first column, lane 63 its
+// last, for each of the R rows; after one barrier lanes 0 and 63 read the
+// neighbouring waves' columns.  A block's outer columns inside the grid are
+// loaded by its first and last wave; at the grid border the neighbour is the
+// cell itself.  The per-cell arithmetic is the window kernel's.
+template <int R>
+__global__ __launch_bounds__(kBandCols / 4) void k_hotspot_band_f32(HotspotArgs a) {
+  constexpr int nw = kBandCols / kWinCols;
+  unsigned bx, band;
+  xcd_tile(bx, band);  // grid (column blocks, bands)
+  if (a.first && bx == 0 && band == 0 && threadIdx.x == 0) write_slot_hdr(a.hdr, a.js);
+  __shared__ float lo[nw + 2][R], hi[nw + 2][R];
+  const int w = a.w, h = a.h, hm = h - 1;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int y0 = (int)band * R;
+  const unsigned xb = bx * (unsigned)kBandCols;
+  const unsigned x = xb + (unsigned)wave * kWinCols + 4u * (unsigned)lane;
+  const uint32_t pitch = (uint32_t)w * 4u;
+  const bool left_out = wave == 0 && bx > 0;
+  const bool right_out = wave == nw - 1 && bx + 1 < gridDim.x;
+  auto row_base = [&](const float* g, int r) {  // row y0 + r, clamped
+    uint64_t row = reinterpret_cast<uint64_t>(g) + (uint64_t)(uint32_t)clampi(y0 + r, 0, hm) * pitch;
+    asm("" : "+s"(row));
+    return row;
+  };
+  float e[R];
+  if (left_out || right_out) {
+    const unsigned hc = (left_out ? xb - 1u : xb + (unsigned)kBandCols) * 4u;
+#pragma unroll
+    for (int r = 0; r < R; ++r) e[r] = *reinterpret_cast<const GlobalF32*>(row_base(a.tin, r) + hc);
+  }
+  float4 v[R + 2], pv[R];
+#pragma unroll
+  for (int r = 0; r < R + 2; ++r) {
+    const v4f_t t = *reinterpret_cast<const GlobalV4f*>(row_base(a.tin, r - 1) + x * 4u);
+    v[r] = make_float4(t.x, t.y, t.z, t.w);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const v4f_t t = *reinterpret_cast<const GlobalV4f*>(row_base(a.p, r) + x * 4u);
+    pv[r] = make_float4(t.x, t.y, t.z, t.w);
+  }
+  if (left_out || right_out) {
+    float* dst = left_out ? &hi[0][0] : &lo[nw + 1][0];
+    if (lane == (left_out ? 0 : 63))
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r] = e[r];
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) lo[wave + 1][r] = v[r + 1].x;
+    if (wave == 0 && bx == 0)
+#pragma unroll
+      for (int r = 0; r < R; ++r) hi[0][r] = v[r + 1].x;
+  } else if (lane == 63) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) hi[wave + 1][r] = v[r + 1].w;
+    if (wave == nw - 1 && bx + 1 == gridDim.x)
+#pragma unroll
+      for (int r = 0; r < R; ++r) lo[nw + 1][r] = v[r + 1].w;
+  }
+  __syncthreads();
+  const float* halo = lane == 0 ? &hi[wave][0] : &lo[wave + 2][0];
+  float f[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) f[r] = halo[r];
+#pragma unroll
+  for (int r = 1; r <= R; ++r) {
+    const int y = y0 + r - 1;
+    const float c[6] = {from_left(v[r].w, f[r - 1]), v[r].x, v[r].y, v[r].z, v[r].w, from_right(v[r].x, f[r - 1])};
+    const float n4[4] = {v[r - 1].x, v[r - 1].y, v[r - 1].z, v[r - 1].w};
+    const float s4[4] = {v[r + 1].x, v[r + 1].y, v[r + 1].z, v[r + 1].w};
+    const float p4[4] = {pv[r - 1].x, pv[r - 1].y, pv[r - 1].z, pv[r - 1].w};
+    float o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = hotspot::step(c[j + 1], p4[j], n4[j], s4[j], c[j], c[j + 2]);
+    if (y < h) {
+      uint64_t orow = reinterpret_cast<uint64_t>(a.tout) + (uint64_t)(uint32_t)y * pitch;
+      asm("" : "+s"(orow));
+      __builtin_nontemporal_store(make_v4f(o[0], o[1], o[2], o[3]), reinterpret_cast<GlobalV4f*>(orow + x * 4u));
+    }
+  }
+}
+template __global__ void k_hotspot_band_f32<8>(HotspotArgs a);
+template __global__ void k_hotspot_band_f32<16>(HotspotArgs a);
 template __global__ void k_hotspot_win_f32<true>(HotspotArgs a);
 template __global__ void k_hotspot_win_f32<false>(HotspotArgs a);
 

@@ -202,6 +202,8 @@ struct HotspotArgs {
 };
 template <bool FULL>
 __global__ void k_hotspot_win_f32(HotspotArgs a);
+template <int R>
+__global__ void k_hotspot_band_f32(HotspotArgs a);
 __global__ void k_hotspot_f32(HotspotArgs a);
 
 __global__ void k_box3_u8_u16(BoxArgs a);

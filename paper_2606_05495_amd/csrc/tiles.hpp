@@ -100,7 +100,19 @@ inline uint64_t sobel_partials(int h, int w) {
 // Thermal-grid step: the register window (4 columns x kHotWinRows rows per
 // lane) for widths that are multiples of 4, one pixel per thread otherwise.
 constexpr int kHotWinRows = 2;
+// Row bands (the Gaussian's layout) for widths that are a multiple of
+// kBandCols and grids of 2^22 to 2^24 cells: 8 rows per band up to 2^22
+// cells, 16 above; 0 = not the band path.  Measured cold per step (window /
+// 8-row / 16-row band): 10.3 / 9.0 / 10.4 us at 2048^2, 10.3 / 9.4 us at
+// 4096x1024, 38.9 / 39.6 / 37.4 us at 4096^2; at 2048x1024 the 8-row band
+// was the slower (6.9 against 6.1 us).
+inline int hotspot_band_rows(int h, int w) {
+  const int64_t n = (int64_t)h * w;
+  if (w <= 0 || (w % kBandCols) != 0 || n < ((int64_t)1 << 22) || n > ((int64_t)1 << 24)) return 0;
+  return n <= ((int64_t)1 << 22) ? 8 : 16;
+}
 inline Grid3 hotspot_grid(int h, int w) {
+  if (const int r = hotspot_band_rows(h, w)) return {(unsigned)(w / kBandCols), (unsigned)((h + r - 1) / r), 1u};
   if (image_window_path(w)) return window_grid(h, w, kHotWinRows);
   const uint64_t n = (uint64_t)h * w;
   return {(unsigned)((n + kBlock - 1) / kBlock), 1u, 1u};

@@ -77,12 +77,12 @@ def _inputs(args, slots):
     elif args.pipeline == "hotspot":
         base = []
         for k in range(8):
-            t0, p = synth.hotspot_input(0, k, args.side, args.side)
+            t0, p = synth.hotspot_input(0, k, args.height or args.side, args.side)
             base.append(np.concatenate([t0.ravel(), p.ravel()]).view(np.uint8))
     elif args.pipeline == "box_hist":
-        base = [synth.box_image(0, k, args.side, args.side).ravel() for k in range(8)]
+        base = [synth.box_image(0, k, args.height or args.side, args.side).ravel() for k in range(8)]
     else:
-        base = [synth.normal_image(0, k, args.side, args.side).view(np.uint8).ravel() for k in range(8)]
+        base = [synth.normal_image(0, k, args.height or args.side, args.side).view(np.uint8).ravel() for k in range(8)]
     return [base[k % 8] for k in range(n)]
 
 
@@ -90,7 +90,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--pipeline", default="gauss_sobel", choices=["gauss_sobel", "box_hist", "scan", "hotspot"])
     ap.add_argument("--steps", type=int, default=4, help="hotspot: steps per job")
-    ap.add_argument("--side", type=int, default=1024)
+    ap.add_argument("--side", type=int, default=1024, help="image / grid width (and height, unless --height)")
+    ap.add_argument("--height", type=int, default=0, help="image / grid height (default: --side)")
     ap.add_argument("--n", type=int, default=1 << 21)
     ap.add_argument("--reps", type=int, default=100)
     ap.add_argument("--slots", type=int, default=0,
@@ -108,10 +109,10 @@ def main():
         if args.pipeline == "scan":
             return ctx.define("scan", max_n=args.n)
         if args.pipeline == "hotspot":
-            return ctx.define("hotspot", width=args.side, height=args.side, max_n=args.steps)
+            return ctx.define("hotspot", width=args.side, height=args.height or args.side, max_n=args.steps)
         if args.pipeline == "box_hist":
-            return ctx.define("box_hist", width=args.side, height=args.side)
-        return ctx.define("gauss_sobel", width=args.side, height=args.side)
+            return ctx.define("box_hist", width=args.side, height=args.height or args.side)
+        return ctx.define("gauss_sobel", width=args.side, height=args.height or args.side)
 
     slots = args.slots
     if slots <= 0:

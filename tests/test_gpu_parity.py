@@ -1275,6 +1275,23 @@ def test_hotspot_parity_large_grids(torch_gpu, shape):
             assert np.max(np.abs(o - ref)) <= oracle.hotspot_tolerance(ref, steps), (shape, steps)
 
 
+@pytest.mark.parametrize("shape", [(37, 2048), (9, 4096), (3, 6144), (130, 2048),
+                                   (2048, 2048), (1025, 4096), (683, 6144), (4097, 4096)])
+def test_hotspot_parity_wide_grids(torch_gpu, shape):
+    """Widths that are multiples of 2048, 1 and 3 steps.  Below 2^22 cells the
+    window kernel; from 2^22 to 2^24 cells the row bands, 8 rows (2048^2) or
+    16 (the others, ragged against the 16 rows, one to three 2048-column
+    blocks per band); 4097x4096, above 2^24, the window kernel again."""
+    _say("hotspot wide", shape)
+    h, w = shape
+    grids = [synth.hotspot_input(2, k, h, w) for k in range(2)]
+    for steps in (1, 3):
+        outs = _run_hotspot("set", grids, steps, workers=2, slots=2)
+        for (t0, p), o in zip(grids, outs):
+            ref = oracle.hotspot(t0, p, steps)
+            assert np.max(np.abs(o - ref)) <= oracle.hotspot_tolerance(ref, steps), (shape, steps)
+
+
 def test_tallest_image_and_grid(torch_gpu):
     """The tallest templates allowed, 2^19 rows of 4 columns: the second
     launch-grid dimension reaches 32,768 blocks for the image stages and
