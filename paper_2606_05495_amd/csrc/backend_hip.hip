@@ -589,9 +589,10 @@ class HipBackend : public Backend {
     HIPCK(hipEventCreate(&e0));
     HIPCK(hipEventCreate(&e1));
     // Untimed launches first, so the timed ones start behind a queue of work
-    // and the host's enqueue rate cannot pace them: the last slots before
-    // the rotation's first (or slot 0 64 times).
-    const size_t ahead = rotate ? std::min<size_t>(nslots, 64) : 64;
+    // and the host's enqueue rate cannot pace them (a queue of twice the
+    // timed launches covers a host that enqueues at up to a third of the
+    // kernel's rate): the last slots before the rotation's first, or slot 0.
+    const size_t ahead = std::min<size_t>(rotate ? nslots : SIZE_MAX, std::max<size_t>(64, 2 * (size_t)reps));
     for (size_t r = 0; r < ahead; ++r) HIPCK(once((int)(nslots - 1 - r % nslots)));
     HIPCK(hipEventRecord(e0, st));
     for (int r = 0; r < reps; ++r) HIPCK(once(r));

@@ -367,14 +367,15 @@ def pmc_values(dirpath: str, counter: str):
     return [(d, n, v) for d, (n, v) in sorted(acc.items())]
 
 
-def loop_average(values, name_part: str, skip: int):
-    """Mean counter value over the dispatches of the kernel whose name
-    contains name_part, after the first `skip` of them."""
-    v = [x for _, n, x in values if name_part in n][skip:]
+def loop_average(values, name_part: str, last: int):
+    """Mean counter value over the last `last` dispatches of the kernel whose
+    name contains name_part (a cold loop's timed launches, which come after
+    the batch's dispatches, the untimed passes and the loop's head start)."""
+    v = [x for _, n, x in values if name_part in n][-last:]
     return (sum(v) / len(v), len(v)) if v else (None, 0)
 
 
-def traffic_record(fetch_dir: str, write_dir: str, kernels: dict, skip: int, calib_bytes: int,
+def traffic_record(fetch_dir: str, write_dir: str, kernels: dict, last: int, calib_bytes: int,
                    calib_name: str = "copyBuffer") -> dict:
     """HBM bytes per launch of each kernel from FETCH_SIZE and WRITE_SIZE runs
     (KiB per dispatch), each scaled by the factor that makes the counter read
@@ -388,8 +389,8 @@ def traffic_record(fetch_dir: str, write_dir: str, kernels: dict, skip: int, cal
     ff, wf = calib_bytes / (fc[-1] * 1024.0), calib_bytes / (wc[-1] * 1024.0)
     out = {"fetch_factor": round(ff, 4), "write_factor": round(wf, 4), "unit": "bytes per launch", "kernels": {}}
     for label, part in kernels.items():
-        f, nf = loop_average(fv, part, skip)
-        w, nw = loop_average(wv, part, skip)
+        f, nf = loop_average(fv, part, last)
+        w, nw = loop_average(wv, part, last)
         if f is None or w is None:
             continue
         out["kernels"][label] = {"fetch": round(f * 1024 * ff), "write": round(w * 1024 * wf),
@@ -435,21 +436,23 @@ def summarize(dirpath: str, kernel: str = "", batch: int = 0, library_window: bo
 def traffic_file(out_path: str, runs: dict, calib_bytes: int = 64 << 20) -> dict:
     """Write the counter-traffic record the benchmark reads: runs maps a
     workload name to (fetch_dir, write_dir, probe_json) of a stage_probe
-    --cold-only pair of counter runs; the skip count (the batch's dispatches
-    and the cold loop's warm-up launches) comes from the probe's slot count."""
+    --cold-only pair of counter runs; the average covers the cold loop's timed
+    launches, the last `reps` dispatches of each kernel (reps from the probe's
+    record)."""
     import hashlib
     kernels_src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "kernels.hip")
     rec = {"kernels_sha256": hashlib.sha256(open(kernels_src, "rb").read()).hexdigest(), "unit": "bytes per launch",
            "method": "rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE (KiB per dispatch), each scaled by the "
                      "factor that makes the counter read 64 MiB for the run's last plain 64 MiB device copy "
-                     "(__amd_rocclr_copyBuffer); mean over the cold-loop dispatches of stage_probe --cold-only "
-                     "(after the batch's dispatches and the loop's warm-up launches)",
+                     "(__amd_rocclr_copyBuffer); mean over the timed cold-loop dispatches of stage_probe "
+                     "--cold-only (each kernel's last `reps` dispatches)",
            "workloads": {}}
     for name, (fdir, wdir, probe) in runs.items():
         line = [l for l in open(probe) if l.startswith("{")][-1]
-        slots = json.loads(line)["slots"]
+        probe_rec = json.loads(line)
+        slots = probe_rec["slots"]
         r = traffic_record(fdir, wdir, {"gauss5_f32": "k_gauss5", "sobel_thresh_f32": "k_sobel_thresh",
-                                        "sobel_final": "k_sobel_final"}, skip=slots + min(slots, 64),
+                                        "sobel_final": "k_sobel_final"}, last=int(probe_rec.get("reps", 100)),
                            calib_bytes=calib_bytes)
         r["slots"] = slots
         rec["workloads"][name] = r
