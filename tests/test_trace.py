@@ -175,3 +175,48 @@ def test_library_window_drops_setup_before_the_jobs(tmp_path):
     assert win["span"] == pytest.approx(40 / 1e3)
     assert win["gpu_idle_fraction"] == pytest.approx(1 - 28 / 40)
     assert win["h2d_copies"] == 1
+
+
+def _pmc_csv(path, counter, rows):
+    """A rocprofv3 --pmc counter file: rows of (dispatch id, kernel name, value);
+    a dispatch may appear in several rows (one per XCD), which are summed."""
+    import csv
+    path.mkdir(parents=True, exist_ok=True)
+    with open(path / "pmc_counter_collection.csv", "w", newline="") as fh:
+        wr = csv.writer(fh)
+        wr.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for d, name, v in rows:
+            wr.writerow([d, name, counter, v])
+
+
+def test_traffic_record_scales_by_the_calibration_copy_and_averages_the_timed_loop(tmp_path):
+    """Per-launch HBM bytes: counter KiB scaled so the last 64 MiB copy reads
+    64 MiB, averaged over each kernel's last `last` dispatches (a cold loop's
+    timed launches after the batch, the untimed pass and the head start).
+    Values chosen so any other window or factor gives a different answer."""
+    from paper_2606_05495_amd import trace
+    mib64 = 64 << 20
+    gauss = "void setrt::k_gauss5_win_f32<4, true>(setrt::GaussArgs)"
+    fetch, write = [], []
+    d = 0
+    for i in range(10):  # earlier dispatches (batch, untimed pass): different values
+        d += 1
+        fetch.append((d, gauss, 999.0))
+        write.append((d, gauss, 777.0))
+    for i in range(4):  # the timed loop: each dispatch reported by two XCD rows
+        d += 1
+        fetch += [(d, gauss, 1000.0 + i), (d, gauss, 1000.0 + i)]
+        write += [(d, gauss, 2048.0), (d, gauss, 2048.0)]
+    d += 1
+    fetch.append((d, "__amd_rocclr_copyBuffer", 32768.0))  # fetch counts half the copy's bytes
+    write.append((d, "__amd_rocclr_copyBuffer", 65536.0))
+    _pmc_csv(tmp_path / "f", "FETCH_SIZE", fetch)
+    _pmc_csv(tmp_path / "w", "WRITE_SIZE", write)
+    r = trace.traffic_record(str(tmp_path / "f"), str(tmp_path / "w"), {"gauss5_f32": "k_gauss5"}, last=4,
+                             calib_bytes=mib64)
+    assert r["fetch_factor"] == 2.0 and r["write_factor"] == 1.0
+    k = r["kernels"]["gauss5_f32"]
+    # fetch: mean of 2 x (1000..1003) KiB = 2003 KiB, times 2; write: 4096 KiB
+    assert k["fetch"] == round(2003.0 * 1024 * 2.0)
+    assert k["write"] == 4096 * 1024
+    assert k["dispatches"] == 4
