@@ -44,6 +44,19 @@ int main() {
   }
   for (unsigned long long n : {1ull, 2048ull, 2049ull, 1ull << 20, (1ull << 31) - 1, 1ull << 31})
     if (scan_tiles(n) < 1 || scan_tiles(n) > 2147483647u || vec_blocks(n) < 1) ++bad;
+  // the row-band choices the stage rooflines were measured for
+  struct Case { int h, w, gauss_rows, hot_rows; };
+  const Case cases[] = {{1024, 1024, 0, 0}, {2048, 2048, 8, 8}, {1024, 2048, 8, 0}, {1024, 4096, 8, 8},
+                        {4096, 4096, 8, 16}, {8192, 8192, 4, 0}, {2048, 2052, 0, 0}, {2048, 6144, 8, 16}};
+  for (const Case& c : cases) {
+    const int g = gauss_band_path(c.w) ? gauss_band_rows(c.h, c.w) : 0;
+    const int t = hotspot_band_rows(c.h, c.w);
+    if (g != c.gauss_rows || t != c.hot_rows) {
+      std::printf("band rows %dx%d: gauss %d (want %d), thermal %d (want %d)\n", c.h, c.w, g, c.gauss_rows, t,
+                  c.hot_rows);
+      ++bad;
+    }
+  }
   std::printf("shapes %lld bad %d\n", shapes, bad);
   return bad ? 1 : 0;
 }
@@ -51,6 +64,7 @@ int main() {
 
 
 def test_every_valid_template_grid_fits_the_launch_limits(tmp_path):
+    """Also pins which shapes take the row-band kernels, and with how many rows."""
     src = tmp_path / "grids.cpp"
     exe = tmp_path / "grids"
     src.write_text(PROGRAM)
